@@ -1,0 +1,233 @@
+"""Benchmark: Silhouette points/s on one MI355X.
+
+One step = the whole hot path (per-cluster statistics, table finalisation, fused MFMA
+GEMM+epilogue, reduction of S) over the resident synthetic workload, through the C ABI.
+
+Default workload: blobs-50m-d128-k1000 (N=50,000,000, D=128, K=1000 Gaussian blobs), squared
+Euclidean, X stored bf16, bf16 MFMA with fp32 accumulation.  The fp32 form (X stored fp32, fp32
+MFMA) is timed beside it on the same points; |dS| between the two and against the FP64 oracle on
+sampled points is reported.  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"bf16": 2.5e15, "fp32": 157.3e12, "hbm": 8.0e12}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="blobs-50m-d128-k1000")
+    ap.add_argument("--metric", default="sqeuclid", choices=["sqeuclid", "cosine"])
+    ap.add_argument("--form", default="bf16", choices=["bf16", "fp8", "f32"])
+    ap.add_argument("--products", type=int, default=3)
+    ap.add_argument("--fp32-steps", type=int, default=4)
+    ap.add_argument("--no-fp32", action="store_true", help="skip the fp32-form comparison")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle check on sampled points")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--cpu-sample", type=int, default=200_000)
+    ap.add_argument("--n", type=int, default=0, help="override N (testing only)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def timed_steps(fn, steps, warmup, torch):
+    """Run `warmup` untimed calls, then `steps` timed ones between synchronisations; returns
+    (ms per step, phase ms per step [4])."""
+    from paper_2303_14102_amd import _lib
+    lib = _lib.load()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    _lib.check(lib.silhouette_profile_begin(steps), "profile_begin")
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    ms = (ctypes.c_float * 4)()
+    n = ctypes.c_int32()
+    _lib.check(lib.silhouette_profile_end(ms, ctypes.byref(n)), "profile_end")
+    total = start.elapsed_time(stop)
+    return total / steps, [v / max(1, n.value) for v in ms], wall / steps
+
+
+def cpu_baseline(spec, X_host_codes, labels_host, metric, col_scale, n_sample):
+    import numpy as np
+    import oracle
+    n = min(n_sample, len(labels_host))
+    Xs = np.ascontiguousarray(X_host_codes[:n])
+    ls = np.ascontiguousarray(labels_host[:n])
+    t0 = time.perf_counter()
+    oracle.silhouette(Xs, ls, spec.k, metric, col_scale=col_scale)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {n} rows of {spec.name} ({X_host_codes.dtype} storage), whole FP64 "
+                      f"oracle (statistics pass + every point), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU form is a design note, not a measured path)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2303_14102_amd import binding as sil
+    from paper_2303_14102_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    spec = wl.WORKLOADS[args.workload]
+    if args.n:
+        spec = wl.scaled(spec, args.n)
+    log(f"generating {spec.name} N={spec.n} D={spec.d} K={spec.k}")
+    t0 = time.perf_counter()
+    blobs = wl.make_blobs(spec, dev)
+    X32, labels = blobs.X, blobs.labels
+    col_scale = None
+    if args.form == "bf16":
+        X = wl.to_bf16(X32)
+    elif args.form == "fp8":
+        X, col_scale = wl.to_fp8_e4m3(X32)
+    else:
+        X = X32
+    torch.cuda.synchronize()
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+
+    ws = sil.new_workspace(spec.n, spec.d, spec.k, args.metric, X.dtype, 0, dev)
+    s = torch.empty(spec.n, dtype=torch.float32, device=dev)
+    S = torch.empty((), dtype=torch.float64, device=dev)
+
+    from paper_2303_14102_amd import _lib
+    lib = _lib.load()
+    fn_c = lib.silhouette_sqeuclid if args.metric == "sqeuclid" else lib.silhouette_cosine
+    dcode = sil._dtype_code(X)
+    stream = sil._stream(dev)
+    cs_ptr = sil._ptr(col_scale)
+
+    def step():
+        rc = fn_c(sil._ptr(X), dcode, cs_ptr, sil._ptr(labels), spec.n, spec.d, spec.k, args.products, 0,
+                  sil._ptr(s), sil._ptr(S), sil._ptr(ws), ws.numel(), stream)
+        if rc:
+            raise _lib.SilhouetteError(rc, "step")
+
+    log(f"timing {args.form} form: warmup {args.warmup}, steps {args.steps}")
+    ms, phases, wall = timed_steps(step, args.steps, args.warmup, torch)
+    st = sil.status(ws)
+    _lib.check(st, "device status")
+    S_form = S.item()
+    log(f"{args.form}: {ms:.3f} ms/step (wall {wall:.3f}), phases {['%.3f' % p for p in phases]}, S={S_form:.10f}")
+
+    out = {
+        "metric": "Silhouette points/s at D=128,K=1000; bf16-MFMA vs fp32 form at |dS|<1e-4",
+        "value": spec.n / (ms * 1e-3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"bf16": "bf16", "fp8": "fp8e4m3", "f32": "f32"}[args.form],
+        "data": "synthetic",
+        "config": {"workload": spec.name, "n": spec.n, "d": spec.d, "k": spec.k,
+                   "metric": args.metric, "storage": args.form,
+                   "products": args.products if args.form != "f32" else None,
+                   "centred": args.metric == "sqeuclid"},
+        "phases_ms": {"stats": phases[0], "finalize": phases[1], "gemm_epilogue": phases[2],
+                      "reduce": phases[3]},
+        "S": S_form,
+    }
+
+    # roofline of the dominant kernel: the fused GEMM + epilogue
+    useful = 2.0 * spec.n * spec.d * spec.k
+    t_main = phases[2] * 1e-3
+    peak = PEAK["fp32"] if args.form == "f32" else PEAK["bf16"]
+    prods = 1 if args.form == "f32" else args.products
+    out["roofline"] = {"bound": "mfma", "achieved": useful / t_main / 1e12, "peak": peak / 1e12,
+                       "unit": "TFLOP/s", "frac": useful / t_main / peak, "traffic": None,
+                       "kernel": "k_main_bf16" if args.form != "f32" else "k_main_f32",
+                       "issued_frac": useful * prods / t_main / peak,
+                       "note": "achieved = 2*N*D*K useful flops / mean duration of the fused kernel; "
+                               "issued_frac counts every split product"}
+    stats_bytes = spec.n * spec.d * X.element_size() + 4 * spec.n
+    out["stats_pass"] = {"bound": "hbm", "algorithmic_bytes": stats_bytes,
+                         "achieved_GBps": stats_bytes / (phases[0] * 1e-3) / 1e9,
+                         "frac": stats_bytes / (phases[0] * 1e-3) / PEAK["hbm"]}
+
+    if not args.no_fp32 and args.form != "f32":
+        ws32 = sil.new_workspace(spec.n, spec.d, spec.k, args.metric, torch.float32, 0, dev)
+        S32 = torch.empty((), dtype=torch.float64, device=dev)
+
+        def step32():
+            rc = fn_c(sil._ptr(X32), 0, None, sil._ptr(labels), spec.n, spec.d, spec.k, 0, 0,
+                      None, sil._ptr(S32), sil._ptr(ws32), ws32.numel(), stream)
+            if rc:
+                raise _lib.SilhouetteError(rc, "step32")
+
+        log(f"timing fp32 form: {args.fp32_steps} steps")
+        ms32, ph32, _ = timed_steps(step32, args.fp32_steps, 1, torch)
+        _lib.check(sil.status(ws32), "device status fp32")
+        out["fp32_form"] = {"ms_per_step": ms32, "value": spec.n / (ms32 * 1e-3), "S": S32.item(),
+                            "gemm_epilogue_ms": ph32[2],
+                            "gemm_frac_of_fp32_peak": useful / (ph32[2] * 1e-3) / PEAK["fp32"]}
+        out["speedup_vs_fp32_form"] = ms32 / ms
+        out["dS_vs_fp32_form"] = abs(S_form - S32.item())
+        log(f"fp32 form: {ms32:.3f} ms/step, S={S32.item():.10f}")
+        del ws32
+
+    host_codes = None
+    if not args.no_check or not args.no_cpu:
+        host_codes = wl.host_codes(X)
+        labels_host = labels.cpu().numpy()
+        cs_host = None if col_scale is None else col_scale.cpu().numpy()
+
+    if not args.no_check:
+        import oracle
+        log("oracle check on sampled points (FP64 statistics over the full data)")
+        t0 = time.perf_counter()
+        stats = oracle.cluster_stats(host_codes, labels_host, spec.k, args.metric, col_scale=cs_host)
+        idx = np.random.default_rng(7).choice(spec.n, size=256, replace=False)
+        s_ref, a_ref, b_ref, _ = oracle.scores_at(host_codes, labels_host, spec.k, idx, stats,
+                                                  args.metric, col_scale=cs_host)
+        s_gpu = s.cpu().numpy()[idx].astype(np.float64)
+        s_all = s.cpu().numpy().astype(np.float64)
+        out["check"] = {"sampled_points": int(len(idx)),
+                        "max_abs_ds_sampled": float(np.abs(s_gpu - s_ref).max()),
+                        "S_vs_sum_of_s": abs(S_form - s_all.sum() / spec.n),
+                        "oracle_stats_s": time.perf_counter() - t0}
+        log(f"check: {out['check']}")
+
+    if not args.no_cpu:
+        log(f"cpu baseline: oracle on {args.cpu_sample} rows")
+        out["cpu_baseline"] = cpu_baseline(spec, host_codes, labels_host, args.metric, cs_host, args.cpu_sample)
+        log(f"cpu baseline: {out['cpu_baseline']}")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,142 @@
+/*
+ * silhouette.h — C ABI of the MI355X (gfx950) linear-complexity Silhouette library.
+ *
+ * Method: M. Gaido, "Distributed Silhouette Algorithm: Evaluating Clustering on Big Data"
+ * (arXiv 2303.14102).  For points X[N,D] with cluster labels, the Silhouette of point i is
+ * s_i = (b_i - a_i) / max(a_i, b_i) (Section II, Eq.1/Eq.2), where a_i is the mean distance to
+ * the other members of its own cluster and b_i the mean distance to the closest other cluster;
+ * the overall score is S = sum_i s_i / N.  The mean distance from a point to a whole cluster is
+ * obtained from per-cluster statistics in linear time: Eq.11 (squared Euclidean: N_k, Y_k,
+ * Psi_k) and Eq.18 (cosine: N_k, Omega_k).
+ *
+ * Conventions for every entry point
+ *  - Pointers named "device" are HIP device pointers; host pointers are marked "host".
+ *  - X is row-major [N, D] in the storage given by `dtype` (sil_dtype).  labels is int32 [N]
+ *    with values in [0, K) (0-based cluster ids; ids may be unused).
+ *  - s (optional, may be NULL) receives s_i as float32 [N]; S receives the mean as one float64.
+ *  - The caller owns every buffer, including the workspace `ws` (device, at least
+ *    silhouette_workspace_bytes(...) bytes, 256-byte aligned).  The library never allocates or
+ *    frees device memory.  Calls are asynchronous on `stream` (a hipStream_t, NULL = default
+ *    stream) and do not synchronise it.  Calls are re-entrant when they use distinct workspaces.
+ *  - Problems visible on the host (sizes, NULL pointers, dtype, workspace too small) return a
+ *    negative sil_status at once and launch nothing.  Problems in the data (a label outside
+ *    [0, K), a non-finite value, a zero row under the cosine distance, fewer than two non-empty
+ *    clusters) are found on the device: the call still returns SIL_OK, S becomes NaN, s becomes
+ *    NaN, and silhouette_status() reports the first such error.
+ *  - Readings of the paper: a point alone in its cluster has s_i = 0 and counts in N; s_i = 0
+ *    when max(a_i, b_i) = 0; a_i and b_i are clamped at 0; b_i ranges over non-empty clusters.
+ *  - Limits: 1 <= N <= 2^31 - 1, 1 <= D <= 256, 2 <= K <= 65536.
+ */
+#ifndef PAPER_2303_14102_AMD_SILHOUETTE_H
+#define PAPER_2303_14102_AMD_SILHOUETTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SIL_OK = 0,
+  SIL_E_ARG = -1,          /* size out of range or NULL pointer */
+  SIL_E_DTYPE = -2,        /* unknown storage type, or fp8 without col_scale */
+  SIL_E_LABEL = -3,        /* (device) a label outside [0, K) */
+  SIL_E_FEW_CLUSTERS = -4, /* (device) fewer than two non-empty clusters */
+  SIL_E_ZERO_NORM = -5,    /* (device) a zero row under the cosine distance */
+  SIL_E_NONFINITE = -6,    /* (device) NaN or infinity in X */
+  SIL_E_WORKSPACE = -7,    /* workspace NULL, misaligned or smaller than required */
+  SIL_E_HIP = -8           /* a HIP runtime call failed */
+} sil_status;
+
+/* Storage of X.  SIL_BF16: bfloat16 values.  SIL_FP8_E4M3: OCP e4m3fn codes, element (i,l)
+ * worth code * col_scale[l]. */
+typedef enum { SIL_F32 = 0, SIL_BF16 = 1, SIL_FP8_E4M3 = 2 } sil_dtype;
+
+typedef enum { SIL_SQEUCLID = 0, SIL_COSINE = 1 } sil_metric;
+
+/* Option bits for `flags`. */
+enum {
+  /* Squared Euclidean only: do not subtract the global mean before the cross term.  Centring is
+   * exact for this distance (it is translation invariant) and is on by default. */
+  SIL_FLAG_NO_CENTRE = 1 << 0,
+  /* Keep a_i, b_i and the neighbouring cluster id of every point in the workspace, as the
+   * backward entry points need them. */
+  SIL_FLAG_SAVE_FOR_GRAD = 1 << 1
+};
+
+/*
+ * Device workspace needed by the forward (and backward) calls for this problem shape.
+ * `products` as in silhouette_sqeuclid; metric a sil_metric.  Returns 0 for arguments outside
+ * the limits.
+ */
+size_t silhouette_workspace_bytes(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dtype,
+                                  int32_t flags);
+
+/*
+ * Silhouette with the squared Euclidean distance (Section III-A, Eq.4-11).
+ *   X          device, [N, D] row-major, storage `dtype`
+ *   col_scale  device, float32 [D]; required for SIL_FP8_E4M3, ignored otherwise
+ *   labels     device, int32 [N]
+ *   products   number of bf16 MFMA products for the point-to-cluster-mean cross term when X is
+ *              bf16 or fp8: 1 (hi x hi), 2 (adds x x mean_lo), 3 (adds x_lo x mean_hi); 0 picks
+ *              the default (3).  Ignored for SIL_F32, which uses fp32 MFMA.
+ *   flags      SIL_FLAG_* bits
+ *   s          device, float32 [N], or NULL
+ *   S          device, float64 [1]
+ *   ws         device workspace, ws_bytes >= silhouette_workspace_bytes(...)
+ *   stream     hipStream_t or NULL
+ * Returns a sil_status.
+ */
+int silhouette_sqeuclid(const void* X, int32_t dtype, const float* col_scale,
+                        const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t products,
+                        int32_t flags, float* s, double* S, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/*
+ * Silhouette with the cosine distance 1 - x.y/(||x|| ||y||) (Section III-B, Eq.12-18).
+ * Arguments as silhouette_sqeuclid; SIL_FLAG_NO_CENTRE is ignored (cosine is never centred).
+ */
+int silhouette_cosine(const void* X, int32_t dtype, const float* col_scale, const int32_t* labels,
+                      int64_t N, int32_t D, int32_t K, int32_t products, int32_t flags, float* s,
+                      double* S, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Only the per-cluster statistics pass (one pass over X; Eq.5, Eq.6, Eq.8 for the squared
+ * Euclidean distance, Eq.15-16 for cosine), copied out of the workspace:
+ *   count  device, int32 [K]        N_k
+ *   V      device, float64 [K, D]   Y_k (squared Euclidean) or Omega_k (cosine)
+ *   psi    device, float64 [K]      Psi_k (squared Euclidean; zeros for cosine)
+ * Any of count/V/psi may be NULL.  Same error behaviour as the forward calls.
+ */
+int silhouette_cluster_stats(const void* X, int32_t dtype, const float* col_scale,
+                             const int32_t* labels, int64_t N, int32_t D, int32_t K,
+                             int32_t metric, int32_t* count, double* V, double* psi, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/*
+ * Waits for `stream`, then returns the first device-detected error recorded in `ws` by the last
+ * call that used it (SIL_OK if none), or SIL_E_HIP if the wait failed.
+ */
+int silhouette_status(const void* ws, void* stream);
+
+/* Static English text for a sil_status value. */
+const char* silhouette_strerror(int status);
+
+/*
+ * Phase timing for benchmarks (not needed for results).  After silhouette_profile_begin(n), the
+ * next n forward calls (either metric) record HIP events on their own stream around their four
+ * phases: cluster statistics, table finalisation, fused GEMM+epilogue, reduction of S.
+ * silhouette_profile_end waits for the last recorded event, writes the summed milliseconds of
+ * each phase into ms_sum[4] (host) and the number of recorded calls into *ncalls (host), and
+ * stops recording.  Process-wide state: not for concurrent use from several host threads.
+ * Returns a sil_status (SIL_E_HIP if an event call failed, SIL_E_ARG for n outside 1..4096).
+ */
+int silhouette_profile_begin(int32_t max_calls);
+int silhouette_profile_end(float* ms_sum, int32_t* ncalls);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_2303_14102_AMD_SILHOUETTE_H */

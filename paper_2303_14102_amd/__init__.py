@@ -1,0 +1,7 @@
+"""MI355X (gfx950) linear-complexity Silhouette (arXiv 2303.14102): squared Euclidean and cosine.
+
+The computation lives in the HIP library libsilhouette.so behind the C ABI of
+include/silhouette.h; ``silhouette`` and ``cluster_stats`` are thin torch-facing bindings.
+"""
+
+from .binding import cluster_stats, silhouette, status, workspace_bytes  # noqa: F401

@@ -1,0 +1,108 @@
+"""Torch-facing wrappers of the C ABI (include/silhouette.h).
+
+torch supplies device memory and the current HIP stream; the library does all the work.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib as L
+
+METRIC = {"sqeuclid": L.SIL_SQEUCLID, "cosine": L.SIL_COSINE}
+
+
+def _dtype_code(X: torch.Tensor) -> int:
+    if X.dtype == torch.float32:
+        return L.SIL_F32
+    if X.dtype == torch.bfloat16:
+        return L.SIL_BF16
+    if X.dtype == torch.float8_e4m3fn:
+        return L.SIL_FP8_E4M3
+    raise TypeError(f"unsupported X dtype {X.dtype} (float32, bfloat16 or float8_e4m3fn)")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_inputs(X, labels, col_scale):
+    if X.device.type != "cuda" or labels.device != X.device:
+        raise ValueError("X and labels must be on the same GPU")
+    if X.dim() != 2 or not X.is_contiguous():
+        raise ValueError("X must be a contiguous [N, D] tensor")
+    if labels.dtype != torch.int32 or labels.shape != (X.shape[0],) or not labels.is_contiguous():
+        raise ValueError("labels must be a contiguous int32 [N] tensor")
+    if X.dtype == torch.float8_e4m3fn:
+        if col_scale is None or col_scale.dtype != torch.float32 or col_scale.shape != (X.shape[1],):
+            raise ValueError("fp8 X needs a float32 [D] col_scale on the same device")
+
+
+def workspace_bytes(N: int, D: int, K: int, metric: str = "sqeuclid", dtype=torch.float32,
+                    flags: int = 0) -> int:
+    code = {torch.float32: L.SIL_F32, torch.bfloat16: L.SIL_BF16,
+            torch.float8_e4m3fn: L.SIL_FP8_E4M3}[dtype]
+    n = L.load().silhouette_workspace_bytes(N, D, K, METRIC[metric], code, flags)
+    if n == 0:
+        raise ValueError(f"shape out of range: N={N} D={D} K={K}")
+    return n
+
+
+def new_workspace(N: int, D: int, K: int, metric: str, dtype, flags: int, device) -> torch.Tensor:
+    nbytes = workspace_bytes(N, D, K, metric, dtype, flags)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def silhouette(X: torch.Tensor, labels: torch.Tensor, K: int, metric: str = "sqeuclid", *,
+               products: int = 0, centre: bool = True, col_scale: Optional[torch.Tensor] = None,
+               want_s: bool = True, save_for_grad: bool = False,
+               workspace: Optional[torch.Tensor] = None, check_status: bool = False):
+    """Per-point s_i (float32 [N] or None) and the mean S (float64 0-d tensor on the device).
+
+    products: bf16/fp8 cross-term products (1, 2, 3; 0 = library default).  centre: subtract
+    the global mean first (squared Euclidean only).  workspace: a uint8 device tensor of at least
+    workspace_bytes(...) bytes, reused across calls; allocated here when None.
+    """
+    _check_inputs(X, labels, col_scale)
+    N, D = X.shape
+    flags = (0 if centre else L.SIL_FLAG_NO_CENTRE) | (L.SIL_FLAG_SAVE_FOR_GRAD if save_for_grad else 0)
+    if workspace is None:
+        workspace = new_workspace(N, D, K, metric, X.dtype, flags, X.device)
+    s = torch.empty(N, dtype=torch.float32, device=X.device) if want_s else None
+    S = torch.empty((), dtype=torch.float64, device=X.device)
+    fn = L.load().silhouette_sqeuclid if metric == "sqeuclid" else L.load().silhouette_cosine
+    rc = fn(_ptr(X), _dtype_code(X), _ptr(col_scale), _ptr(labels), N, D, int(K), int(products), flags,
+            _ptr(s), _ptr(S), _ptr(workspace), workspace.numel(), _stream(X.device))
+    L.check(rc, f"silhouette_{metric}")
+    if check_status:
+        L.check(status(workspace), f"silhouette_{metric} (device)")
+    return s, S
+
+
+def cluster_stats(X: torch.Tensor, labels: torch.Tensor, K: int, metric: str = "sqeuclid", *,
+                  col_scale: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None):
+    """(count int32 [K], V float64 [K, D], psi float64 [K]) from one pass over X."""
+    _check_inputs(X, labels, col_scale)
+    N, D = X.shape
+    if workspace is None:
+        workspace = new_workspace(N, D, K, metric, X.dtype, 0, X.device)
+    count = torch.empty(K, dtype=torch.int32, device=X.device)
+    V = torch.empty((K, D), dtype=torch.float64, device=X.device)
+    psi = torch.empty(K, dtype=torch.float64, device=X.device)
+    rc = L.load().silhouette_cluster_stats(_ptr(X), _dtype_code(X), _ptr(col_scale), _ptr(labels), N, D,
+                                           int(K), METRIC[metric], _ptr(count), _ptr(V), _ptr(psi),
+                                           _ptr(workspace), workspace.numel(), _stream(X.device))
+    L.check(rc, "silhouette_cluster_stats")
+    return count, V, psi
+
+
+def status(workspace: torch.Tensor) -> int:
+    """First device-detected error of the last call on this workspace (waits for the stream)."""
+    return L.load().silhouette_status(_ptr(workspace), _stream(workspace.device))

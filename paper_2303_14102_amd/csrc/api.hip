@@ -1,0 +1,260 @@
+// C ABI entry points: argument checks, workspace carving, the stream-ordered launch sequence.
+#include "sil_internal.h"
+
+namespace sil {
+
+static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+WsLayout make_layout(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dtype,
+                     int32_t flags) {
+  WsLayout L{};
+  L.N = N;
+  L.D = D;
+  L.DP = padded_depth(D);
+  L.K = K;
+  L.Kpad = static_cast<int32_t>(round_up(K, kColTile));
+  L.nseg = ceil_div(N, kSegLen);
+  L.nblocks = ceil_div(N, kMainWaves * 32);  // upper bound over all kernel families
+  L.dtype = dtype;
+  L.metric = metric;
+  L.flags = flags;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  // hdr .. segpart are zeroed together by the statistics pass: keep them first and contiguous
+  L.hdr = take(64 * 4);
+  L.count = take(static_cast<size_t>(K) * 4);
+  L.offset = take(static_cast<size_t>(K + 1) * 4);
+  L.cursor = take(static_cast<size_t>(K) * 4);
+  L.V = take(static_cast<size_t>(K) * D * 8);
+  L.psi = take(static_cast<size_t>(K) * 8);
+  L.segpart = take(static_cast<size_t>(L.nseg) * 2 * (D + 1) * 8);
+  L.perm = take(static_cast<size_t>(N) * 4);
+  L.gmean = take(static_cast<size_t>(L.DP) * 8);
+  L.mvec = take(static_cast<size_t>(L.DP) * 4);
+  const size_t bt_elem = dtype == SIL_F32 ? 4 : 2 * 2;  // fp32, or bf16 hi + lo
+  L.btab = take(static_cast<size_t>(L.Kpad) * L.DP * bt_elem);
+  L.cvec = take(static_cast<size_t>(L.Kpad) * 4);
+  L.atab = take(static_cast<size_t>(K) * L.DP * 4);
+  L.avec = take(static_cast<size_t>(K) * 4);
+  L.ascale = take(static_cast<size_t>(K) * 4);
+  L.bpart = take(static_cast<size_t>(L.nblocks) * 8);
+  const bool save = (flags & SIL_FLAG_SAVE_FOR_GRAD) != 0;
+  L.save_a = take(save ? static_cast<size_t>(N) * 4 : 0);
+  L.save_b = take(save ? static_cast<size_t>(N) * 4 : 0);
+  L.save_n = take(save ? static_cast<size_t>(N) * 4 : 0);
+  L.total = o;
+  return L;
+}
+
+WsPtrs carve(const WsLayout& L, void* ws) {
+  char* b = static_cast<char*>(ws);
+  WsPtrs w;
+  w.hdr = reinterpret_cast<int32_t*>(b + L.hdr);
+  w.count = reinterpret_cast<int32_t*>(b + L.count);
+  w.offset = reinterpret_cast<int32_t*>(b + L.offset);
+  w.cursor = reinterpret_cast<int32_t*>(b + L.cursor);
+  w.V = reinterpret_cast<double*>(b + L.V);
+  w.psi = reinterpret_cast<double*>(b + L.psi);
+  w.segpart = reinterpret_cast<double*>(b + L.segpart);
+  w.perm = reinterpret_cast<int32_t*>(b + L.perm);
+  w.gmean = reinterpret_cast<double*>(b + L.gmean);
+  w.mvec = reinterpret_cast<float*>(b + L.mvec);
+  w.btab = b + L.btab;
+  w.cvec = reinterpret_cast<float*>(b + L.cvec);
+  w.atab = reinterpret_cast<float*>(b + L.atab);
+  w.avec = reinterpret_cast<float*>(b + L.avec);
+  w.ascale = reinterpret_cast<float*>(b + L.ascale);
+  w.bpart = reinterpret_cast<double*>(b + L.bpart);
+  w.save_a = reinterpret_cast<float*>(b + L.save_a);
+  w.save_b = reinterpret_cast<float*>(b + L.save_b);
+  w.save_n = reinterpret_cast<int32_t*>(b + L.save_n);
+  return w;
+}
+
+static bool shape_ok(int64_t N, int32_t D, int32_t K) {
+  return N >= 1 && N <= INT32_MAX && D >= 1 && D <= kMaxD && K >= 2 && K <= kMaxK;
+}
+
+static int check_common(const void* X, int32_t dtype, const float* col_scale,
+                        const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t metric,
+                        const void* ws, size_t ws_bytes, int32_t flags, WsLayout* L) {
+  if (!shape_ok(N, D, K) || !X || !labels) return SIL_E_ARG;
+  if (metric != SIL_SQEUCLID && metric != SIL_COSINE) return SIL_E_ARG;
+  if (dtype != SIL_F32 && dtype != SIL_BF16 && dtype != SIL_FP8_E4M3) return SIL_E_DTYPE;
+  if (dtype == SIL_FP8_E4M3 && !col_scale) return SIL_E_DTYPE;
+  *L = make_layout(N, D, K, metric, dtype, flags);
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) || ws_bytes < L->total) return SIL_E_WORKSPACE;
+  return SIL_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// phase timing (benchmarks)
+
+struct Profile {
+  bool on = false;
+  int cap = 0, used = 0;
+  hipEvent_t* ev = nullptr;  // 5 events per call
+};
+static Profile g_prof;
+
+static void prof_record(int call, int point, hipStream_t st) {
+  if (g_prof.on && call >= 0) hipEventRecord(g_prof.ev[call * 5 + point], st);
+}
+
+static int forward(int32_t metric, const void* X, int32_t dtype, const float* col_scale,
+                   const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t products,
+                   int32_t flags, float* s, double* S, void* ws, size_t ws_bytes, void* stream) {
+  WsLayout L;
+  int rc = check_common(X, dtype, col_scale, labels, N, D, K, metric, ws, ws_bytes, flags, &L);
+  if (rc) return rc;
+  if (!S) return SIL_E_ARG;
+  if (products == 0) products = 3;
+  if (products < 1 || products > 3) return SIL_E_ARG;
+  const WsPtrs w = carve(L, ws);
+  if ((flags & SIL_FLAG_SAVE_FOR_GRAD) && dtype != SIL_F32) return SIL_E_DTYPE;
+  const int64_t nblocks = ceil_div(N, main_rows_per_block(dtype, L.DP, products));
+  Problem p{X, col_scale, labels, N, D, L.DP, K, L.Kpad, dtype, metric, products, flags, s, S,
+            nblocks};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int call = g_prof.on && g_prof.used < g_prof.cap ? g_prof.used++ : -1;
+  prof_record(call, 0, st);
+  if (launch_stats(p, L, w, st) != hipSuccess) return SIL_E_HIP;
+  prof_record(call, 1, st);
+  if (launch_finalize(p, L, w, st) != hipSuccess) return SIL_E_HIP;
+  prof_record(call, 2, st);
+  if (launch_main(p, L, w, st) != hipSuccess) return SIL_E_HIP;
+  prof_record(call, 3, st);
+  if (launch_reduce(p, L, w, st) != hipSuccess) return SIL_E_HIP;
+  prof_record(call, 4, st);
+  return SIL_OK;
+}
+
+// 16-byte-or-less device-to-device copies of the statistics (kernels, so that the call stays
+// capturable and never touches the host)
+__global__ void k_copy_stats(const int32_t* __restrict__ cnt_in, const double* __restrict__ V_in,
+                             const double* __restrict__ psi_in, int32_t K, int32_t D,
+                             int32_t* __restrict__ cnt, double* __restrict__ V,
+                             double* __restrict__ psi) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t KD = static_cast<int64_t>(K) * D;
+  if (V && i < KD) V[i] = V_in[i];
+  if (i < K) {
+    if (cnt) cnt[i] = cnt_in[i];
+    if (psi) psi[i] = psi_in[i];
+  }
+}
+
+hipError_t launch_copy_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, int32_t* count,
+                             double* V, double* psi, hipStream_t st) {
+  (void)L;
+  const int64_t n = static_cast<int64_t>(p.K) * p.D > p.K ? static_cast<int64_t>(p.K) * p.D : p.K;
+  k_copy_stats<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, st>>>(w.count, w.V, w.psi, p.K,
+                                                                        p.D, count, V, psi);
+  return hipGetLastError();
+}
+
+}  // namespace sil
+
+using namespace sil;
+
+extern "C" {
+
+size_t silhouette_workspace_bytes(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dtype,
+                                  int32_t flags) {
+  if (!shape_ok(N, D, K)) return 0;
+  return make_layout(N, D, K, metric, dtype, flags).total;
+}
+
+int silhouette_sqeuclid(const void* X, int32_t dtype, const float* col_scale,
+                        const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t products,
+                        int32_t flags, float* s, double* S, void* ws, size_t ws_bytes,
+                        void* stream) {
+  return forward(SIL_SQEUCLID, X, dtype, col_scale, labels, N, D, K, products, flags, s, S, ws,
+                 ws_bytes, stream);
+}
+
+int silhouette_cosine(const void* X, int32_t dtype, const float* col_scale, const int32_t* labels,
+                      int64_t N, int32_t D, int32_t K, int32_t products, int32_t flags, float* s,
+                      double* S, void* ws, size_t ws_bytes, void* stream) {
+  return forward(SIL_COSINE, X, dtype, col_scale, labels, N, D, K, products,
+                 flags & ~SIL_FLAG_NO_CENTRE, s, S, ws, ws_bytes, stream);
+}
+
+int silhouette_cluster_stats(const void* X, int32_t dtype, const float* col_scale,
+                             const int32_t* labels, int64_t N, int32_t D, int32_t K,
+                             int32_t metric, int32_t* count, double* V, double* psi, void* ws,
+                             size_t ws_bytes, void* stream) {
+  WsLayout L;
+  int rc = check_common(X, dtype, col_scale, labels, N, D, K, metric, ws, ws_bytes, 0, &L);
+  if (rc) return rc;
+  const WsPtrs w = carve(L, ws);
+  Problem p{X, col_scale, labels, N, D, L.DP, K, L.Kpad, dtype, metric, 3, 0, nullptr, nullptr, 0};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (launch_stats(p, L, w, st) != hipSuccess) return SIL_E_HIP;
+  if (launch_copy_stats(p, L, w, count, V, psi, st) != hipSuccess) return SIL_E_HIP;
+  return SIL_OK;
+}
+
+int silhouette_profile_begin(int32_t max_calls) {
+  if (max_calls < 1 || max_calls > 4096) return SIL_E_ARG;
+  if (g_prof.cap < max_calls) {
+    for (int i = 0; i < g_prof.cap * 5; ++i) hipEventDestroy(g_prof.ev[i]);
+    delete[] g_prof.ev;
+    g_prof.ev = new hipEvent_t[static_cast<size_t>(max_calls) * 5];
+    for (int i = 0; i < max_calls * 5; ++i)
+      if (hipEventCreate(&g_prof.ev[i]) != hipSuccess) {
+        g_prof.cap = i / 5;
+        return SIL_E_HIP;
+      }
+    g_prof.cap = max_calls;
+  }
+  g_prof.used = 0;
+  g_prof.on = true;
+  return SIL_OK;
+}
+
+int silhouette_profile_end(float* ms_sum, int32_t* ncalls) {
+  g_prof.on = false;
+  if (!ms_sum || !ncalls) return SIL_E_ARG;
+  for (int k = 0; k < 4; ++k) ms_sum[k] = 0.0f;
+  *ncalls = g_prof.used;
+  if (g_prof.used == 0) return SIL_OK;
+  if (hipEventSynchronize(g_prof.ev[g_prof.used * 5 - 1]) != hipSuccess) return SIL_E_HIP;
+  for (int c = 0; c < g_prof.used; ++c)
+    for (int k = 0; k < 4; ++k) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, g_prof.ev[c * 5 + k], g_prof.ev[c * 5 + k + 1]) != hipSuccess)
+        return SIL_E_HIP;
+      ms_sum[k] += ms;
+    }
+  return SIL_OK;
+}
+
+int silhouette_status(const void* ws, void* stream) {
+  if (!ws) return SIL_E_WORKSPACE;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return SIL_E_HIP;
+  int32_t v = 0;
+  if (hipMemcpy(&v, ws, sizeof v, hipMemcpyDeviceToHost) != hipSuccess) return SIL_E_HIP;
+  return v;
+}
+
+const char* silhouette_strerror(int status) {
+  switch (status) {
+    case SIL_OK: return "ok";
+    case SIL_E_ARG: return "argument out of range or NULL pointer";
+    case SIL_E_DTYPE: return "unsupported storage type (or fp8 without col_scale)";
+    case SIL_E_LABEL: return "a label lies outside [0, K)";
+    case SIL_E_FEW_CLUSTERS: return "fewer than two non-empty clusters";
+    case SIL_E_ZERO_NORM: return "a point has zero norm under the cosine distance";
+    case SIL_E_NONFINITE: return "X holds a NaN or an infinity";
+    case SIL_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case SIL_E_HIP: return "a HIP runtime call failed";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// Dispatch of the fused GEMM+epilogue kernel, and the fixed-order reduction of S (Section II:
+// S = sum_i s_i / N).
+#include "main_kernels.h"
+
+namespace sil {
+
+// S = sum of the workgroup sums / N in a fixed order; NaN when the workspace holds an error.
+__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ bpart, int64_t nb,
+                                                 int64_t N, const int32_t* __restrict__ hdr,
+                                                 double* __restrict__ S) {
+  __shared__ double sh[1024];
+  const int t = threadIdx.x;
+  double v = 0.0;
+  for (int64_t i = t; i < nb; i += 1024) v += bpart[i];
+  sh[t] = v;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  if (t == 0) *S = hdr[0] != 0 ? __builtin_nan("") : sh[0] / static_cast<double>(N);
+}
+
+__global__ void k_poison(const int32_t* __restrict__ hdr, float* __restrict__ s, int64_t N) {
+  if (hdr[0] == 0) return;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride)
+    s[i] = __builtin_nanf("");
+}
+
+int main_rows_per_block(int dtype, int DP, int products) {
+  if (dtype == SIL_F32) return kMainWaves * 32;
+  if (products < 1 || products > 3) products = 3;
+  return kMainWaves * 32 * bf16_nb(DP, products);
+}
+
+hipError_t launch_main(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
+  (void)L;
+  MainArgs m;
+  m.X = p.X;
+  m.col_scale = p.col_scale;
+  m.labels = p.labels;
+  m.N = p.N;
+  m.D = p.D;
+  m.K = p.K;
+  m.btab = w.btab;
+  m.cvec = w.cvec;
+  m.atab = w.atab;
+  m.avec = w.avec;
+  m.ascale = w.ascale;
+  m.mvec = w.mvec;
+  m.Kpad = p.Kpad;
+  m.ntiles = p.Kpad / kColTile;
+  m.s = p.s;
+  m.bpart = w.bpart;
+  m.save_a = w.save_a;
+  m.save_b = w.save_b;
+  m.save_n = w.save_n;
+  const unsigned grid = static_cast<unsigned>(p.nblocks);
+  if (p.dtype == SIL_F32)
+    launch_main_f32(m, p.DP, p.metric, (p.flags & SIL_FLAG_SAVE_FOR_GRAD) != 0, grid, st);
+  else if (p.dtype == SIL_BF16)
+    launch_main_bf16(m, p.DP, p.metric, p.products, grid, st);
+  else
+    launch_main_fp8(m, p.DP, p.metric, p.products, grid, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
+  (void)L;
+  k_reduce<<<1, 1024, 0, st>>>(w.bpart, p.nblocks, p.N, w.hdr, p.S);
+  if (p.s) k_poison<<<1024, 256, 0, st>>>(w.hdr, p.s, p.N);
+  return hipGetLastError();
+}
+
+}  // namespace sil

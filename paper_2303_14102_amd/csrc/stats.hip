@@ -1,0 +1,352 @@
+// Pass 1 of the method: per-cluster statistics in one pass over the points.
+//
+//   N_k                       cluster sizes
+//   Y_k   = sum_{j in k} x_j                  (Eq.8)       squared Euclidean
+//   Psi_k = sum_{j in k} ||x_j||^2            (Eq.5, Eq.6)
+//   Omega_k = sum_{j in k} x_j / ||x_j||      (Eq.15, Eq.16) cosine
+//
+// The paper accumulates Y and Psi together in one pass with per-worker partial sums that one
+// node then adds up (footnotes to Eq.6 and Eq.9).  On the GPU the "workers" are waves, and the
+// per-cluster sums are made contention-free by a counting sort of the row ids by label:
+//   k_hist      label histogram (LDS-privatised, validates labels)
+//   k_scan      exclusive prefix of N_k -> start of every cluster in sorted order
+//   k_scatter   row ids scattered to their cluster's range (LDS-reserved blocks)
+//   k_segreduce each wave owns kSegLen consecutive sorted positions and accumulates the rows it
+//               gathers in FP64 registers; a run of one cluster that lies wholly inside the
+//               segment is stored directly, a run cut by a segment border goes to one of two
+//               partial slots of the segment
+//   k_combine   adds the partial slots of clusters that span several segments, in segment order
+// No floating-point atomics are used, so the sums do not depend on the schedule except through
+// the order of rows within a cluster, which the scatter leaves unspecified.
+#include "sil_internal.h"
+
+namespace sil {
+
+// ------------------------------------------------------------------------------------------
+// element decoding (storage -> float)
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) {
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+
+// OCP FP8 E4M3 ("fn"): bias 7, no infinities, S.1111.111 is NaN, exponent 0 is subnormal.
+__device__ __forceinline__ float e4m3_to_f32(uint8_t q) {
+  const uint32_t sign = static_cast<uint32_t>(q & 0x80) << 24;
+  const uint32_t e = (q >> 3) & 15u;
+  const uint32_t m = q & 7u;
+  if (e == 15u && m == 7u) return __uint_as_float(0x7fc00000u);
+  if (e == 0u) {
+    const float v = static_cast<float>(m) * 0.001953125f;  // m/8 * 2^-6
+    return sign ? -v : v;
+  }
+  return __uint_as_float(sign | ((e + 120u) << 23) | (m << 20));
+}
+
+template <int DT>
+__device__ __forceinline__ float load_elem(const void* X, const float* col_scale, int64_t row,
+                                           int32_t D, int32_t col) {
+  const int64_t idx = row * static_cast<int64_t>(D) + col;
+  if constexpr (DT == SIL_F32) {
+    return static_cast<const float*>(X)[idx];
+  } else if constexpr (DT == SIL_BF16) {
+    return bf16_bits_to_f32(static_cast<const uint16_t*>(X)[idx]);
+  } else {
+    return e4m3_to_f32(static_cast<const uint8_t*>(X)[idx]) * col_scale[col];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+
+__global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n_words) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n_words;
+       i += stride)
+    p[i] = 0u;
+}
+
+// Label histogram; labels outside [0, K) are skipped and reported.
+__global__ __launch_bounds__(256) void k_hist(const int32_t* __restrict__ labels, int64_t N,
+                                              int32_t K, int32_t* __restrict__ count,
+                                              int32_t* __restrict__ hdr) {
+  extern __shared__ int32_t sh[];
+  const bool in_lds = K <= kLdsHistMaxK;
+  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kChunk;
+  const int64_t c1 = min(N, c0 + static_cast<int64_t>(kChunk));
+  if (in_lds) {
+    for (int k = threadIdx.x; k < K; k += blockDim.x) sh[k] = 0;
+    __syncthreads();
+  }
+  bool bad = false;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+    const int32_t k = labels[i];
+    if (k < 0 || k >= K) {
+      bad = true;
+      continue;
+    }
+    if (in_lds)
+      atomicAdd(&sh[k], 1);
+    else
+      atomicAdd(&count[k], 1);
+  }
+  if (bad) set_status(hdr, SIL_E_LABEL);
+  if (in_lds) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += blockDim.x)
+      if (sh[k]) atomicAdd(&count[k], sh[k]);
+  }
+}
+
+// Exclusive prefix of the cluster sizes, scatter cursors, number of valid points and of
+// non-empty clusters.  One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count, int32_t K,
+                                               int32_t* __restrict__ offset,
+                                               int32_t* __restrict__ cursor,
+                                               int32_t* __restrict__ hdr) {
+  __shared__ int32_t part[1024];
+  __shared__ int32_t nz[1024];
+  const int t = threadIdx.x;
+  const int per = static_cast<int>((K + 1023) / 1024);
+  const int k0 = min(K, t * per), k1 = min(K, k0 + per);
+  int32_t sum = 0, nonempty = 0;
+  for (int k = k0; k < k1; ++k) {
+    sum += count[k];
+    nonempty += count[k] > 0;
+  }
+  part[t] = sum;
+  nz[t] = nonempty;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the 1024 partial sums
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int32_t v = t >= d ? part[t - d] : 0;
+    const int32_t w = t >= d ? nz[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    nz[t] += w;
+    __syncthreads();
+  }
+  int32_t run = part[t] - sum;  // exclusive
+  for (int k = k0; k < k1; ++k) {
+    offset[k] = run;
+    cursor[k] = run;
+    run += count[k];
+  }
+  if (t == 1023) {
+    offset[K] = part[1023];
+    hdr[1] = part[1023];
+    hdr[2] = nz[1023];
+    if (nz[1023] < 2) set_status(hdr, SIL_E_FEW_CLUSTERS);
+  }
+}
+
+// Scatter row ids into their cluster's range of the sorted order.
+__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ labels, int64_t N,
+                                                 int32_t K, int32_t* __restrict__ cursor,
+                                                 int32_t* __restrict__ perm) {
+  extern __shared__ int32_t sh[];
+  const bool in_lds = K <= kLdsHistMaxK;
+  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kChunk;
+  const int64_t c1 = min(N, c0 + static_cast<int64_t>(kChunk));
+  if (in_lds) {
+    for (int k = threadIdx.x; k < K; k += blockDim.x) sh[k] = 0;
+    __syncthreads();
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+      const int32_t k = labels[i];
+      if (k >= 0 && k < K) atomicAdd(&sh[k], 1);
+    }
+    __syncthreads();
+    // reserve one block of positions per cluster present in this chunk
+    for (int k = threadIdx.x; k < K; k += blockDim.x)
+      if (sh[k]) sh[k] = atomicAdd(&cursor[k], sh[k]);
+    __syncthreads();
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+      const int32_t k = labels[i];
+      if (k >= 0 && k < K) perm[atomicAdd(&sh[k], 1)] = static_cast<int32_t>(i);
+    }
+  } else {
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+      const int32_t k = labels[i];
+      if (k >= 0 && k < K) perm[atomicAdd(&cursor[k], 1)] = static_cast<int32_t>(i);
+    }
+  }
+}
+
+// Cluster whose sorted range contains position q (0 <= q < offset[K]): the largest k with
+// offset[k] <= q, which skips empty clusters.
+__device__ __forceinline__ int32_t find_cluster(const int32_t* __restrict__ offset, int32_t K,
+                                                int64_t q) {
+  int32_t lo = 0, hi = K;  // offset[lo] <= q < offset[hi]
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (offset[mid] <= q)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ double shfl_xor_f64(double v, int m) {
+  return __shfl_xor(v, m, 64);
+}
+
+// One wave per segment of kSegLen sorted positions.  A group of G lanes handles one row at a
+// time (lane covers E consecutive columns), RPW = 64/G rows per step.
+template <int DT, int METRIC>
+__global__ __launch_bounds__(256) void k_segreduce(
+    const void* __restrict__ X, const float* __restrict__ col_scale,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ offset, int32_t K, int32_t D,
+    int G, int E, int64_t nseg, double* __restrict__ V, double* __restrict__ psi,
+    double* __restrict__ segpart, int32_t* __restrict__ hdr) {
+  const int lane = threadIdx.x & 63;
+  const int64_t seg = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (seg >= nseg) return;
+  const int64_t nvalid = hdr[1];
+  const int64_t p0 = seg * kSegLen;
+  const int64_t p1 = min(nvalid, p0 + static_cast<int64_t>(kSegLen));
+  if (p0 >= p1) return;
+  const int RPW = 64 / G;
+  const int g = lane / G, lig = lane % G;
+
+  int32_t kc = find_cluster(offset, K, p0);
+  int64_t rs = offset[kc], re = offset[kc + 1];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double accq = 0.0;
+  bool bad_value = false, zero_norm = false;
+
+  auto flush = [&]() {
+    for (int off = G; off < 64; off <<= 1)
+      for (int e = 0; e < 4; ++e) acc[e] += shfl_xor_f64(acc[e], off);
+    for (int off = 1; off < 64; off <<= 1) accq += shfl_xor_f64(accq, off);
+    double* dst;
+    double* dpsi;
+    if (rs >= p0 && re <= p1) {  // the whole cluster lies in this segment
+      dst = V + static_cast<int64_t>(kc) * D;
+      dpsi = psi + kc;
+    } else {
+      const int slot = rs <= p0 ? 0 : 1;  // run through p0 -> slot 0, run past p1 -> slot 1
+      dst = segpart + (seg * 2 + slot) * static_cast<int64_t>(D + 1);
+      dpsi = dst + D;
+    }
+    if (g == 0)
+      for (int e = 0; e < E; ++e) {
+        const int col = lig * E + e;
+        if (col < D) dst[col] = acc[e];
+      }
+    if (lane == 0) *dpsi = accq;
+    for (int e = 0; e < 4; ++e) acc[e] = 0.0;
+    accq = 0.0;
+  };
+
+  for (int64_t p = p0; p < p1; p += RPW) {
+    const int64_t pos = p + g;
+    const bool valid = pos < p1;
+    double x[4] = {0.0, 0.0, 0.0, 0.0};
+    double sq = 0.0;
+    if (valid) {
+      const int64_t row = perm[pos];
+      for (int e = 0; e < E; ++e) {
+        const int col = lig * E + e;
+        if (col < D) {
+          const float v = load_elem<DT>(X, col_scale, row, D, col);
+          bad_value |= !isfinite(v);
+          x[e] = static_cast<double>(v);
+          sq = fma(x[e], x[e], sq);
+        }
+      }
+    }
+    // row norm over the G lanes of the group
+    double rowsq = sq;
+    for (int off = 1; off < G; off <<= 1) rowsq += shfl_xor_f64(rowsq, off);
+    if constexpr (METRIC == SIL_COSINE) {
+      if (valid && rowsq == 0.0) zero_norm = true;
+      const double inv = 1.0 / sqrt(rowsq);
+      for (int e = 0; e < 4; ++e) x[e] *= inv;
+    }
+    bool done = !valid;
+    while (true) {
+      if (!done && pos < re) {
+        for (int e = 0; e < 4; ++e) acc[e] += x[e];
+        if constexpr (METRIC == SIL_SQEUCLID) accq += sq;
+        done = true;
+      }
+      if (__all(done)) break;
+      flush();
+      kc = find_cluster(offset, K, re);
+      rs = offset[kc];
+      re = offset[kc + 1];
+    }
+  }
+  flush();
+  if (bad_value) set_status(hdr, SIL_E_NONFINITE);
+  if (zero_norm) set_status(hdr, SIL_E_ZERO_NORM);
+}
+
+// Sums of clusters whose sorted range spans several segments.  One thread per (cluster,
+// column), column D being Psi.
+__global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ offset, int32_t K,
+                                                 int32_t D, const double* __restrict__ segpart,
+                                                 double* __restrict__ V,
+                                                 double* __restrict__ psi) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t W = D + 1;
+  if (t >= static_cast<int64_t>(K) * W) return;
+  const int32_t k = static_cast<int32_t>(t / W);
+  const int32_t col = static_cast<int32_t>(t % W);
+  const int64_t a = offset[k], b = offset[k + 1];
+  if (a == b) return;
+  const int64_t s0 = a / kSegLen, s1 = (b - 1) / kSegLen;
+  if (s0 == s1) return;
+  double sum = 0.0;
+  for (int64_t s = s0; s <= s1; ++s) {
+    const int slot = (s == s0 && a != s0 * kSegLen) ? 1 : 0;
+    sum += segpart[(s * 2 + slot) * W + col];
+  }
+  if (col < D)
+    V[static_cast<int64_t>(k) * D + col] = sum;
+  else
+    psi[k] = sum;
+}
+
+// ------------------------------------------------------------------------------------------
+
+static void lanes_per_row(int D, int* G, int* E) {
+  int g = 1;
+  while (g < D && g < 64) g <<= 1;
+  *G = g;
+  *E = static_cast<int>(ceil_div(D, g));
+}
+
+hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
+  // zero: header .. segpart are contiguous in the layout; zero [hdr, perm)
+  const int64_t words = static_cast<int64_t>((L.perm - L.hdr) / 4);
+  const int64_t zblocks = ceil_div(words, 256) < 2048 ? ceil_div(words, 256) : 2048;
+  k_fill_zero<<<static_cast<unsigned>(zblocks), 256, 0, st>>>(
+      reinterpret_cast<uint32_t*>(w.hdr), words);
+  const unsigned nchunk = static_cast<unsigned>(ceil_div(p.N, kChunk));
+  const size_t lds = p.K <= kLdsHistMaxK ? static_cast<size_t>(p.K) * 4 : 0;
+  k_hist<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.count, w.hdr);
+  k_scan<<<1, 1024, 0, st>>>(w.count, p.K, w.offset, w.cursor, w.hdr);
+  k_scatter<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.cursor, w.perm);
+  int G, E;
+  lanes_per_row(p.D, &G, &E);
+  const unsigned nblk = static_cast<unsigned>(ceil_div(L.nseg, 4));
+#define SIL_SEG(DT, MT)                                                                      \
+  k_segreduce<DT, MT><<<nblk, 256, 0, st>>>(p.X, p.col_scale, w.perm, w.offset, p.K, p.D, G, E, \
+                                            L.nseg, w.V, w.psi, w.segpart, w.hdr)
+  if (p.metric == SIL_SQEUCLID) {
+    if (p.dtype == SIL_F32) SIL_SEG(SIL_F32, SIL_SQEUCLID);
+    else if (p.dtype == SIL_BF16) SIL_SEG(SIL_BF16, SIL_SQEUCLID);
+    else SIL_SEG(SIL_FP8_E4M3, SIL_SQEUCLID);
+  } else {
+    if (p.dtype == SIL_F32) SIL_SEG(SIL_F32, SIL_COSINE);
+    else if (p.dtype == SIL_BF16) SIL_SEG(SIL_BF16, SIL_COSINE);
+    else SIL_SEG(SIL_FP8_E4M3, SIL_COSINE);
+  }
+#undef SIL_SEG
+  const int64_t nt = static_cast<int64_t>(p.K) * (p.D + 1);
+  k_combine<<<static_cast<unsigned>(ceil_div(nt, 256)), 256, 0, st>>>(w.offset, p.K, p.D,
+                                                                       w.segpart, w.V, w.psi);
+  return hipGetLastError();
+}
+
+}  // namespace sil

@@ -1,0 +1,82 @@
+"""The C-ABI library loads and exports every entry point include/silhouette.h declares, and the
+host-side argument checks behave as documented (no device work is launched here)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "silhouette.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(silhouette_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2303_14102_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libsilhouette.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("silhouette_sqeuclid", "silhouette_cosine", "silhouette_workspace_bytes",
+              "silhouette_cluster_stats", "silhouette_status", "silhouette_strerror"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2303_14102_amd import _lib
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"binding lacks {name}"
+
+
+def test_workspace_bytes_host_logic(lib):
+    from paper_2303_14102_amd import _lib
+    f = lib.silhouette_workspace_bytes
+    assert f(0, 8, 4, 0, 0, 0) == 0
+    assert f(10, 0, 4, 0, 0, 0) == 0
+    assert f(10, 257, 4, 0, 0, 0) == 0
+    assert f(10, 8, 1, 0, 0, 0) == 0
+    assert f(10, 8, 65537, 0, 0, 0) == 0
+    a = f(10_000, 8, 4, 0, _lib.SIL_F32, 0)
+    b = f(10_000, 8, 4, 0, _lib.SIL_F32, _lib.SIL_FLAG_SAVE_FOR_GRAD)
+    assert a > 0 and b >= a + 3 * 4 * 10_000
+    # grows linearly in N (the sorted row ids), with the table part independent of N
+    big = f(50_000_000, 128, 1000, 0, _lib.SIL_BF16, 0)
+    assert 50_000_000 * 4 < big < 50_000_000 * 4 + 64 * 2**20
+    assert f(2**31 - 1, 1, 2, 0, 0, 0) > 0
+    assert f(2**31, 1, 2, 0, 0, 0) == 0
+
+
+def test_host_argument_errors_launch_nothing(lib):
+    from paper_2303_14102_amd import _lib
+    fake = ctypes.c_void_p(0x1000)       # never dereferenced: every call below fails its checks first
+    ws = ctypes.c_void_p(0x100000)
+    for fn in (lib.silhouette_sqeuclid, lib.silhouette_cosine):
+        assert fn(None, 0, None, fake, 10, 4, 2, 0, 0, None, fake, ws, 1 << 30, None) == -1
+        assert fn(fake, 0, None, None, 10, 4, 2, 0, 0, None, fake, ws, 1 << 30, None) == -1
+        assert fn(fake, 0, None, fake, 0, 4, 2, 0, 0, None, fake, ws, 1 << 30, None) == -1
+        assert fn(fake, 0, None, fake, 10, 4, 1, 0, 0, None, fake, ws, 1 << 30, None) == -1
+        assert fn(fake, 7, None, fake, 10, 4, 2, 0, 0, None, fake, ws, 1 << 30, None) == -2
+        assert fn(fake, 2, None, fake, 10, 4, 2, 0, 0, None, fake, ws, 1 << 30, None) == -2  # fp8 w/o scale
+        assert fn(fake, 0, None, fake, 10, 4, 2, 0, 0, None, fake, ws, 16, None) == -7       # too small
+        assert fn(fake, 0, None, fake, 10, 4, 2, 0, 0, None, fake, ctypes.c_void_p(0x100010), 1 << 30, None) == -7
+        assert fn(fake, 0, None, fake, 10, 4, 2, 0, 0, None, fake, None, 1 << 30, None) == -7
+        assert fn(fake, 0, None, fake, 10, 4, 2, 4, 0, None, fake, ws, 1 << 30, None) == -1  # products
+        assert fn(fake, 0, None, fake, 10, 4, 2, 0, 0, None, None, ws, 1 << 30, None) == -1  # S NULL
+        # backward saves exist for fp32 storage only
+        assert fn(fake, 1, None, fake, 10, 4, 2, 0, _lib.SIL_FLAG_SAVE_FOR_GRAD, None, fake, ws, 1 << 30, None) == -2
+
+
+def test_strerror(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, 99):
+        assert isinstance(lib.silhouette_strerror(code), bytes)

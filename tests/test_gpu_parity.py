@@ -1,0 +1,248 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same seeded inputs.
+
+Tolerances:
+  - cluster sizes: exact;  Y / Omega / Psi: relative 1e-12 (FP64 sums in another order);
+  - S: |dS| <= 1e-6 for fp32 storage, <= 1e-4 for bf16 / fp8 storage (oracle on the dequantised
+    input);
+  - s_i: the error bound of the kernel's arithmetic, per point (``per_point_bound``).  With the
+    cross term x'.mu'_k carried to a relative accuracy eps (fp32 accumulation over D terms, or
+    the bf16 hi/lo split with 1, 2 or 3 products), |db_i| <= 2 eps ||x'_i|| max_k ||mu'_k|| plus
+    fp32 rounding of ||x'_i||^2 + c_k; a_i comes from the difference form in fp32; then
+    |ds_i| <= 2 (|da_i| + |db_i|) / max(a_i, b_i).
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2303_14102_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL_S_MEAN = {"f32": 1e-6, "bf16": 1e-4, "fp8": 1e-4}
+U32 = 2.0 ** -24
+
+
+def cross_term_eps(form, products, metric, centre, D):
+    """Relative accuracy of the computed cross term x'.mu'_k."""
+    acc = U32 * (D + 8)                      # fp32 accumulation (MFMA or the epilogue)
+    if form == "f32":
+        return acc
+    exact_x = metric == "sqeuclid" and not centre  # bf16/fp8 storage is exact in bf16 uncentred
+    mu_split = 2.0 ** -16                    # hi + lo carries ~16 bits of the mean
+    if products == 3:
+        return 2.0 ** -16 + acc
+    if products == 2:
+        return (mu_split if exact_x else 2.0 ** -8) + acc
+    return 2.0 ** -8 + (0.0 if exact_x else 2.0 ** -8) + acc
+
+
+def per_point_bound(form, products, metric, centre, Xh, labels, K, a, b):
+    """Per-point bound on |s_i(GPU) - s_i(oracle)| (module docstring)."""
+    X = np.asarray(Xh, np.float64)
+    D = X.shape[1]
+    cnt = np.bincount(labels, minlength=K).astype(np.float64)
+    ne = cnt > 0
+    sums = np.zeros((K, D))
+    np.add.at(sums, labels, X if metric == "sqeuclid" else X / np.linalg.norm(X, axis=1, keepdims=True))
+    mu = sums[ne] / cnt[ne, None]
+    if metric == "sqeuclid":
+        m = X.mean(0) if centre else np.zeros(D)
+        xp = X - m
+        mup = mu - m
+        sq = np.zeros(K)
+        np.add.at(sq, labels, (X * X).sum(1))
+        var = sq[ne] / cnt[ne] - (mu * mu).sum(1)
+        cmax = ((mup * mup).sum(1) + var).max()
+    else:
+        xp = X / np.linalg.norm(X, axis=1, keepdims=True)
+        mup = mu
+        cmax = 1.0
+    nx = np.linalg.norm(xp, axis=1)
+    eps = cross_term_eps(form, products, metric, centre, D)
+    db = 2 * eps * nx * np.linalg.norm(mup, axis=1).max() + 4 * U32 * (nx ** 2 + cmax)
+    da = 4 * U32 * (D + 8) * (a + np.abs(a))
+    return 2 * (da + db) / np.maximum(np.maximum(a, b), 1e-30) + 4 * U32
+
+
+def dequantised(codes, col_scale):
+    if codes.dtype == np.uint16:
+        return (codes.astype(np.uint32) << 16).view(np.float32)
+    if codes.dtype == np.uint8:
+        return torch.from_numpy(codes).view(torch.float8_e4m3fn).float().numpy() * col_scale
+    return codes
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_14102_amd import _lib
+    _lib.load()  # fails loudly when the library is missing
+    return torch.device("cuda:0")
+
+
+def storage(X32: torch.Tensor, form: str):
+    """(X on device in the given storage, col_scale or None, host codes for the oracle)."""
+    if form == "f32":
+        return X32, None, wl.host_codes(X32)
+    if form == "bf16":
+        q = wl.to_bf16(X32)
+        return q, None, wl.host_codes(q)
+    q, sc = wl.to_fp8_e4m3(X32)
+    return q, sc, wl.host_codes(q)
+
+
+def run_case(dev, X32, labels, K, metric, form, products=0, centre=True):
+    from paper_2303_14102_amd import binding as sil
+    Xd, sc, codes = storage(X32.to(dev), form)
+    lab = labels.to(dev)
+    print(f"[case] N={X32.shape[0]} D={X32.shape[1]} K={K} metric={metric} form={form} "
+          f"products={products} centre={centre}", flush=True)
+    s, S = sil.silhouette(Xd, lab, K, metric, products=products, centre=centre, col_scale=sc,
+                          check_status=True)
+    torch.cuda.synchronize()
+    cs = None if sc is None else sc.cpu().numpy()
+    lab_h = labels.cpu().numpy()
+    s_ref, S_ref, a, b, _ = oracle.silhouette(codes, lab_h, K, metric, col_scale=cs, details=True)
+    bound = per_point_bound(form, products, metric, centre, dequantised(codes, cs), lab_h, K, a, b)
+    s = s.cpu().numpy().astype(np.float64)
+    worst = np.abs(s - s_ref) / bound
+    print(f"  S={S.item():.10f} ref={S_ref:.10f} |dS|={abs(S.item() - S_ref):.2e} "
+          f"max|ds|={np.abs(s - s_ref).max():.2e} max(|ds|/bound)={worst.max():.3f}", flush=True)
+    assert np.all(np.abs(s - s_ref) <= bound), f"point {int(worst.argmax())} exceeds its bound"
+    # S is the mean of s_i: the reduced forms (1 or 2 products on a split point) are held to the
+    # mean of their per-point bounds, the full forms to the stated targets
+    tol_S = TOL_S_MEAN[form] if products in (0, 3) else max(TOL_S_MEAN[form], bound.mean())
+    assert abs(S.item() - S_ref) <= tol_S
+    return s, S.item(), s_ref, S_ref
+
+
+# ---------------------------------------------------------------------------------------------
+# cluster statistics
+
+
+@pytest.mark.parametrize("metric", ["sqeuclid", "cosine"])
+@pytest.mark.parametrize("form", ["f32", "bf16", "fp8"])
+def test_stats_parity(dev, metric, form):
+    from paper_2303_14102_amd import binding as sil
+    b = wl.make_small(20_011, 40, 70, seed=3, singletons=2)  # ragged everywhere, 5 segments
+    Xd, sc, codes = storage(b.X.to(dev), form)
+    print(f"[stats] metric={metric} form={form}", flush=True)
+    count, V, psi = sil.cluster_stats(Xd, b.labels.to(dev), 73, metric, col_scale=sc)
+    c_ref, V_ref, p_ref = oracle.cluster_stats(codes, b.labels.numpy(), 73, metric,
+                                               col_scale=None if sc is None else sc.cpu().numpy())
+    assert np.array_equal(count.cpu().numpy(), c_ref)
+    scale = np.abs(V_ref).max()
+    np.testing.assert_allclose(V.cpu().numpy(), V_ref, rtol=1e-12, atol=1e-12 * scale)
+    np.testing.assert_allclose(psi.cpu().numpy(), p_ref, rtol=1e-12, atol=0)
+
+
+def test_stats_large_clusters_span_segments(dev):
+    # a few clusters of ~1e5 points: every cluster crosses many segment borders
+    from paper_2303_14102_amd import binding as sil
+    b = wl.make_small(300_000, 24, 3, seed=8)
+    count, V, psi = sil.cluster_stats(b.X.to(dev), b.labels.to(dev), 3)
+    c_ref, V_ref, p_ref = oracle.cluster_stats(b.X.numpy(), b.labels.numpy(), 3)
+    assert np.array_equal(count.cpu().numpy(), c_ref)
+    np.testing.assert_allclose(V.cpu().numpy(), V_ref, rtol=1e-11, atol=1e-9)
+    np.testing.assert_allclose(psi.cpu().numpy(), p_ref, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------------------------
+# the whole forward
+
+
+@pytest.mark.parametrize("metric", ["sqeuclid", "cosine"])
+def test_small_workload_fp32(dev, metric):
+    b = wl.make_blobs(wl.WORKLOADS["blobs-10k-d8-k4"])
+    s, S, s_ref, S_ref = run_case(dev, b.X, b.labels, 4, metric, "f32")
+    assert abs(S - S_ref) <= TOL_S_MEAN["f32"]
+
+
+CASES = [
+    # (N, D, K, singletons, seed): several tiles of 32 clusters, ragged N / D / K, empty ids
+    (5_037, 40, 70, 2, 11),
+    (3_001, 128, 100, 1, 12),
+    (2_000, 256, 40, 0, 13),
+    (4_099, 16, 33, 1, 14),
+    (1_500, 3, 5, 1, 15),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"N{c[0]}-D{c[1]}-K{c[2]}")
+@pytest.mark.parametrize("metric", ["sqeuclid", "cosine"])
+@pytest.mark.parametrize("form,products", [("f32", 0), ("bf16", 3), ("bf16", 2), ("bf16", 1),
+                                           ("fp8", 3)])
+def test_forward_parity(dev, case, metric, form, products):
+    N, D, K, single, seed = case
+    b = wl.make_small(N, D, K, seed=seed, singletons=single, sigma=1.5)
+    Kt = K + 2  # two unused ids
+    s, S, s_ref, S_ref = run_case(dev, b.X, b.labels, Kt, metric, form, products)
+    # singletons score exactly 0
+    sizes = np.bincount(b.labels.numpy(), minlength=Kt)
+    assert np.all(s[sizes[b.labels.numpy()] == 1] == 0.0)
+
+
+def test_uncentred_and_offset_data(dev):
+    # far from the origin, centring keeps the bf16 cross term accurate; fp32 too
+    b = wl.make_small(4_000, 32, 20, seed=21)
+    X = b.X + 1000.0
+    for form, products in (("f32", 0), ("bf16", 3)):
+        s, S, s_ref, S_ref = run_case(dev, X, b.labels, 20, "sqeuclid", form, products, centre=True)
+        assert abs(S - S_ref) <= TOL_S_MEAN[form]
+    s, S, s_ref, S_ref = run_case(dev, b.X, b.labels, 20, "sqeuclid", "f32", 0, centre=False)
+    assert abs(S - S_ref) <= TOL_S_MEAN["f32"]
+
+
+def test_two_points(dev):
+    # smallest input: two singletons -> s = 0, S = 0
+    X = torch.tensor([[0.0, 1.0], [2.0, 3.0]])
+    lab = torch.tensor([0, 1], dtype=torch.int32)
+    s, S, s_ref, S_ref = run_case(dev, X, lab, 2, "sqeuclid", "f32")
+    assert S == 0.0 and np.all(s == 0)
+
+
+def test_hand_example_on_gpu(dev):
+    X = torch.tensor([[0.0], [1.0], [4.0], [6.0]])
+    lab = torch.tensor([0, 0, 1, 1], dtype=torch.int32)
+    s, S, _, _ = run_case(dev, X, lab, 2, "sqeuclid", "f32")
+    want = np.array([25 / 26, 16 / 17, 17 / 25, 53 / 61])
+    np.testing.assert_allclose(s, want, atol=1e-6)
+    assert abs(S - want.mean()) < 1e-6
+
+
+# ---------------------------------------------------------------------------------------------
+# device-detected errors
+
+
+def test_device_errors(dev):
+    from paper_2303_14102_amd import _lib
+    from paper_2303_14102_amd import binding as sil
+    X = torch.randn(1000, 8, device=dev)
+    lab = torch.randint(0, 4, (1000,), dtype=torch.int32, device=dev)
+    ws = sil.new_workspace(1000, 8, 4, "sqeuclid", torch.float32, 0, dev)
+    bad = lab.clone()
+    bad[17] = 4
+    s, S = sil.silhouette(X, bad, 4, workspace=ws)
+    assert sil.status(ws) == -3 and math.isnan(S.item()) and torch.isnan(s).all()
+    Xn = X.clone()
+    Xn[5, 3] = float("nan")
+    s, S = sil.silhouette(Xn, lab, 4, workspace=ws)
+    assert sil.status(ws) == -6 and math.isnan(S.item())
+    one = torch.zeros_like(lab)
+    s, S = sil.silhouette(X, one, 4, workspace=ws)
+    assert sil.status(ws) == -4 and math.isnan(S.item())
+    Xz = X.clone()
+    Xz[9] = 0
+    wsc = sil.new_workspace(1000, 8, 4, "cosine", torch.float32, 0, dev)
+    s, S = sil.silhouette(Xz, lab, 4, "cosine", workspace=wsc)
+    assert sil.status(wsc) == -5 and math.isnan(S.item())
+    # the same workspace recovers on a good call
+    s, S = sil.silhouette(X, lab, 4, workspace=ws)
+    assert sil.status(ws) == 0 and not math.isnan(S.item())
+    with pytest.raises((ValueError, _lib.SilhouetteError)):
+        sil.silhouette(X, lab, 1)
