@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-sample", type=int, default=200_000)
     ap.add_argument("--n", type=int, default=0, help="override N (testing only)")
+    ap.add_argument("--k", type=int, default=0, help="override K (testing only)")
     return ap.parse_args()
 
 
@@ -102,6 +103,9 @@ def main():
     spec = wl.WORKLOADS[args.workload]
     if args.n:
         spec = wl.scaled(spec, args.n)
+    if args.k:
+        import dataclasses
+        spec = dataclasses.replace(spec, k=args.k, name=f"{spec.name}@k{args.k}")
     log(f"generating {spec.name} N={spec.n} D={spec.d} K={spec.k}")
     t0 = time.perf_counter()
     blobs = wl.make_blobs(spec, dev)

@@ -10,7 +10,7 @@ WsLayout make_layout(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dt
   WsLayout L{};
   L.N = N;
   L.D = D;
-  L.DP = padded_depth(D);
+  L.DPX = gemm_depth(D, dtype);
   L.K = K;
   L.Kpad = static_cast<int32_t>(round_up(K, kColTile));
   L.nseg = ceil_div(N, kSegLen);
@@ -33,15 +33,16 @@ WsLayout make_layout(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dt
   L.psi = take(static_cast<size_t>(K) * 8);
   L.segpart = take(static_cast<size_t>(L.nseg) * 2 * (D + 1) * 8);
   L.perm = take(static_cast<size_t>(N) * 4);
-  L.gmean = take(static_cast<size_t>(L.DP) * 8);
-  L.mvec = take(static_cast<size_t>(L.DP) * 4);
+  L.lsorted = take(static_cast<size_t>(N) * 4);
+  L.gmean = take(static_cast<size_t>(L.DPX) * 8);
+  L.mvec = take(static_cast<size_t>(L.DPX) * 4);
   const size_t bt_elem = dtype == SIL_F32 ? 4 : 2 * 2;  // fp32, or bf16 hi + lo
-  L.btab = take(static_cast<size_t>(L.Kpad) * L.DP * bt_elem);
-  L.cvec = take(static_cast<size_t>(L.Kpad) * 4);
-  L.atab = take(static_cast<size_t>(K) * L.DP * 4);
+  L.btab = take(static_cast<size_t>(L.Kpad) * table_stride(L.DPX, dtype) * bt_elem);
+  L.atab = take(static_cast<size_t>(K) * L.DPX * 4);
   L.avec = take(static_cast<size_t>(K) * 4);
   L.ascale = take(static_cast<size_t>(K) * 4);
   L.bpart = take(static_cast<size_t>(L.nblocks) * 8);
+  L.bpart2 = take(1024 * 8);
   const bool save = (flags & SIL_FLAG_SAVE_FOR_GRAD) != 0;
   L.save_a = take(save ? static_cast<size_t>(N) * 4 : 0);
   L.save_b = take(save ? static_cast<size_t>(N) * 4 : 0);
@@ -61,14 +62,15 @@ WsPtrs carve(const WsLayout& L, void* ws) {
   w.psi = reinterpret_cast<double*>(b + L.psi);
   w.segpart = reinterpret_cast<double*>(b + L.segpart);
   w.perm = reinterpret_cast<int32_t*>(b + L.perm);
+  w.lsorted = reinterpret_cast<int32_t*>(b + L.lsorted);
   w.gmean = reinterpret_cast<double*>(b + L.gmean);
   w.mvec = reinterpret_cast<float*>(b + L.mvec);
   w.btab = b + L.btab;
-  w.cvec = reinterpret_cast<float*>(b + L.cvec);
   w.atab = reinterpret_cast<float*>(b + L.atab);
   w.avec = reinterpret_cast<float*>(b + L.avec);
   w.ascale = reinterpret_cast<float*>(b + L.ascale);
   w.bpart = reinterpret_cast<double*>(b + L.bpart);
+  w.bpart2 = reinterpret_cast<double*>(b + L.bpart2);
   w.save_a = reinterpret_cast<float*>(b + L.save_a);
   w.save_b = reinterpret_cast<float*>(b + L.save_b);
   w.save_n = reinterpret_cast<int32_t*>(b + L.save_n);
@@ -116,8 +118,8 @@ static int forward(int32_t metric, const void* X, int32_t dtype, const float* co
   if (products < 1 || products > 3) return SIL_E_ARG;
   const WsPtrs w = carve(L, ws);
   if ((flags & SIL_FLAG_SAVE_FOR_GRAD) && dtype != SIL_F32) return SIL_E_DTYPE;
-  const int64_t nblocks = ceil_div(N, main_rows_per_block(dtype, L.DP, products));
-  Problem p{X, col_scale, labels, N, D, L.DP, K, L.Kpad, dtype, metric, products, flags, s, S,
+  const int64_t nblocks = ceil_div(N, main_rows_per_block(dtype, L.DPX, products));
+  Problem p{X, col_scale, labels, N, D, L.DPX, K, L.Kpad, dtype, metric, products, flags, s, S,
             nblocks};
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int call = g_prof.on && g_prof.used < g_prof.cap ? g_prof.used++ : -1;
@@ -192,7 +194,7 @@ int silhouette_cluster_stats(const void* X, int32_t dtype, const float* col_scal
   int rc = check_common(X, dtype, col_scale, labels, N, D, K, metric, ws, ws_bytes, 0, &L);
   if (rc) return rc;
   const WsPtrs w = carve(L, ws);
-  Problem p{X, col_scale, labels, N, D, L.DP, K, L.Kpad, dtype, metric, 3, 0, nullptr, nullptr, 0};
+  Problem p{X, col_scale, labels, N, D, L.DPX, K, L.Kpad, dtype, metric, 3, 0, nullptr, nullptr, 0};
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (launch_stats(p, L, w, st) != hipSuccess) return SIL_E_HIP;
   if (launch_copy_stats(p, L, w, count, V, psi, st) != hipSuccess) return SIL_E_HIP;

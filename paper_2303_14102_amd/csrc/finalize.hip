@@ -9,9 +9,9 @@
 //     c_k = ||mu'_k||^2 + sigma_k^2            (uncentred: c_k = Psi_k / N_k, m = 0).
 // Cosine (Eq.18), z = x/||x||, mu_k = Omega_k / N_k:
 //     m(x, k) = 1 - z.mu_k = (1 - ||mu_k||^2 + ||z - mu_k||^2) / 2.
-// The b-path (minimum over the other clusters) uses the GEMM form; the a-path (own cluster)
-// uses the difference form, which has no cancellation.  All table entries are formed in FP64
-// and rounded once.
+// The b-path (minimum over the other clusters) uses the GEMM form, with c_k carried in the GEMM
+// depth; the a-path (own cluster) uses the difference form, which has no cancellation.  All
+// table entries are formed in FP64 and rounded once.
 #include "sil_internal.h"
 
 namespace sil {
@@ -27,22 +27,31 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
   return __uint_as_float(static_cast<uint32_t>(h) << 16);
 }
 
-// Global mean (centring vector), one thread per column; zeros when not centring.
+// Global mean (centring vector): one workgroup per column reduces the cluster sums in a fixed
+// order; zeros when not centring.
 __global__ __launch_bounds__(256) void k_gmean(const double* __restrict__ V,
                                                const int32_t* __restrict__ hdr, int32_t K,
                                                int32_t D, int32_t DP, int centre,
                                                double* __restrict__ gmean,
                                                float* __restrict__ mvec) {
-  const int l = threadIdx.x;
-  if (l >= DP) return;
+  __shared__ double sh[256];
+  const int l = blockIdx.x;
+  const int t = threadIdx.x;
   double m = 0.0;
-  if (centre && l < D) {
-    const double n = static_cast<double>(hdr[1]);
-    for (int32_t k = 0; k < K; ++k) m += V[static_cast<int64_t>(k) * D + l];
-    m = n > 0.0 ? m / n : 0.0;
+  if (centre && l < D)
+    for (int32_t k = t; k < K; k += 256) m += V[static_cast<int64_t>(k) * D + l];
+  sh[t] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
   }
-  gmean[l] = m;
-  mvec[l] = static_cast<float>(m);
+  if (t == 0) {
+    const double n = static_cast<double>(hdr[1]);
+    const double mean = (centre && l < D && n > 0.0) ? sh[0] / n : 0.0;
+    gmean[l] = mean;
+    mvec[l] = static_cast<float>(mean);
+  }
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -50,89 +59,96 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// One wave per (padded) cluster.
+// One wave per (padded) cluster.  GEMM table row k (DPX entries):
+//   fp32:  [alpha mu'_k (D), c_k, 0 ...]
+//   bf16:  hi = [bf16(alpha mu'_k) (D), c_hi, c_mid, c_lo, 0 ...],
+//          lo = [bf16(alpha mu'_k - hi) (D), 0 ...]
+// alpha = -2 (squared Euclidean) or -1 (cosine) is a power of two, so alpha mu' splits exactly
+// like mu'.  Empty and padding clusters get c_k = kEmptyC (finite, so that 0 * c stays 0 in the
+// split products) and a zero mean.
+constexpr double kEmptyC = 1.0e30;
+
 template <int METRIC, bool BF16TAB>
 __global__ __launch_bounds__(256) void k_finalize(
     const int32_t* __restrict__ count, const double* __restrict__ V,
     const double* __restrict__ psi, const double* __restrict__ gmean, int32_t K, int32_t Kpad,
-    int32_t D, int32_t DP, void* __restrict__ btab, float* __restrict__ cvec,
-    float* __restrict__ atab, float* __restrict__ avec, float* __restrict__ ascale) {
+    int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ atab,
+    float* __restrict__ avec, float* __restrict__ ascale) {
+  constexpr double ALPHA = METRIC == SIL_SQEUCLID ? -2.0 : -1.0;
   const int lane = threadIdx.x & 63;
   const int32_t k = static_cast<int32_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (k >= Kpad) return;
-  const int nrep = (DP + 63) / 64;
+  const int nrep = (RS + 63) / 64;
   float* bt32 = static_cast<float*>(btab);
   uint16_t* bthi = static_cast<uint16_t*>(btab);
-  uint16_t* btlo = bthi + static_cast<int64_t>(Kpad) * DP;
-  const int64_t brow = static_cast<int64_t>(k) * DP;
+  uint16_t* btlo = bthi + static_cast<int64_t>(Kpad) * RS;
+  const int64_t brow = static_cast<int64_t>(k) * RS;  // table row
+  const int64_t arow = static_cast<int64_t>(k) * DPX; // a-path row
   const int32_t n = k < K ? count[k] : 0;
-  if (n == 0) {
-    for (int r = 0; r < nrep; ++r) {
-      const int l = lane + 64 * r;
-      if (l >= DP) break;
-      if (BF16TAB) {
-        bthi[brow + l] = 0;
-        btlo[brow + l] = 0;
-      } else {
-        bt32[brow + l] = 0.0f;
-      }
-      if (k < K) atab[brow + l] = 0.0f;
-    }
-    if (lane == 0) {
-      cvec[k] = __builtin_inff();
-      if (k < K) {
-        avec[k] = 0.0f;
-        ascale[k] = 0.0f;
-      }
-    }
-    return;
-  }
   const double dn = static_cast<double>(n);
   double mu2 = 0.0, muc2 = 0.0;
   for (int r = 0; r < nrep; ++r) {
     const int l = lane + 64 * r;
-    if (l >= DP) break;
-    const double mu = l < D ? V[static_cast<int64_t>(k) * D + l] / dn : 0.0;
-    const double muc = METRIC == SIL_SQEUCLID ? mu - gmean[l] : mu;
+    if (l >= RS) break;
+    double mu = 0.0, muc = 0.0;
+    if (n > 0 && l < D) {
+      mu = V[static_cast<int64_t>(k) * D + l] / dn;
+      muc = METRIC == SIL_SQEUCLID ? mu - gmean[l] : mu;
+    }
     mu2 += mu * mu;
     muc2 += muc * muc;
+    const double g = ALPHA * muc;  // exact scaling
     if (BF16TAB) {
-      const uint16_t hi = f32_to_bf16_rne(static_cast<float>(muc));
-      const uint16_t lo = f32_to_bf16_rne(static_cast<float>(muc - static_cast<double>(bf16_to_f32(hi))));
+      const uint16_t hi = f32_to_bf16_rne(static_cast<float>(g));
       bthi[brow + l] = hi;
-      btlo[brow + l] = lo;
+      btlo[brow + l] = f32_to_bf16_rne(static_cast<float>(g - static_cast<double>(bf16_to_f32(hi))));
     } else {
-      bt32[brow + l] = static_cast<float>(muc);
+      bt32[brow + l] = static_cast<float>(g);
     }
-    atab[brow + l] = static_cast<float>(muc);
+    if (k < K && l < DPX) atab[arow + l] = static_cast<float>(muc);
   }
   mu2 = wave_sum(mu2);
   muc2 = wave_sum(muc2);
   if (lane == 0) {
-    double c, av;
-    if (METRIC == SIL_SQEUCLID) {
-      const double mean_sq = psi[k] / dn;
-      const double sigma2 = fmax(0.0, mean_sq - mu2);
-      c = muc2 + sigma2;  // equals Psi_k/N_k when gmean = 0
-      av = sigma2;
-    } else {
-      c = 1.0;
-      av = fmax(0.0, 1.0 - mu2);
+    double c = kEmptyC, av = 0.0;
+    if (n > 0) {
+      if (METRIC == SIL_SQEUCLID) {
+        const double sigma2 = fmax(0.0, psi[k] / dn - mu2);
+        c = muc2 + sigma2;  // equals Psi_k/N_k when the centring vector is zero
+        av = sigma2;
+      } else {
+        c = 1.0;
+        av = fmax(0.0, 1.0 - mu2);
+      }
     }
-    cvec[k] = static_cast<float>(c);
-    avec[k] = static_cast<float>(av);
-    ascale[k] = n >= 2 ? static_cast<float>(dn / (dn - 1.0)) : 0.0f;
+    if (BF16TAB) {  // c as three bf16 pieces in the slots D, D+1, D+2
+      const uint16_t c1 = f32_to_bf16_rne(static_cast<float>(c));
+      const double r1 = c - static_cast<double>(bf16_to_f32(c1));
+      const uint16_t c2 = f32_to_bf16_rne(static_cast<float>(r1));
+      const double r2 = r1 - static_cast<double>(bf16_to_f32(c2));
+      bthi[brow + D] = c1;
+      bthi[brow + D + 1] = c2;
+      bthi[brow + D + 2] = f32_to_bf16_rne(static_cast<float>(r2));
+    } else {
+      bt32[brow + D] = static_cast<float>(c);
+    }
+    if (k < K) {
+      avec[k] = static_cast<float>(av);
+      ascale[k] = n >= 2 ? static_cast<float>(dn / (dn - 1.0)) : 0.0f;
+    }
   }
 }
 
 hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
   const int centre = p.metric == SIL_SQEUCLID && !(p.flags & SIL_FLAG_NO_CENTRE);
-  k_gmean<<<1, 256, 0, st>>>(w.V, w.hdr, p.K, p.D, p.DP, centre, w.gmean, w.mvec);
+  k_gmean<<<static_cast<unsigned>(p.DPX), 256, 0, st>>>(w.V, w.hdr, p.K, p.D, p.DPX, centre,
+                                                        w.gmean, w.mvec);
   const unsigned nb = static_cast<unsigned>(ceil_div(p.Kpad, 4));
   const bool bf = p.dtype != SIL_F32;
 #define SIL_FIN(MT, BF)                                                                        \
-  k_finalize<MT, BF><<<nb, 256, 0, st>>>(w.count, w.V, w.psi, w.gmean, p.K, p.Kpad, p.D, p.DP, \
-                                         w.btab, w.cvec, w.atab, w.avec, w.ascale)
+  k_finalize<MT, BF><<<nb, 256, 0, st>>>(w.count, w.V, w.psi, w.gmean, p.K, p.Kpad, p.D, p.DPX, \
+                                         table_stride(p.DPX, p.dtype), w.btab, w.atab, w.avec,  \
+                                         w.ascale)
   if (p.metric == SIL_SQEUCLID) {
     if (bf) SIL_FIN(SIL_SQEUCLID, true);
     else SIL_FIN(SIL_SQEUCLID, false);

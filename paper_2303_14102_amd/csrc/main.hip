@@ -4,21 +4,37 @@
 
 namespace sil {
 
-// S = sum of the workgroup sums / N in a fixed order; NaN when the workspace holds an error.
-__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ bpart, int64_t nb,
-                                                 int64_t N, const int32_t* __restrict__ hdr,
-                                                 double* __restrict__ S) {
-  __shared__ double sh[1024];
+// S = sum of the workgroup sums / N, in two fixed-order stages (deterministic); NaN when the
+// workspace holds an error.  Stage 1: block b sums partials [b*chunk, (b+1)*chunk).
+__device__ __forceinline__ double block_sum_1024(double v, double* sh) {
   const int t = threadIdx.x;
-  double v = 0.0;
-  for (int64_t i = t; i < nb; i += 1024) v += bpart[i];
   sh[t] = v;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
     if (t < w) sh[t] += sh[t + w];
     __syncthreads();
   }
-  if (t == 0) *S = hdr[0] != 0 ? __builtin_nan("") : sh[0] / static_cast<double>(N);
+  return sh[0];
+}
+
+__global__ __launch_bounds__(1024) void k_reduce1(const double* __restrict__ bpart, int64_t nb,
+                                                  int64_t chunk, double* __restrict__ out) {
+  __shared__ double sh[1024];
+  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t b1 = min(nb, b0 + chunk);
+  double v = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += 1024) v += bpart[i];
+  const double tot = block_sum_1024(v, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_reduce2(const double* __restrict__ part, int n,
+                                                  int64_t N, const int32_t* __restrict__ hdr,
+                                                  double* __restrict__ S) {
+  __shared__ double sh[1024];
+  const double v = static_cast<int>(threadIdx.x) < n ? part[threadIdx.x] : 0.0;
+  const double tot = block_sum_1024(v, sh);
+  if (threadIdx.x == 0) *S = hdr[0] != 0 ? __builtin_nan("") : tot / static_cast<double>(N);
 }
 
 __global__ void k_poison(const int32_t* __restrict__ hdr, float* __restrict__ s, int64_t N) {
@@ -28,10 +44,10 @@ __global__ void k_poison(const int32_t* __restrict__ hdr, float* __restrict__ s,
     s[i] = __builtin_nanf("");
 }
 
-int main_rows_per_block(int dtype, int DP, int products) {
+int main_rows_per_block(int dtype, int DPX, int products) {
   if (dtype == SIL_F32) return kMainWaves * 32;
   if (products < 1 || products > 3) products = 3;
-  return kMainWaves * 32 * bf16_nb(DP, products);
+  return kMainWaves * 32 * bf16_nb(DPX, products);
 }
 
 hipError_t launch_main(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
@@ -39,17 +55,18 @@ hipError_t launch_main(const Problem& p, const WsLayout& L, const WsPtrs& w, hip
   MainArgs m;
   m.X = p.X;
   m.col_scale = p.col_scale;
-  m.labels = p.labels;
+  m.perm = w.perm;
+  m.lsorted = w.lsorted;
+  m.hdr = w.hdr;
   m.N = p.N;
   m.D = p.D;
   m.K = p.K;
   m.btab = w.btab;
-  m.cvec = w.cvec;
+  m.piece = static_cast<int64_t>(p.Kpad) * table_stride(p.DPX, p.dtype);
   m.atab = w.atab;
   m.avec = w.avec;
   m.ascale = w.ascale;
   m.mvec = w.mvec;
-  m.Kpad = p.Kpad;
   m.ntiles = p.Kpad / kColTile;
   m.s = p.s;
   m.bpart = w.bpart;
@@ -58,17 +75,20 @@ hipError_t launch_main(const Problem& p, const WsLayout& L, const WsPtrs& w, hip
   m.save_n = w.save_n;
   const unsigned grid = static_cast<unsigned>(p.nblocks);
   if (p.dtype == SIL_F32)
-    launch_main_f32(m, p.DP, p.metric, (p.flags & SIL_FLAG_SAVE_FOR_GRAD) != 0, grid, st);
+    launch_main_f32(m, p.DPX, p.metric, (p.flags & SIL_FLAG_SAVE_FOR_GRAD) != 0, grid, st);
   else if (p.dtype == SIL_BF16)
-    launch_main_bf16(m, p.DP, p.metric, p.products, grid, st);
+    launch_main_bf16(m, p.DPX, p.metric, p.products, grid, st);
   else
-    launch_main_fp8(m, p.DP, p.metric, p.products, grid, st);
+    launch_main_fp8(m, p.DPX, p.metric, p.products, grid, st);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
   (void)L;
-  k_reduce<<<1, 1024, 0, st>>>(w.bpart, p.nblocks, p.N, w.hdr, p.S);
+  const int64_t chunk = ceil_div(p.nblocks, 1024) < 4096 ? 4096 : ceil_div(p.nblocks, 1024);
+  const int n1 = static_cast<int>(ceil_div(p.nblocks, chunk));
+  k_reduce1<<<static_cast<unsigned>(n1), 1024, 0, st>>>(w.bpart, p.nblocks, chunk, w.bpart2);
+  k_reduce2<<<1, 1024, 0, st>>>(w.bpart2, n1, p.N, w.hdr, p.S);
   if (p.s) k_poison<<<1024, 256, 0, st>>>(w.hdr, p.s, p.N);
   return hipGetLastError();
 }

@@ -3,31 +3,32 @@
 
 namespace sil {
 
-template <int DP, int METRIC>
+template <int DPX, int METRIC>
 static void run_f32(const MainArgs& m, bool save, unsigned grid, hipStream_t st) {
   if (save)
-    k_main_f32<DP, 1, METRIC, true><<<grid, 256, 0, st>>>(m);
+    k_main_f32<DPX, 1, METRIC, true><<<grid, 256, 0, st>>>(m);
   else
-    k_main_f32<DP, 1, METRIC, false><<<grid, 256, 0, st>>>(m);
+    k_main_f32<DPX, 1, METRIC, false><<<grid, 256, 0, st>>>(m);
 }
 
 template <int METRIC>
-static void run_f32_dp(const MainArgs& m, int DP, bool save, unsigned grid, hipStream_t st) {
-  switch (DP) {
+static void run_f32_dp(const MainArgs& m, int DPX, bool save, unsigned grid, hipStream_t st) {
+  switch (DPX) {
     case 16: run_f32<16, METRIC>(m, save, grid, st); break;
-    case 32: run_f32<32, METRIC>(m, save, grid, st); break;
-    case 64: run_f32<64, METRIC>(m, save, grid, st); break;
-    case 128: run_f32<128, METRIC>(m, save, grid, st); break;
-    default: run_f32<256, METRIC>(m, save, grid, st); break;
+    case 24: run_f32<24, METRIC>(m, save, grid, st); break;
+    case 40: run_f32<40, METRIC>(m, save, grid, st); break;
+    case 72: run_f32<72, METRIC>(m, save, grid, st); break;
+    case 136: run_f32<136, METRIC>(m, save, grid, st); break;
+    default: run_f32<264, METRIC>(m, save, grid, st); break;
   }
 }
 
-void launch_main_f32(const MainArgs& m, int DP, int metric, bool save, unsigned grid,
+void launch_main_f32(const MainArgs& m, int DPX, int metric, bool save, unsigned grid,
                      hipStream_t st) {
   if (metric == SIL_SQEUCLID)
-    run_f32_dp<SIL_SQEUCLID>(m, DP, save, grid, st);
+    run_f32_dp<SIL_SQEUCLID>(m, DPX, save, grid, st);
   else
-    run_f32_dp<SIL_COSINE>(m, DP, save, grid, st);
+    run_f32_dp<SIL_COSINE>(m, DPX, save, grid, st);
 }
 
 }  // namespace sil

@@ -1,28 +1,35 @@
 // Pass 2 of the method, fused: for every point the mean distance to every cluster from the
-// cluster statistics (Eq.11 / Eq.18), a_i, b_i, s_i (Eq.1) and a per-workgroup sum of s_i;
-// then the fixed-order reduction of S (Section II).
+// cluster statistics (Eq.11 / Eq.18), a_i, b_i, s_i (Eq.1) and a per-workgroup sum of s_i.
 //
-// The point-to-cluster-mean cross term x'.mu'_k over all (i, k) is a dense [N x D] x [D x K]
-// product and runs on MFMA; the [N x K] result never leaves registers.
+// The point-to-cluster-mean term over all (i, k) is a dense [N x D] x [D x K] product and runs
+// on MFMA; the [N x K] result never leaves registers.  The per-cluster constant rides in the
+// GEMM depth: the table row of cluster k is [alpha * mu'_k, c_k] and the point carries
+// [x', 1], so the accumulator directly holds
+//     v_ik = c_k + alpha x'_i.mu'_k      (alpha = -2 squared Euclidean, -1 cosine)
+// and the epilogue is a running minimum.  b_i = ||x'_i||^2 + min_{k != own} v_ik (squared
+// Euclidean) or min_{k != own} v_ik (cosine, c_k = 1).  Empty and padding clusters carry a huge
+// finite c_k.  (For bf16 the constant is carried as three bf16 pieces, hi + mid + lo.)
 //
-// Workgroup: 4 waves; each wave owns NB blocks of 32 rows whose MFMA A-fragments stay in
-// registers for the whole sweep over the clusters.  The cluster-mean table is streamed through
-// LDS in tiles of 32 clusters (double-buffered, one barrier per tile).  Per tile every wave runs
-// the 32x32 MFMA blocks and the epilogue
-//     v = c_k + alpha * acc          (alpha = -2 squared Euclidean, -1 cosine)
-//     v = +inf for the own cluster   (the column equal to the row's label)
-//     running minimum over the tiles (and its column when the backward needs it)
-// so b_i = ||x'_i||^2 + min_k v (squared Euclidean) or min_k v (cosine).  Empty and padding
-// clusters carry c_k = +inf.
+// Rows are visited in label-sorted order (the permutation of the statistics pass), so a block
+// of 32 rows almost always belongs to one cluster: its own-cluster column is then excluded by a
+// lane mask in a single tile instead of a test per element.  Blocks that straddle a cluster
+// boundary take a per-element test against labels staged in LDS.
+//
+// Workgroup: 4 waves; each wave owns NB blocks of 32 sorted rows whose MFMA A-fragments stay in
+// registers for the whole sweep over the clusters.  The table is streamed in tiles of 64
+// clusters through an LDS ring of NSTAGE stages filled by direct global->LDS loads, NSTAGE-1
+// tiles ahead, one barrier per tile.  Within a tile the two 32-cluster blocks alternate between
+// two accumulator sets, so that the minimum over one block runs while the MFMAs of the next are
+// in flight, and each k-step's table fragments are read one step ahead.
 //
 // a_i uses the difference form ||x' - mu'_o||^2 + sigma_o^2 (cosine: (1 - ||mu_o||^2 +
 // ||z - mu_o||^2)/2) in fp32 from the unrounded point, so the own-cluster term has no
 // cancellation; it is computed in the prologue while the point is loaded.
 //
 // bf16 / fp8 storage: the point is decoded to fp32, centred (squared Euclidean), normalised
-// (cosine), then split x' = hi + lo into two bf16; the cluster means are split the same way in
-// the table.  products = 1: hi.hi; 2: hi.hi + hi.lo; 3: hi.hi + hi.lo + lo.hi.  fp32 storage
-// runs fp32 MFMA on the unsplit values.
+// (cosine), then split x' = hi + lo into two bf16; the table holds the same split of
+// alpha mu'.  products = 1: hi.hi; 2: hi.hi + hi.lo; 3: hi.hi + hi.lo + lo.hi.  fp32 storage
+// runs fp32 MFMA on unsplit values.
 #pragma once
 #include "sil_internal.h"
 
@@ -31,23 +38,25 @@ namespace sil {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef int32_t i32x4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
 
 struct MainArgs {
   const void* X;
   const float* col_scale;
-  const int32_t* labels;
+  const int32_t* perm;     // sorted position -> row
+  const int32_t* lsorted;  // sorted position -> label
+  const int32_t* hdr;      // [1] = number of valid (sorted) positions
   int64_t N;
   int32_t D;
   int32_t K;
-  const void* btab;
-  const float* cvec;
-  const float* atab;
+  const void* btab;        // [pieces][Kpad][RS], RS = table_stride(DPX)
+  int64_t piece;           // elements per piece (Kpad * RS)
+  const float* atab;       // [K][DPX] mu' (a-path)
   const float* avec;
   const float* ascale;
-  const float* mvec;
-  int32_t Kpad;
+  const float* mvec;       // [DPX] centring vector (zeros when not centring)
   int32_t ntiles;
   float* s;
   double* bpart;
@@ -76,7 +85,7 @@ __device__ __forceinline__ float e4m3_f32(uint32_t q) {
 }
 
 // W consecutive stored elements of row `row` starting at column c0, decoded to fp32; zero
-// outside [0, D) and for rows outside [0, N).
+// outside [0, D) and for invalid rows.
 template <int DT, int W>
 __device__ __forceinline__ void load_chunk(const void* __restrict__ X,
                                            const float* __restrict__ col_scale, int64_t row,
@@ -136,31 +145,129 @@ __device__ __forceinline__ void load_chunk(const void* __restrict__ X,
 __device__ __forceinline__ int out_row(int j, int h) { return 8 * (j >> 2) + 4 * h + (j & 3); }
 
 // ------------------------------------------------------------------------------------------
+// Per-block bookkeeping: sorted positions, rows, labels.
+
+template <int NB>
+struct Blocks {
+  int64_t p0;          // first sorted position of the wave's blocks
+  int64_t row[NB];     // row id of this lane's A-layout row (lane % 32) in block nb
+  bool ok[NB];         // position valid
+  int32_t lab[NB];     // label of that row (-1 if invalid)
+  bool mixed[NB];      // block straddles a cluster boundary (wave-uniform)
+  int32_t town[NB];    // uniform block: tile holding the own cluster (wave-uniform)
+  int32_t cown[NB];    // uniform block: lane column of the own cluster (wave-uniform)
+};
+
+template <int NB>
+__device__ __forceinline__ void load_blocks(const MainArgs& a, int64_t nvalid, int64_t p0,
+                                            int lane, Blocks<NB>& B, int32_t* lds_lab) {
+  const int r = lane & 31;
+  B.p0 = p0;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t pos = p0 + nb * 32 + r;
+    B.ok[nb] = pos < nvalid;
+    B.row[nb] = B.ok[nb] ? a.perm[pos] : 0;
+    int32_t o = B.ok[nb] ? a.lsorted[pos] : -1;
+    if (o >= a.K) o = -1;
+    B.lab[nb] = o;
+    const int32_t o0 = __shfl(o, 0, 64);
+    B.mixed[nb] = !__all(o == o0 || o < 0);
+    B.town[nb] = o0 >> 5;
+    B.cown[nb] = o0 & 31;
+    if (lane < 32) lds_lab[nb * 32 + r] = o;  // labels of the block for the mixed-block path
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Prologue shared by both kernel families.  Lane (r = lane%32, h = lane/32) holds, for each of
 // its NB row blocks, the chunks c = 2q + h (q < NQ) of W elements of row r: it decodes them,
 // centres / normalises, computes its halves of ||x'||^2 and of the a-path sum, and hands each
-// transformed chunk to `emit(nb, q, vals)`.
-template <int DT, int W, int NQ, int NB, int METRIC, typename Emit>
-__device__ __forceinline__ void prologue(const MainArgs& a, int64_t wrow0, int lane,
-                                         float (&nrow)[NB], float (&arow)[NB],
-                                         int32_t (&orow)[NB], Emit&& emit) {
-  const int r = lane & 31, h = lane >> 5;
+// transformed chunk (with the constant-carrying slots [D, D+NC) set to 1) to emit(nb, q, vals).
+// When D is a multiple of W every chunk is one aligned vector load, issued for the whole row
+// before any is used (addresses clamped in range, values masked afterwards).
+
+template <int DT>
+struct RawChunk;
+template <>
+struct RawChunk<SIL_F32> { typedef f32x4_t T; };
+template <>
+struct RawChunk<SIL_BF16> { typedef u32x4_t T; };
+template <>
+struct RawChunk<SIL_FP8_E4M3> { typedef u32x2_t T; };
+
+template <int DT, int W>
+__device__ __forceinline__ typename RawChunk<DT>::T load_raw(const void* __restrict__ X,
+                                                              int64_t row, int32_t D, int32_t c0) {
+  const int64_t base = row * static_cast<int64_t>(D) + c0;
+  if constexpr (DT == SIL_F32)
+    return *reinterpret_cast<const f32x4_t*>(static_cast<const float*>(X) + base);
+  else if constexpr (DT == SIL_BF16)
+    return *reinterpret_cast<const u32x4_t*>(static_cast<const uint16_t*>(X) + base);
+  else
+    return *reinterpret_cast<const u32x2_t*>(static_cast<const uint8_t*>(X) + base);
+}
+
+template <int DT, int W>
+__device__ __forceinline__ void decode_raw(typename RawChunk<DT>::T raw,
+                                           const float* __restrict__ col_scale, int32_t c0,
+                                           bool valid, float* out) {
+  if constexpr (DT == SIL_F32) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = raw[e];
+  } else if constexpr (DT == SIL_BF16) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      out[2 * e] = bf16_bits_f32(raw[e] & 0xffffu);
+      out[2 * e + 1] = bf16_bits_f32(raw[e] >> 16);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      out[e] = e4m3_f32((raw[0] >> (8 * e)) & 0xffu) * col_scale[c0 + e];
+      out[4 + e] = e4m3_f32((raw[1] >> (8 * e)) & 0xffu) * col_scale[c0 + 4 + e];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < W; ++e) out[e] = valid ? out[e] : 0.0f;
+}
+
+template <int DT, int W, int NQ, int NB, int METRIC, int NC, typename Emit>
+__device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B, int lane,
+                                         float (&nrow)[NB], float (&arow)[NB], Emit&& emit) {
+  constexpr int DPX = 2 * NQ * W;
+  const int h = lane >> 5;
+  const bool vec = (a.D % W) == 0;  // wave-uniform
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    const int64_t row = wrow0 + nb * 32 + r;
-    const bool ok = row < a.N;
-    int32_t o = ok ? a.labels[row] : -1;
-    if (o < 0 || o >= a.K) o = -1;
+    const bool ok = B.ok[nb];
+    const int64_t row = ok ? B.row[nb] : 0;
+    const int32_t o = B.lab[nb];
+    const int64_t orow = static_cast<int64_t>(o >= 0 ? o : 0) * DPX;
+    float xv[NQ][W];
+    if (vec) {
+      typename RawChunk<DT>::T raw[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int c0 = (2 * q + h) * W;
+        raw[q] = load_raw<DT, W>(a.X, row, a.D, c0 < a.D ? c0 : 0);
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int c0 = (2 * q + h) * W;
+        decode_raw<DT, W>(raw[q], a.col_scale, c0 < a.D ? c0 : 0, ok && c0 < a.D, xv[q]);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) load_chunk<DT, W>(a.X, a.col_scale, row, ok, a.D, (2 * q + h) * W, xv[q]);
+    }
     float inv = 1.0f;
     if constexpr (METRIC == SIL_COSINE) {
       float n2 = 0.0f;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        float v[W];
-        load_chunk<DT, W>(a.X, a.col_scale, row, ok, a.D, (2 * q + h) * W, v);
+      for (int q = 0; q < NQ; ++q)
 #pragma unroll
-        for (int e = 0; e < W; ++e) n2 = fmaf(v[e], v[e], n2);
-      }
+        for (int e = 0; e < W; ++e) n2 = fmaf(xv[q][e], xv[q][e], n2);
       n2 += __shfl_xor(n2, 32, 64);
       inv = n2 > 0.0f ? 1.0f / sqrtf(n2) : 0.0f;
     }
@@ -169,26 +276,23 @@ __device__ __forceinline__ void prologue(const MainArgs& a, int64_t wrow0, int l
     for (int q = 0; q < NQ; ++q) {
       const int c0 = (2 * q + h) * W;
       float v[W];
-      load_chunk<DT, W>(a.X, a.col_scale, row, ok, a.D, c0, v);
 #pragma unroll
       for (int e = 0; e < W; ++e) {
-        if constexpr (METRIC == SIL_COSINE) {
-          v[e] *= inv;
-        } else {
-          v[e] = ok ? v[e] - a.mvec[c0 + e] : 0.0f;  // mvec is zero when not centring
-        }
+        if constexpr (METRIC == SIL_COSINE)
+          v[e] = xv[q][e] * inv;
+        else
+          v[e] = ok ? xv[q][e] - a.mvec[c0 + e] : 0.0f;  // mvec is zero when not centring
         nx = fmaf(v[e], v[e], nx);
-        if (o >= 0) {
-          const float dd = v[e] - a.atab[static_cast<int64_t>(o) * (2 * NQ * W) + c0 + e];
-          ad = fmaf(dd, dd, ad);
-        }
+        const float dd = v[e] - a.atab[orow + c0 + e];
+        ad = fmaf(dd, dd, ad);
+        const int idx = c0 + e;
+        if (idx >= a.D && idx < a.D + NC) v[e] = 1.0f;  // carries c_k through the GEMM
       }
       emit(nb, q, v);
     }
     nx += __shfl_xor(nx, 32, 64);
     ad += __shfl_xor(ad, 32, 64);
     nrow[nb] = nx;
-    orow[nb] = o;
     if (o >= 0) {
       const float sc = a.ascale[o];
       arow[nb] = METRIC == SIL_SQEUCLID ? sc * (ad + a.avec[o]) : sc * 0.5f * (a.avec[o] + ad);
@@ -198,14 +302,57 @@ __device__ __forceinline__ void prologue(const MainArgs& a, int64_t wrow0, int l
   }
 }
 
-// Epilogue after the sweep: row minima across the 32 lanes of each half, then s_i per row and
-// the workgroup's sum of s_i.
+// Running minimum over one tile of the accumulators of block nb.
+template <bool SAVE>
+__device__ __forceinline__ void tile_min(const f32x16_t& acc, float (&mn)[16], int32_t (&arg)[16],
+                                         bool mixed, bool own_tile, int col, int cown, int t32,
+                                         const int32_t* lab_block, int h) {
+  constexpr float BIG = 3.0e38f;
+  if (mixed) {  // per-element own-cluster test against the block's labels
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const i32x4_t l4 = *reinterpret_cast<const i32x4_t*>(lab_block + 8 * q + 4 * h);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = 4 * q + e;
+        const float v = (l4[e] == t32 + col) ? BIG : acc[j];
+        if constexpr (SAVE) {
+          if (v < mn[j]) { mn[j] = v; arg[j] = t32 + col; }
+        } else {
+          mn[j] = fminf(mn[j], v);
+        }
+      }
+    }
+  } else if (own_tile) {  // the own cluster is column cown of this tile for every row
+    const bool me = col == cown;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const float v = me ? BIG : acc[j];
+      if constexpr (SAVE) {
+        if (v < mn[j]) { mn[j] = v; arg[j] = t32 + col; }
+      } else {
+        mn[j] = fminf(mn[j], v);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if constexpr (SAVE) {
+        if (acc[j] < mn[j]) { mn[j] = acc[j]; arg[j] = t32 + col; }
+      } else {
+        mn[j] = fminf(mn[j], acc[j]);
+      }
+    }
+  }
+}
+
+// After the sweep: row minima across the 32 lanes of each half, then s_i per row (written to
+// the row's original index) and the workgroup's sum of s_i.
 template <int NB, int METRIC, bool SAVE>
-__device__ __forceinline__ void finish(const MainArgs& a, int64_t wrow0, int wave, int lane,
+__device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Blocks<NB>& B, int wave, int lane,
                                        float (&mn)[NB][16], int32_t (&arg)[NB][16],
                                        const float (&nrow)[NB], const float (&arow)[NB],
-                                       const int32_t (&orow)[NB], float* lds_min,
-                                       int32_t* lds_arg, double* lds_bsum) {
+                                       float* lds_min, int32_t* lds_arg, double* lds_bsum) {
   const int h = lane >> 5, col = lane & 31;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
@@ -234,10 +381,10 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wrow0, int wav
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     if ((nb & 1) != h) continue;  // lanes of half h finish the blocks nb = h, h+2, ...
+    if (!B.ok[nb]) continue;
     const int r = lane & 31;
-    const int64_t row = wrow0 + nb * 32 + r;
-    if (row >= a.N) continue;
-    const int32_t o = orow[nb];
+    const int64_t row = B.row[nb];
+    const int32_t o = B.lab[nb];
     float b = lds_min[nb * 32 + r];
     if constexpr (METRIC == SIL_SQEUCLID) b += nrow[nb];
     b = fmaxf(b, 0.0f);
@@ -261,68 +408,95 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wrow0, int wav
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int w = 0; w < kMainWaves; ++w) t += lds_bsum[w];
-    a.bpart[blockIdx.x] = t;
+    a.bpart[wb] = t;
   }
+  __syncthreads();  // lds_min / lds_bsum are reused by the next row block
 }
 
 // ------------------------------------------------------------------------------------------
-// Staging of one 32-cluster tile of the mean table: global (L2) -> registers -> LDS.  Every
-// thread loads a valid 16-byte chunk (small tiles wrap around) so that the staging registers
-// are written unconditionally; only threads with a chunk index below CHUNKS store to LDS.
+// Tile ring: one tile is PIECES contiguous blocks of kColTile table rows x ROWBYTES in global memory;
+// wave w moves 1 KB per instruction (lane l -> 16 bytes at LDS offset 16 l), IPW instructions
+// per wave and tile.
 
-template <int DP, int NPC, int CPT>
-__device__ __forceinline__ void stage_load_bf16(u32x4_t (&stg)[NPC][CPT],
-                                                const uint16_t* __restrict__ bt, int64_t piece,
-                                                int t, int tid) {
-  constexpr int CHUNKS = 32 * DP / 8;
+template <int PIECES, int ROWBYTES>
+struct Ring {
+  static constexpr int SLOTS_PER_PIECE = kColTile * ROWBYTES / 16;
+  static constexpr int TOT = PIECES * SLOTS_PER_PIECE;  // 16-byte slots per tile
+  static constexpr int IPW = (TOT + 64 * kMainWaves - 1) / (64 * kMainWaves);
+  // fewest instructions any wave issues per tile: waiting until at most this many are in
+  // flight guarantees that every older tile has landed
+  static constexpr int IPW_MIN = TOT / (64 * kMainWaves);
+  static constexpr int STAGE_BYTES = TOT * 16;
+  // three stages while two workgroups per CU still fit the 160 KB of LDS, else two
+  static constexpr int NSTAGE = 3 * STAGE_BYTES <= 52 * 1024 ? 3 : 2;
+};
+
+template <typename R>
+__device__ __forceinline__ void issue_tile(const char* __restrict__ base, int64_t piece_bytes,
+                                           int t, uint8_t* stage, int wave, int lane) {
 #pragma unroll
-  for (int pc = 0; pc < NPC; ++pc)
-#pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-      const int q = (tid + 256 * i) % CHUNKS;
-      const int rr = q / (DP / 8), cc = q % (DP / 8);
-      stg[pc][i] = *reinterpret_cast<const u32x4_t*>(bt + pc * piece +
-                                                    static_cast<int64_t>(32 * t + rr) * DP + 8 * cc);
+  for (int i = 0; i < R::IPW; ++i) {
+    const int blk = i * kMainWaves + wave;
+    const int q = blk * 64 + lane;
+    if (blk * 64 < R::TOT) {
+      const int pc = q / R::SLOTS_PER_PIECE, w = q % R::SLOTS_PER_PIECE;
+      const char* src = base + pc * piece_bytes + static_cast<int64_t>(t) * R::SLOTS_PER_PIECE * 16 +
+                        static_cast<int64_t>(w) * 16;
+      if (q < R::TOT)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(stage + blk * 1024),
+                                         16, 0, 0);
     }
-}
-
-template <int DP, int NPC, int CPT, int LROW>
-__device__ __forceinline__ void stage_store_bf16(const u32x4_t (&stg)[NPC][CPT], uint16_t* lds,
-                                                 int tile_elems, int tid) {
-  constexpr int CHUNKS = 32 * DP / 8;
-#pragma unroll
-  for (int pc = 0; pc < NPC; ++pc)
-#pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-      const int q = tid + 256 * i;
-      if (CHUNKS % 256 == 0 || q < CHUNKS) {
-        const int rr = q / (DP / 8), cc = q % (DP / 8);
-        *reinterpret_cast<u32x4_t*>(lds + pc * tile_elems + rr * LROW + 8 * cc) = stg[pc][i];
-      }
-    }
-}
-
-template <int DP, int CPT>
-__device__ __forceinline__ void stage_load_f32(f32x4_t (&stg)[CPT], const float* __restrict__ bt,
-                                               int t, int tid) {
-  constexpr int CHUNKS = 32 * DP / 4;
-#pragma unroll
-  for (int i = 0; i < CPT; ++i) {
-    const int q = (tid + 256 * i) % CHUNKS;
-    const int rr = q / (DP / 4), cc = q % (DP / 4);
-    stg[i] = *reinterpret_cast<const f32x4_t*>(bt + static_cast<int64_t>(32 * t + rr) * DP + 4 * cc);
   }
 }
 
-template <int DP, int CPT, int LROW>
-__device__ __forceinline__ void stage_store_f32(const f32x4_t (&stg)[CPT], float* lds, int tid) {
-  constexpr int CHUNKS = 32 * DP / 4;
-#pragma unroll
-  for (int i = 0; i < CPT; ++i) {
-    const int q = tid + 256 * i;
-    if (CHUNKS % 256 == 0 || q < CHUNKS) {
-      const int rr = q / (DP / 4), cc = q % (DP / 4);
-      *reinterpret_cast<f32x4_t*>(lds + rr * LROW + 4 * cc) = stg[i];
+// s_waitcnt for the vector-memory counter only (expcnt and lgkmcnt left at their maximum);
+// gfx9 encoding: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt_hi[15:14].
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Sweep over the tiles (the first NSTAGE-1 already issued by issue_first) with an LDS ring of
+// NSTAGE (2 or 3) stages, each its own __shared__
+// array and visited in a statically unrolled order, so that the compiler can tell the stage
+// being read from the stages being filled.  body(t, stage_to_read, prefetch) must call
+// prefetch() once, after its first LDS read; prefetch() issues tile t + NSTAGE - 1 into the stage
+// read in the previous step.  Each step: wait for this wave's loads of tile t, barrier (without
+// a memory fence: the loads of later tiles stay in flight), then the body.
+// The first NSTAGE-1 tiles, issued before the row block's prologue so that their latency
+// overlaps it (every wave must be done with the ring: call after a barrier).
+template <typename R>
+__device__ __forceinline__ void issue_first(const char* bt, int64_t piece_bytes, int ntiles,
+                                            uint8_t* r0, uint8_t* r1, int wave, int lane) {
+  for (int t = 0; t < R::NSTAGE - 1 && t < ntiles; ++t)
+    issue_tile<R>(bt, piece_bytes, t, t == 0 ? r0 : r1, wave, lane);
+}
+
+template <typename R, typename Body>
+__device__ __forceinline__ void sweep(const char* bt, int64_t piece_bytes, int ntiles,
+                                      uint8_t* r0, uint8_t* r1, uint8_t* r2, int wave, int lane,
+                                      Body&& body) {
+  constexpr int NS = R::NSTAGE;
+  auto step = [&](int t, uint8_t* rd, uint8_t* wr) __attribute__((always_inline)) {
+    if (NS == 3 && t + 1 < ntiles)
+      wait_vmcnt<R::IPW_MIN>();
+    else
+      wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    body(t, rd, [&]() __attribute__((always_inline)) {
+      if (t + NS - 1 < ntiles) issue_tile<R>(bt, piece_bytes, t + NS - 1, wr, wave, lane);
+    });
+  };
+  for (int t = 0; t < ntiles; t += NS) {
+    if constexpr (NS == 3) {
+      step(t, r0, r2);
+      if (t + 1 < ntiles) step(t + 1, r1, r0);
+      if (t + 2 < ntiles) step(t + 2, r2, r1);
+    } else {
+      step(t, r0, r1);
+      if (t + 1 < ntiles) step(t + 1, r1, r0);
     }
   }
 }
@@ -331,31 +505,40 @@ __device__ __forceinline__ void stage_store_f32(const f32x4_t (&stg)[CPT], float
 // bf16 MFMA family (X stored bf16 or fp8).  v_mfma_f32_32x32x16_bf16: lane (r, h) supplies
 // A[row r][16s + 8h .. +8] and B[col r][16s + 8h .. +8] for k-step s.
 
-template <int DP, int NB, int P, int DT, int METRIC, bool SAVE>
-__global__ __launch_bounds__(256, DP >= 256 ? 1 : 2) void k_main_bf16(MainArgs a) {
-  constexpr int S = DP / 16;
+template <int DPX, int NB, int P, int DT, int METRIC, bool SAVE>
+__global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_bf16(MainArgs a) {
+  constexpr int S = DPX / 16;
   constexpr int NPC = P >= 2 ? 2 : 1;
-  constexpr int LROW = DP + 8;  // padded LDS row (bf16 elements)
-  constexpr int TILE = 32 * LROW;
-  constexpr int CHUNKS = 32 * DP / 8;  // 16-byte chunks per piece per tile
-  constexpr int CPT = (CHUNKS + 255) / 256;
-  constexpr float ALPHA = METRIC == SIL_SQEUCLID ? -2.0f : -1.0f;
-  __shared__ __attribute__((aligned(16))) uint16_t lds_b[2][NPC][TILE];
+  constexpr int RS = table_stride(DPX, SIL_BF16);
+  using R = Ring<NPC, RS * 2>;
+  __shared__ __attribute__((aligned(16))) uint8_t ring0[R::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t ring1[R::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t ring2[R::NSTAGE == 3 ? R::STAGE_BYTES : 16];
   __shared__ float lds_min[kMainWaves][NB * 32];
   __shared__ int32_t lds_arg[kMainWaves][SAVE ? NB * 32 : 1];
+  __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves][NB * 32];
   __shared__ double lds_bsum[kMainWaves];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int col = lane & 31, h = lane >> 5;
-  const int64_t wrow0 = static_cast<int64_t>(blockIdx.x) * (kMainWaves * NB * 32) + wave * NB * 32;
+  const int64_t nvalid = a.hdr[1];
+  const int64_t wb = blockIdx.x;
+  const int64_t wg0 = wb * (kMainWaves * NB * 32);
+  if (wg0 >= nvalid) {  // no valid position in this row block (uniform)
+    if (tid == 0) a.bpart[wb] = 0.0;
+    return;
+  }
+  // the first tiles' latency overlaps the prologue
+  issue_first<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, wave, lane);
 
-  // ---- A fragments
+  Blocks<NB> B;
+  load_blocks<NB>(a, nvalid, wg0 + wave * NB * 32, lane, B, lds_lab[wave]);
+
   u32x4_t ahi[NB][S];
   u32x4_t alo[NB][P == 3 ? S : 1];
   float nrow[NB], arow[NB];
-  int32_t orow[NB];
-  prologue<DT, 8, S, NB, METRIC>(
-      a, wrow0, lane, nrow, arow, orow, [&](int nb, int q, const float* v) __attribute__((always_inline)) {
+  prologue<DT, 8, S, NB, METRIC, 3>(
+      a, B, lane, nrow, arow, [&](int nb, int q, const float* v) __attribute__((always_inline)) {
         uint32_t hw[4], lw[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -372,83 +555,81 @@ __global__ __launch_bounds__(256, DP >= 256 ? 1 : 2) void k_main_bf16(MainArgs a
         if constexpr (P == 3) alo[nb][q] = u32x4_t{lw[0], lw[1], lw[2], lw[3]};
       });
 
-  // own-cluster test: label(row of accumulator j) - col == 32 t
-  int32_t dlab[NB][16];
   float mn[NB][16];
   int32_t arg[NB][16];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const int32_t o = __shfl(orow[nb], out_row(j, h), 64);
-      dlab[nb][j] = o >= 0 ? o - col : -1;
       mn[nb][j] = __builtin_inff();
       arg[nb][j] = -1;
     }
 
-  // ---- sweep over cluster tiles
-  const uint16_t* bt = static_cast<const uint16_t*>(a.btab);
-  const int64_t piece = static_cast<int64_t>(a.Kpad) * DP;
-  u32x4_t stg[NPC][CPT];
-  stage_load_bf16<DP, NPC, CPT>(stg, bt, piece, 0, tid);
-  stage_store_bf16<DP, NPC, CPT, LROW>(stg, &lds_b[0][0][0], TILE, tid);
-  float cv_next = a.cvec[col];
-  __syncthreads();
-
-  for (int t = 0; t < a.ntiles; ++t) {
-    const int buf = t & 1;
-    const float cv = cv_next;
-    if (t + 1 < a.ntiles) {
-      stage_load_bf16<DP, NPC, CPT>(stg, bt, piece, t + 1, tid);
-      cv_next = a.cvec[32 * (t + 1) + col];
+  // B fragments of k-step s for both 32-cluster blocks of the tile: [block][piece]
+  struct Frag { bf16x8_t v[2][2]; };
+  auto bfrag = [&](const uint8_t* st, int s) __attribute__((always_inline)) {
+    Frag f;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int off = ((cb * 32 + col) * RS + 16 * s + 8 * h) * 2;
+      f.v[cb][0] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(st + off));
+      if constexpr (P >= 2)
+        f.v[cb][1] = __builtin_bit_cast(bf16x8_t,
+                                        *reinterpret_cast<const u32x4_t*>(st + R::SLOTS_PER_PIECE * 16 + off));
     }
-    f32x16_t acc[NB];
+    return f;
+  };
+  constexpr int LA = S >= 3 ? 2 : 1;  // k-steps of table fragments read ahead
+
+  f32x16_t acc0[NB], acc1[NB];
+  sweep<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, ring2, wave, lane,
+           [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
+    Frag f[LA + 1];
+    f[0] = bfrag(st, 0);
+    prefetch();
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int j = 0; j < 16; ++j) acc[nb][j] = 0.0f;
+    for (int s = 1; s < LA; ++s) f[s] = bfrag(st, s);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const u32x4_t bh = *reinterpret_cast<const u32x4_t*>(&lds_b[buf][0][col * LROW + 16 * s + 8 * h]);
-      const bf16x8_t bhv = __builtin_bit_cast(bf16x8_t, bh);
-      bf16x8_t blv;
-      if constexpr (P >= 2) {
-        const u32x4_t bl = *reinterpret_cast<const u32x4_t*>(&lds_b[buf][NPC - 1][col * LROW + 16 * s + 8 * h]);
-        blv = __builtin_bit_cast(bf16x8_t, bl);
-      }
+      if (s + LA < S) f[(s + LA) % (LA + 1)] = bfrag(st, s + LA);
+      // keep the read-ahead ahead: the scheduler would otherwise sink the reads next to
+      // their first use and wait for them there
+      __builtin_amdgcn_sched_barrier(0);
+      const Frag& g = f[s % (LA + 1)];
+      // the two blocks' accumulation chains interleaved: independent MFMAs back to back
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const bf16x8_t ah = __builtin_bit_cast(bf16x8_t, ahi[nb][s]);
-        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bhv, acc[nb], 0, 0, 0);
-        if constexpr (P >= 2) acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, blv, acc[nb], 0, 0, 0);
+        if (s == 0) {
+          acc0[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[0][0], f32x16_t{}, 0, 0, 0);
+          acc1[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[1][0], f32x16_t{}, 0, 0, 0);
+        } else {
+          acc0[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[0][0], acc0[nb], 0, 0, 0);
+          acc1[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[1][0], acc1[nb], 0, 0, 0);
+        }
+        if constexpr (P >= 2) {
+          acc0[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[0][1], acc0[nb], 0, 0, 0);
+          acc1[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[1][1], acc1[nb], 0, 0, 0);
+        }
         if constexpr (P == 3) {
           const bf16x8_t al = __builtin_bit_cast(bf16x8_t, alo[nb][s]);
-          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bhv, acc[nb], 0, 0, 0);
+          acc0[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, g.v[0][0], acc0[nb], 0, 0, 0);
+          acc1[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, g.v[1][0], acc1[nb], 0, 0, 0);
         }
       }
     }
-    const int32_t t32 = 32 * t;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        float v = fmaf(ALPHA, acc[nb][j], cv);
-        v = dlab[nb][j] == t32 ? __builtin_inff() : v;
-        if constexpr (SAVE) {
-          if (v < mn[nb][j]) {
-            mn[nb][j] = v;
-            arg[nb][j] = t32 + col;
-          }
-        } else {
-          mn[nb][j] = fminf(mn[nb][j], v);
-        }
-      }
-    if (t + 1 < a.ntiles) stage_store_bf16<DP, NPC, CPT, LROW>(stg, &lds_b[buf ^ 1][0][0], TILE, tid);
-    __syncthreads();
-  }
+    for (int nb = 0; nb < NB; ++nb) {
+      tile_min<SAVE>(acc0[nb], mn[nb], arg[nb], B.mixed[nb], 2 * t == B.town[nb], col, B.cown[nb],
+                     64 * t, lds_lab[wave] + nb * 32, h);
+      tile_min<SAVE>(acc1[nb], mn[nb], arg[nb], B.mixed[nb], 2 * t + 1 == B.town[nb], col,
+                     B.cown[nb], 64 * t + 32, lds_lab[wave] + nb * 32, h);
+    }
+  });
 
-  finish<NB, METRIC, SAVE>(a, wrow0, wave, lane, mn, arg, nrow, arow, orow, lds_min[wave],
-                           lds_arg[wave], lds_bsum);
+  __syncthreads();
+  finish<NB, METRIC, SAVE>(a, wb, B, wave, lane, mn, arg, nrow, arow, lds_min[wave], lds_arg[wave],
+                           lds_bsum);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -456,95 +637,93 @@ __global__ __launch_bounds__(256, DP >= 256 ? 1 : 2) void k_main_bf16(MainArgs a
 // and B[col r][k(s,h)] with k(s,h) = 8(s/4) + 4h + s%4, so each lane's operands are whole
 // float4 chunks c = 2q + h.
 
-template <int DP, int NB, int METRIC, bool SAVE>
-__global__ __launch_bounds__(256, DP >= 256 ? 1 : 2) void k_main_f32(MainArgs a) {
-  constexpr int NQ = DP / 8;   // float4 chunks per lane per row
-  constexpr int LROW = DP + 4; // padded LDS row (floats)
-  constexpr int TILE = 32 * LROW;
-  constexpr int CHUNKS = 32 * DP / 4;
-  constexpr int CPT = (CHUNKS + 255) / 256;
-  constexpr float ALPHA = METRIC == SIL_SQEUCLID ? -2.0f : -1.0f;
-  __shared__ __attribute__((aligned(16))) float lds_b[2][TILE];
+template <int DPX, int NB, int METRIC, bool SAVE>
+__global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_f32(MainArgs a) {
+  constexpr int NQ = DPX / 8;
+  constexpr int RS = table_stride(DPX, SIL_F32);
+  using R = Ring<1, RS * 4>;
+  __shared__ __attribute__((aligned(16))) uint8_t ring0[R::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t ring1[R::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t ring2[R::NSTAGE == 3 ? R::STAGE_BYTES : 16];
   __shared__ float lds_min[kMainWaves][NB * 32];
   __shared__ int32_t lds_arg[kMainWaves][SAVE ? NB * 32 : 1];
+  __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves][NB * 32];
   __shared__ double lds_bsum[kMainWaves];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int col = lane & 31, h = lane >> 5;
-  const int64_t wrow0 = static_cast<int64_t>(blockIdx.x) * (kMainWaves * NB * 32) + wave * NB * 32;
+  const int64_t nvalid = a.hdr[1];
+  const int64_t wb = blockIdx.x;
+  const int64_t wg0 = wb * (kMainWaves * NB * 32);
+  if (wg0 >= nvalid) {  // no valid position in this row block (uniform)
+    if (tid == 0) a.bpart[wb] = 0.0;
+    return;
+  }
+  // the first tiles' latency overlaps the prologue
+  issue_first<R>(static_cast<const char*>(a.btab), 0, a.ntiles, ring0, ring1, wave, lane);
+
+  Blocks<NB> B;
+  load_blocks<NB>(a, nvalid, wg0 + wave * NB * 32, lane, B, lds_lab[wave]);
 
   f32x4_t areg[NB][NQ];
   float nrow[NB], arow[NB];
-  int32_t orow[NB];
-  prologue<SIL_F32, 4, NQ, NB, METRIC>(
-      a, wrow0, lane, nrow, arow, orow, [&](int nb, int q, const float* v) __attribute__((always_inline)) {
+  prologue<SIL_F32, 4, NQ, NB, METRIC, 1>(
+      a, B, lane, nrow, arow, [&](int nb, int q, const float* v) __attribute__((always_inline)) {
         areg[nb][q] = f32x4_t{v[0], v[1], v[2], v[3]};
       });
 
-  int32_t dlab[NB][16];
   float mn[NB][16];
   int32_t arg[NB][16];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const int32_t o = __shfl(orow[nb], out_row(j, h), 64);
-      dlab[nb][j] = o >= 0 ? o - col : -1;
       mn[nb][j] = __builtin_inff();
       arg[nb][j] = -1;
     }
 
-  const float* bt = static_cast<const float*>(a.btab);
-  f32x4_t stg[CPT];
-  stage_load_f32<DP, CPT>(stg, bt, 0, tid);
-  stage_store_f32<DP, CPT, LROW>(stg, &lds_b[0][0], tid);
-  float cv_next = a.cvec[col];
-  __syncthreads();
-
-  for (int t = 0; t < a.ntiles; ++t) {
-    const int buf = t & 1;
-    const float cv = cv_next;
-    if (t + 1 < a.ntiles) {
-      stage_load_f32<DP, CPT>(stg, bt, t + 1, tid);
-      cv_next = a.cvec[32 * (t + 1) + col];
-    }
-    f32x16_t acc[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int j = 0; j < 16; ++j) acc[nb][j] = 0.0f;
+  auto bfrag = [&](const uint8_t* st, int cb, int q) __attribute__((always_inline)) {
+    return *reinterpret_cast<const f32x4_t*>(st + ((cb * 32 + col) * RS + 4 * (2 * q + h)) * 4);
+  };
+  auto gemm = [&](const uint8_t* st, int cb, f32x16_t (&acc)[NB], auto&& after_first_read)
+      __attribute__((always_inline)) {
+    f32x4_t bv[2];
+    bv[0] = bfrag(st, cb, 0);
+    after_first_read();
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const f32x4_t bv = *reinterpret_cast<const f32x4_t*>(&lds_b[buf][col * LROW + 4 * (2 * q + h)]);
+      if (q + 1 < NQ) bv[(q + 1) & 1] = bfrag(st, cb, q + 1);
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(areg[nb][q][e], bv[e], acc[nb], 0, 0, 0);
+          if (q == 0 && e == 0)
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(areg[nb][0][0], bv[0][0], f32x16_t{}, 0, 0, 0);
+          else
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(areg[nb][q][e], bv[q & 1][e], acc[nb], 0, 0, 0);
         }
     }
-    const int32_t t32 = 32 * t;
+  };
+  auto epi = [&](const f32x16_t (&acc)[NB], int blk) __attribute__((always_inline)) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        float v = fmaf(ALPHA, acc[nb][j], cv);
-        v = dlab[nb][j] == t32 ? __builtin_inff() : v;
-        if constexpr (SAVE) {
-          if (v < mn[nb][j]) {
-            mn[nb][j] = v;
-            arg[nb][j] = t32 + col;
-          }
-        } else {
-          mn[nb][j] = fminf(mn[nb][j], v);
-        }
-      }
-    if (t + 1 < a.ntiles) stage_store_f32<DP, CPT, LROW>(stg, &lds_b[buf ^ 1][0], tid);
-    __syncthreads();
-  }
+      tile_min<SAVE>(acc[nb], mn[nb], arg[nb], B.mixed[nb], blk == B.town[nb], col, B.cown[nb],
+                     32 * blk, lds_lab[wave] + nb * 32, h);
+  };
 
-  finish<NB, METRIC, SAVE>(a, wrow0, wave, lane, mn, arg, nrow, arow, orow, lds_min[wave],
-                           lds_arg[wave], lds_bsum);
+  f32x16_t acc0[NB], acc1[NB];
+  sweep<R>(static_cast<const char*>(a.btab), 0, a.ntiles, ring0, ring1, ring2, wave, lane,
+           [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
+    gemm(st, 0, acc0, prefetch);
+    if (t > 0) epi(acc1, 2 * t - 1);
+    gemm(st, 1, acc1, [] {});
+    epi(acc0, 2 * t);
+  });
+  epi(acc1, 2 * a.ntiles - 1);
+
+  __syncthreads();
+  finish<NB, METRIC, SAVE>(a, wb, B, wave, lane, mn, arg, nrow, arow, lds_min[wave], lds_arg[wave],
+                           lds_bsum);
 }
 
 }  // namespace sil
@@ -552,15 +731,15 @@ __global__ __launch_bounds__(256, DP >= 256 ? 1 : 2) void k_main_f32(MainArgs a)
 namespace sil {
 
 // Per-family launchers (one translation unit each, compiled in parallel).
-void launch_main_f32(const MainArgs& m, int DP, int metric, bool save, unsigned grid,
+void launch_main_f32(const MainArgs& m, int DPX, int metric, bool save, unsigned grid,
                      hipStream_t st);
-void launch_main_bf16(const MainArgs& m, int DP, int metric, int products, unsigned grid,
+void launch_main_bf16(const MainArgs& m, int DPX, int metric, int products, unsigned grid,
                       hipStream_t st);
-void launch_main_fp8(const MainArgs& m, int DP, int metric, int products, unsigned grid,
+void launch_main_fp8(const MainArgs& m, int DPX, int metric, int products, unsigned grid,
                      hipStream_t st);
 
 // Row blocks of 32 per wave for the bf16 family: two unless the split operands of three
-// products (or a 256-deep row) would not fit the register budget of two waves per SIMD.
-constexpr int bf16_nb(int DP, int P) { return (P == 3 || DP > 128) ? 1 : 2; }
+// products (or a deep row) would not fit the register budget of two waves per SIMD.
+constexpr int bf16_nb(int DPX, int P) { return (P == 3 || DPX > 80) ? 1 : 2; }
 
 }  // namespace sil

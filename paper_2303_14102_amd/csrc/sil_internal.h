@@ -15,7 +15,7 @@ namespace sil {
 
 constexpr int kMaxD = 256;
 constexpr int kMaxK = 65536;
-constexpr int kColTile = 32;        // MFMA output columns per tile (one 32x32 block)
+constexpr int kColTile = 64;        // clusters per LDS tile of the fused kernel (two 32x32 blocks)
 constexpr int kSegLen = 4096;       // sorted positions per wave in the statistics reduction
 constexpr int kChunk = 16384;       // labels per workgroup in the histogram / scatter passes
 constexpr int kLdsHistMaxK = 16384; // histogram bins kept in LDS (int32)
@@ -24,12 +24,25 @@ constexpr int kMainWaves = 4;       // waves per workgroup in the fused GEMM+epi
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
-// D rounded up to the GEMM depth the MFMA kernels are instantiated for: 16, 32, 64, 128, 256.
-__host__ __device__ inline int padded_depth(int D) {
-  int p = 16;
-  while (p < D) p *= 2;
-  return p;
+// GEMM depth of the fused kernels: the D coordinates plus the slots that carry the per-cluster
+// constant (three bf16 pieces, or one fp32), rounded up to an instantiated depth.
+constexpr int kDepthsBf16[] = {16, 32, 48, 80, 144, 272};
+constexpr int kDepthsF32[] = {16, 24, 40, 72, 136, 264};
+inline int gemm_depth(int D, int dtype) {
+  if (dtype == SIL_F32) {
+    for (int v : kDepthsF32)
+      if (D + 1 <= v) return v;
+  } else {
+    for (int v : kDepthsBf16)
+      if (D + 3 <= v) return v;
+  }
+  return 0;
 }
+
+// Row stride of the GEMM table in elements: DPX plus one 16-byte chunk, so that a row spans an
+// odd number of 16-byte chunks and the 16 lanes of one LDS read phase hit 16 different bank
+// groups.  (Every instantiated DPX spans an even number of chunks.)
+constexpr int table_stride(int DPX, int dtype) { return dtype == SIL_F32 ? DPX + 4 : DPX + 8; }
 
 // ------------------------------------------------------------------------------------------
 // workspace layout (byte offsets from the workspace base; every region 256-byte aligned)
@@ -43,21 +56,23 @@ struct WsLayout {
   size_t psi;      // f64[K]         Psi_k
   size_t segpart;  // f64[nseg*2*(D+1)] partial sums of runs cut by segment borders
   size_t perm;     // int32[N]       row ids sorted by label
-  size_t gmean;    // f64[DP]        global mean (centring)
-  size_t mvec;     // f32[DP]        global mean as float (centring)
-  size_t btab;     // GEMM operand: f32[Kpad*DP] or bf16[2][Kpad*DP] (hi, lo)
-  size_t cvec;     // f32[Kpad]      per-cluster constant of the b-path (+inf if empty/pad)
-  size_t atab;     // f32[K*DP]      cluster means (centred) for the a-path
+  size_t lsorted;  // int32[N]       labels in sorted order
+  size_t gmean;    // f64[DPX]       global mean (centring)
+  size_t mvec;     // f32[DPX]       global mean as float (centring)
+  size_t btab;     // GEMM operand: f32[Kpad*RS] or bf16[2][Kpad*RS] (hi, lo), RS the row stride:
+                   //   row k = [alpha mu'_k (D), c_k (1 fp32 or 3 bf16 pieces), 0 ...]
+  size_t atab;     // f32[K*DPX]     cluster means (centred) for the a-path
   size_t avec;     // f32[K]         sigma_k^2 (sq. Euclidean) or 1-||mu_k||^2 (cosine)
   size_t ascale;   // f32[K]         N_k/(N_k-1), 0 for singletons
   size_t bpart;    // f64[nblocks]   per-workgroup sums of s_i
+  size_t bpart2;   // f64[1024]      first-stage sums of bpart
   size_t save_a;   // f32[N]         a_i            (SIL_FLAG_SAVE_FOR_GRAD)
   size_t save_b;   // f32[N]         b_i
   size_t save_n;   // int32[N]       neighbouring cluster id
   size_t total;
   // shape
   int64_t N;
-  int32_t D, DP, K, Kpad;
+  int32_t D, DPX, K, Kpad;
   int64_t nseg, nblocks;
   int dtype, metric, flags;
 };
@@ -75,14 +90,15 @@ struct WsPtrs {
   double* psi;
   double* segpart;
   int32_t* perm;
+  int32_t* lsorted;
   double* gmean;
   float* mvec;
   void* btab;
-  float* cvec;
   float* atab;
   float* avec;
   float* ascale;
   double* bpart;
+  double* bpart2;
   float* save_a;
   float* save_b;
   int32_t* save_n;
@@ -101,7 +117,7 @@ struct Problem {
   const float* col_scale;
   const int32_t* labels;
   int64_t N;
-  int32_t D, DP, K, Kpad;
+  int32_t D, DPX, K, Kpad;
   int dtype, metric, products, flags;
   float* s;
   double* S;
@@ -120,6 +136,6 @@ hipError_t launch_copy_stats(const Problem& p, const WsLayout& L, const WsPtrs& 
                              double* V, double* psi, hipStream_t st);
 
 // rows per workgroup of the fused kernel for this problem (host and workspace sizing)
-int main_rows_per_block(int dtype, int DP, int products);
+int main_rows_per_block(int dtype, int DPX, int products);
 
 }  // namespace sil

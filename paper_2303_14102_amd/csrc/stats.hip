@@ -42,16 +42,18 @@ __device__ __forceinline__ float e4m3_to_f32(uint8_t q) {
   return __uint_as_float(sign | ((e + 120u) << 23) | (m << 20));
 }
 
+// Stored element as double; the fp8 code times its column scale is exact in binary64.
 template <int DT>
-__device__ __forceinline__ float load_elem(const void* X, const float* col_scale, int64_t row,
-                                           int32_t D, int32_t col) {
+__device__ __forceinline__ double load_elem(const void* X, const float* col_scale, int64_t row,
+                                            int32_t D, int32_t col) {
   const int64_t idx = row * static_cast<int64_t>(D) + col;
   if constexpr (DT == SIL_F32) {
-    return static_cast<const float*>(X)[idx];
+    return static_cast<double>(static_cast<const float*>(X)[idx]);
   } else if constexpr (DT == SIL_BF16) {
-    return bf16_bits_to_f32(static_cast<const uint16_t*>(X)[idx]);
+    return static_cast<double>(bf16_bits_to_f32(static_cast<const uint16_t*>(X)[idx]));
   } else {
-    return e4m3_to_f32(static_cast<const uint8_t*>(X)[idx]) * col_scale[col];
+    return static_cast<double>(e4m3_to_f32(static_cast<const uint8_t*>(X)[idx])) *
+           static_cast<double>(col_scale[col]);
   }
 }
 
@@ -141,7 +143,8 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count
 // Scatter row ids into their cluster's range of the sorted order.
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ labels, int64_t N,
                                                  int32_t K, int32_t* __restrict__ cursor,
-                                                 int32_t* __restrict__ perm) {
+                                                 int32_t* __restrict__ perm,
+                                                 int32_t* __restrict__ lsorted) {
   extern __shared__ int32_t sh[];
   const bool in_lds = K <= kLdsHistMaxK;
   const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kChunk;
@@ -160,12 +163,20 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ lab
     __syncthreads();
     for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
       const int32_t k = labels[i];
-      if (k >= 0 && k < K) perm[atomicAdd(&sh[k], 1)] = static_cast<int32_t>(i);
+      if (k >= 0 && k < K) {
+        const int32_t pos = atomicAdd(&sh[k], 1);
+        perm[pos] = static_cast<int32_t>(i);
+        lsorted[pos] = k;
+      }
     }
   } else {
     for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
       const int32_t k = labels[i];
-      if (k >= 0 && k < K) perm[atomicAdd(&cursor[k], 1)] = static_cast<int32_t>(i);
+      if (k >= 0 && k < K) {
+        const int32_t pos = atomicAdd(&cursor[k], 1);
+        perm[pos] = static_cast<int32_t>(i);
+        lsorted[pos] = k;
+      }
     }
   }
 }
@@ -247,9 +258,9 @@ __global__ __launch_bounds__(256) void k_segreduce(
       for (int e = 0; e < E; ++e) {
         const int col = lig * E + e;
         if (col < D) {
-          const float v = load_elem<DT>(X, col_scale, row, D, col);
+          const double v = load_elem<DT>(X, col_scale, row, D, col);
           bad_value |= !isfinite(v);
-          x[e] = static_cast<double>(v);
+          x[e] = v;
           sq = fma(x[e], x[e], sq);
         }
       }
@@ -274,6 +285,154 @@ __global__ __launch_bounds__(256) void k_segreduce(
       kc = find_cluster(offset, K, re);
       rs = offset[kc];
       re = offset[kc + 1];
+    }
+  }
+  flush();
+  if (bad_value) set_status(hdr, SIL_E_NONFINITE);
+  if (zero_norm) set_status(hdr, SIL_E_ZERO_NORM);
+}
+
+// Same reduction with 16-byte row chunks and U rows in flight per lane: a lane holds E = 16 /
+// sizeof(element) consecutive columns (fp32 4, bf16 8, fp8 16), a group of G = D / E lanes one
+// row (G a power of two <= 64), RPW = 64 / G rows per wave step, U steps per batch.  A batch
+// whose positions all lie in the current run takes the fast path; otherwise each step is
+// handled as in k_segreduce.
+typedef uint32_t u32x4_s __attribute__((ext_vector_type(4)));
+
+template <int DT>
+__device__ __forceinline__ void decode16(u32x4_s raw, const float* __restrict__ col_scale,
+                                         int c0, double* x) {
+  if constexpr (DT == SIL_F32) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) x[e] = static_cast<double>(__uint_as_float(raw[e]));
+  } else if constexpr (DT == SIL_BF16) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      x[2 * e] = static_cast<double>(__uint_as_float(raw[e] << 16));
+      x[2 * e + 1] = static_cast<double>(__uint_as_float(raw[e] & 0xffff0000u));
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      x[e] = static_cast<double>(e4m3_to_f32(static_cast<uint8_t>(raw[e >> 2] >> (8 * (e & 3))))) *
+             static_cast<double>(col_scale[c0 + e]);
+  }
+}
+
+template <int DT, int METRIC>
+__global__ __launch_bounds__(256) void k_segreduce_vec(
+    const void* __restrict__ X, const float* __restrict__ col_scale,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ offset, int32_t K, int32_t D,
+    int G, int64_t nseg, double* __restrict__ V, double* __restrict__ psi,
+    double* __restrict__ segpart, int32_t* __restrict__ hdr) {
+  constexpr int E = DT == SIL_F32 ? 4 : DT == SIL_BF16 ? 8 : 16;
+  constexpr int ESZ = 16 / E;
+  constexpr int U = DT == SIL_FP8_E4M3 ? 4 : 8;  // rows in flight per lane
+  const int lane = threadIdx.x & 63;
+  const int64_t seg = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (seg >= nseg) return;
+  const int64_t nvalid = hdr[1];
+  const int64_t p0 = seg * kSegLen;
+  const int64_t p1 = min(nvalid, p0 + static_cast<int64_t>(kSegLen));
+  if (p0 >= p1) return;
+  const int RPW = 64 / G;
+  const int g = lane / G, lig = lane % G;
+  const int c0 = lig * E;
+  const char* Xb = static_cast<const char*>(X);
+
+  int32_t kc = find_cluster(offset, K, p0);
+  int64_t rs = offset[kc], re = offset[kc + 1];
+  double acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = 0.0;
+  double accq = 0.0;
+  bool bad_value = false, zero_norm = false;
+
+  auto flush = [&]() __attribute__((always_inline)) {
+    for (int off = G; off < 64; off <<= 1)
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[e] += shfl_xor_f64(acc[e], off);
+    for (int off = 1; off < 64; off <<= 1) accq += shfl_xor_f64(accq, off);
+    double* dst;
+    double* dpsi;
+    if (rs >= p0 && re <= p1) {
+      dst = V + static_cast<int64_t>(kc) * D;
+      dpsi = psi + kc;
+    } else {
+      const int slot = rs <= p0 ? 0 : 1;
+      dst = segpart + (seg * 2 + slot) * static_cast<int64_t>(D + 1);
+      dpsi = dst + D;
+    }
+    if (g == 0)
+#pragma unroll
+      for (int e = 0; e < E; ++e) dst[c0 + e] = acc[e];
+    if (lane == 0) *dpsi = accq;
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = 0.0;
+    accq = 0.0;
+  };
+
+  // row -> E values (scaled to unit norm for cosine) and the row's sum of squares
+  auto prepare = [&](u32x4_s raw, bool valid, double* x, double& sq) __attribute__((always_inline)) {
+    decode16<DT>(raw, col_scale, c0, x);
+    sq = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      bad_value |= valid && !isfinite(x[e]);
+      sq = fma(x[e], x[e], sq);
+    }
+    if constexpr (METRIC == SIL_COSINE) {
+      double rowsq = sq;
+      for (int off = 1; off < G; off <<= 1) rowsq += shfl_xor_f64(rowsq, off);
+      if (valid && rowsq == 0.0) zero_norm = true;
+      const double inv = valid ? 1.0 / sqrt(rowsq) : 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) x[e] *= inv;
+    }
+  };
+
+  const int64_t batch = static_cast<int64_t>(U) * RPW;
+  for (int64_t p = p0; p < p1; p += batch) {
+    u32x4_s raw[U];
+    bool valid[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t pos = p + u * RPW + g;
+      valid[u] = pos < p1;
+      const int64_t row = valid[u] ? perm[pos] : 0;
+      raw[u] = valid[u] ? *reinterpret_cast<const u32x4_s*>(Xb + (row * D + c0) * ESZ)
+                        : u32x4_s{0u, 0u, 0u, 0u};
+    }
+    if (p + batch <= re && p + batch <= p1) {  // the whole batch belongs to the current run
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        double x[E], sq;
+        prepare(raw[u], true, x, sq);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] += x[e];
+        if constexpr (METRIC == SIL_SQEUCLID) accq += sq;
+      }
+      continue;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t pos = p + u * RPW + g;
+      double x[E], sq;
+      prepare(raw[u], valid[u], x, sq);
+      bool done = !valid[u];
+      while (true) {
+        if (!done && pos < re) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) acc[e] += x[e];
+          if constexpr (METRIC == SIL_SQEUCLID) accq += sq;
+          done = true;
+        }
+        if (__all(done)) break;
+        flush();
+        kc = find_cluster(offset, K, re);
+        rs = offset[kc];
+        re = offset[kc + 1];
+      }
     }
   }
   flush();
@@ -326,13 +485,25 @@ hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hi
   const size_t lds = p.K <= kLdsHistMaxK ? static_cast<size_t>(p.K) * 4 : 0;
   k_hist<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.count, w.hdr);
   k_scan<<<1, 1024, 0, st>>>(w.count, p.K, w.offset, w.cursor, w.hdr);
-  k_scatter<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.cursor, w.perm);
+  k_scatter<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.cursor, w.perm, w.lsorted);
+  const unsigned nblk = static_cast<unsigned>(ceil_div(L.nseg, 4));
+  // 16-byte chunks when a row splits into a power-of-two number of them
+  const int esz = p.dtype == SIL_F32 ? 4 : p.dtype == SIL_BF16 ? 2 : 1;
+  const int per16 = 16 / esz;
+  const int Gv = p.D % per16 == 0 ? p.D / per16 : 0;
+  const bool vec = Gv >= 1 && Gv <= 64 && (Gv & (Gv - 1)) == 0;
   int G, E;
   lanes_per_row(p.D, &G, &E);
-  const unsigned nblk = static_cast<unsigned>(ceil_div(L.nseg, 4));
-#define SIL_SEG(DT, MT)                                                                      \
-  k_segreduce<DT, MT><<<nblk, 256, 0, st>>>(p.X, p.col_scale, w.perm, w.offset, p.K, p.D, G, E, \
-                                            L.nseg, w.V, w.psi, w.segpart, w.hdr)
+#define SIL_SEG(DT, MT)                                                                         \
+  do {                                                                                          \
+    if (vec)                                                                                    \
+      k_segreduce_vec<DT, MT><<<nblk, 256, 0, st>>>(p.X, p.col_scale, w.perm, w.offset, p.K,    \
+                                                    p.D, Gv, L.nseg, w.V, w.psi, w.segpart,     \
+                                                    w.hdr);                                     \
+    else                                                                                        \
+      k_segreduce<DT, MT><<<nblk, 256, 0, st>>>(p.X, p.col_scale, w.perm, w.offset, p.K, p.D, G, \
+                                                E, L.nseg, w.V, w.psi, w.segpart, w.hdr);       \
+  } while (0)
   if (p.metric == SIL_SQEUCLID) {
     if (p.dtype == SIL_F32) SIL_SEG(SIL_F32, SIL_SQEUCLID);
     else if (p.dtype == SIL_BF16) SIL_SEG(SIL_BF16, SIL_SQEUCLID);
