@@ -61,7 +61,7 @@ enum {
    * exact for this distance (it is translation invariant) and is on by default. */
   SIL_FLAG_NO_CENTRE = 1 << 0,
   /* Keep a_i, b_i and the neighbouring cluster id of every point in the workspace, as the
-   * backward entry points need them. */
+   * backward entry points need them (fp32 storage only; SIL_E_DTYPE otherwise). */
   SIL_FLAG_SAVE_FOR_GRAD = 1 << 1
 };
 
@@ -100,6 +100,29 @@ int silhouette_sqeuclid(const void* X, int32_t dtype, const float* col_scale,
 int silhouette_cosine(const void* X, int32_t dtype, const float* col_scale, const int32_t* labels,
                       int64_t N, int32_t D, int32_t K, int32_t products, int32_t flags, float* s,
                       double* S, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Gradient dS/dX of the squared-Euclidean Silhouette with the labels held fixed (not in the
+ * paper; derived from Eq.11 by the chain rule through a_i, b_i and the cluster means):
+ *   gS   device, float64 [1]   upstream gradient dL/dS
+ *   dX   device, float32 [N, D] receives gS * dS/dX
+ * Requires X stored fp32 (SIL_E_DTYPE otherwise) and `ws` as left by a silhouette_sqeuclid call
+ * on the same X, labels, K and flags with SIL_FLAG_SAVE_FOR_GRAD set (the workspace sized with
+ * that flag); the call reuses its statistics, a_i, b_i and neighbour ids.  At a kink (a_i = b_i,
+ * or two clusters tying for b_i) it returns one subgradient: the branch a <= b of Eq.2 and the
+ * lowest tied cluster id.  Rows of a forward call that reported a device error get NaN.
+ * Other arguments as silhouette_sqeuclid.
+ */
+int silhouette_sqeuclid_backward(const void* X, int32_t dtype, const float* col_scale,
+                                 const int32_t* labels, int64_t N, int32_t D, int32_t K,
+                                 int32_t flags, const double* gS, float* dX, void* ws,
+                                 size_t ws_bytes, void* stream);
+
+/* The same for the cosine distance (derived from Eq.18); requires a silhouette_cosine forward. */
+int silhouette_cosine_backward(const void* X, int32_t dtype, const float* col_scale,
+                               const int32_t* labels, int64_t N, int32_t D, int32_t K,
+                               int32_t flags, const double* gS, float* dX, void* ws,
+                               size_t ws_bytes, void* stream);
 
 /*
  * Only the per-cluster statistics pass (one pass over X; Eq.5, Eq.6, Eq.8 for the squared

@@ -32,6 +32,8 @@ SIGNATURES = {
     "silhouette_cluster_stats": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
     "silhouette_status": (ctypes.c_int, [_P, _P]),
     "silhouette_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "silhouette_sqeuclid_backward": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "silhouette_cosine_backward": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "silhouette_profile_begin": (ctypes.c_int, [_I32]),
     "silhouette_profile_end": (ctypes.c_int, [_P, _P]),
 }

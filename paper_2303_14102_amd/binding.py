@@ -106,3 +106,48 @@ def cluster_stats(X: torch.Tensor, labels: torch.Tensor, K: int, metric: str = "
 def status(workspace: torch.Tensor) -> int:
     """First device-detected error of the last call on this workspace (waits for the stream)."""
     return L.load().silhouette_status(_ptr(workspace), _stream(workspace.device))
+
+
+def silhouette_backward(X: torch.Tensor, labels: torch.Tensor, K: int, metric: str,
+                        grad_S: torch.Tensor, workspace: torch.Tensor, *, centre: bool = True):
+    """gS * dS/dX (float32 [N, D]) from the workspace of a forward call made with
+    save_for_grad=True on the same inputs.  X must be float32."""
+    _check_inputs(X, labels, None)
+    if X.dtype != torch.float32:
+        raise TypeError("the backward needs X stored float32")
+    N, D = X.shape
+    flags = (0 if centre else L.SIL_FLAG_NO_CENTRE) | L.SIL_FLAG_SAVE_FOR_GRAD
+    gS = grad_S.to(device=X.device, dtype=torch.float64).reshape(()).contiguous()
+    dX = torch.empty_like(X)
+    fn = (L.load().silhouette_sqeuclid_backward if metric == "sqeuclid"
+          else L.load().silhouette_cosine_backward)
+    rc = fn(_ptr(X), L.SIL_F32, None, _ptr(labels), N, D, int(K), flags, _ptr(gS), _ptr(dX),
+            _ptr(workspace), workspace.numel(), _stream(X.device))
+    L.check(rc, f"silhouette_{metric}_backward")
+    return dX
+
+
+class SilhouetteFn(torch.autograd.Function):
+    """S = Silhouette(X, labels) as a differentiable function of X (labels held fixed).
+
+    Forward and backward both run in the HIP library; the workspace of the forward call (with
+    a_i, b_i and the neighbouring cluster of every point) is kept for the backward.
+    """
+
+    @staticmethod
+    def forward(ctx, X, labels, K, metric="sqeuclid", centre=True):
+        X = X.contiguous()
+        N, D = X.shape
+        flags = (0 if centre else L.SIL_FLAG_NO_CENTRE) | L.SIL_FLAG_SAVE_FOR_GRAD
+        ws = new_workspace(N, D, K, metric, X.dtype, flags, X.device)
+        _, S = silhouette(X, labels, K, metric, centre=centre, want_s=False, save_for_grad=True,
+                          workspace=ws)
+        ctx.save_for_backward(X, labels, ws)
+        ctx.K, ctx.metric, ctx.centre = K, metric, centre
+        return S
+
+    @staticmethod
+    def backward(ctx, grad_S):
+        X, labels, ws = ctx.saved_tensors
+        dX = silhouette_backward(X, labels, ctx.K, ctx.metric, grad_S, ws, centre=ctx.centre)
+        return dX, None, None, None, None

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsilhouette.so")
 SOURCES = ["main_f32.hip", "main_bf16.hip", "main_fp8.hip", "api.hip", "stats.hip",
-           "finalize.hip", "main.hip"]
+           "finalize.hip", "main.hip", "backward.hip"]
 ARCH = os.environ.get("SIL_OFFLOAD_ARCH", "gfx950")
 
 

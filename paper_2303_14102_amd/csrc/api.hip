@@ -47,6 +47,9 @@ WsLayout make_layout(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dt
   L.save_a = take(save ? static_cast<size_t>(N) * 4 : 0);
   L.save_b = take(save ? static_cast<size_t>(N) * 4 : 0);
   L.save_n = take(save ? static_cast<size_t>(N) * 4 : 0);
+  const size_t KW = static_cast<size_t>(K) * (D + 1);
+  L.gpart = take(save && bwd_fits_lds(K, D) ? static_cast<size_t>(bwd_accum_workgroups(N)) * KW * 8 : 0);
+  L.gAB = take(save ? KW * 8 : 0);
   L.total = o;
   return L;
 }
@@ -74,6 +77,8 @@ WsPtrs carve(const WsLayout& L, void* ws) {
   w.save_a = reinterpret_cast<float*>(b + L.save_a);
   w.save_b = reinterpret_cast<float*>(b + L.save_b);
   w.save_n = reinterpret_cast<int32_t*>(b + L.save_n);
+  w.gpart = reinterpret_cast<double*>(b + L.gpart);
+  w.gAB = reinterpret_cast<double*>(b + L.gAB);
   return w;
 }
 
@@ -135,6 +140,23 @@ static int forward(int32_t metric, const void* X, int32_t dtype, const float* co
   return SIL_OK;
 }
 
+static int backward(int32_t metric, const void* X, int32_t dtype, const float* col_scale,
+                    const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t flags,
+                    const double* gS, float* dX, void* ws, size_t ws_bytes, void* stream) {
+  WsLayout L;
+  flags |= SIL_FLAG_SAVE_FOR_GRAD;
+  int rc = check_common(X, dtype, col_scale, labels, N, D, K, metric, ws, ws_bytes, flags, &L);
+  if (rc) return rc;
+  if (dtype != SIL_F32) return SIL_E_DTYPE;
+  if (!gS || !dX) return SIL_E_ARG;
+  const WsPtrs w = carve(L, ws);
+  Problem p{X, col_scale, labels, N, D, L.DPX, K, L.Kpad, dtype, metric, 0, flags, nullptr,
+            nullptr, 0};
+  if (launch_backward(p, L, w, gS, dX, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return SIL_E_HIP;
+  return SIL_OK;
+}
+
 // 16-byte-or-less device-to-device copies of the statistics (kernels, so that the call stays
 // capturable and never touches the host)
 __global__ void k_copy_stats(const int32_t* __restrict__ cnt_in, const double* __restrict__ V_in,
@@ -184,6 +206,22 @@ int silhouette_cosine(const void* X, int32_t dtype, const float* col_scale, cons
                       double* S, void* ws, size_t ws_bytes, void* stream) {
   return forward(SIL_COSINE, X, dtype, col_scale, labels, N, D, K, products,
                  flags & ~SIL_FLAG_NO_CENTRE, s, S, ws, ws_bytes, stream);
+}
+
+int silhouette_sqeuclid_backward(const void* X, int32_t dtype, const float* col_scale,
+                                 const int32_t* labels, int64_t N, int32_t D, int32_t K,
+                                 int32_t flags, const double* gS, float* dX, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  return backward(SIL_SQEUCLID, X, dtype, col_scale, labels, N, D, K, flags, gS, dX, ws, ws_bytes,
+                  stream);
+}
+
+int silhouette_cosine_backward(const void* X, int32_t dtype, const float* col_scale,
+                               const int32_t* labels, int64_t N, int32_t D, int32_t K,
+                               int32_t flags, const double* gS, float* dX, void* ws,
+                               size_t ws_bytes, void* stream) {
+  return backward(SIL_COSINE, X, dtype, col_scale, labels, N, D, K, flags & ~SIL_FLAG_NO_CENTRE,
+                  gS, dX, ws, ws_bytes, stream);
 }
 
 int silhouette_cluster_stats(const void* X, int32_t dtype, const float* col_scale,

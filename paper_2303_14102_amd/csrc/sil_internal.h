@@ -69,6 +69,8 @@ struct WsLayout {
   size_t save_a;   // f32[N]         a_i            (SIL_FLAG_SAVE_FOR_GRAD)
   size_t save_b;   // f32[N]         b_i
   size_t save_n;   // int32[N]       neighbouring cluster id
+  size_t gpart;    // f64[nwg*K*(D+1)] backward: per-workgroup partial A_k, B_k
+  size_t gAB;      // f64[K*(D+1)]   backward: A_k (column D) and B_k
   size_t total;
   // shape
   int64_t N;
@@ -102,6 +104,8 @@ struct WsPtrs {
   float* save_a;
   float* save_b;
   int32_t* save_n;
+  double* gpart;
+  double* gAB;
 };
 
 WsPtrs carve(const WsLayout& L, void* ws);
@@ -137,5 +141,11 @@ hipError_t launch_copy_stats(const Problem& p, const WsLayout& L, const WsPtrs& 
 
 // rows per workgroup of the fused kernel for this problem (host and workspace sizing)
 int main_rows_per_block(int dtype, int DPX, int products);
+
+// backward (dS/dX) from the a_i, b_i, neighbour ids kept by a forward call
+hipError_t launch_backward(const Problem& p, const WsLayout& L, const WsPtrs& w, const double* gS,
+                           float* dX, hipStream_t st);
+int bwd_accum_workgroups(int64_t N);
+bool bwd_fits_lds(int32_t K, int32_t D);
 
 }  // namespace sil

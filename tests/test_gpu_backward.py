@@ -1,0 +1,112 @@
+"""dS/dX from the HIP backward (through the C ABI and the autograd Function) against the FP64
+oracle's gradient and against central finite differences of the oracle's S.
+
+Tolerance: relative L2 error <= 1e-4 over the compared entries (the gradient is formed in fp32
+from fp32 statistics; S itself is within 1e-6)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2303_14102_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_14102_amd import _lib
+    _lib.load()
+    return torch.device("cuda:0")
+
+
+def rel_l2(g, ref):
+    return float(np.linalg.norm(g - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def gpu_grad(dev, X, labels, K, metric):
+    from paper_2303_14102_amd import binding as sil
+    Xd = X.to(dev).requires_grad_(True)
+    S = sil.SilhouetteFn.apply(Xd, labels.to(dev), K, metric)
+    S.backward()
+    torch.cuda.synchronize()
+    return S.item(), Xd.grad.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("metric", ["sqeuclid", "cosine"])
+@pytest.mark.parametrize("n,d,k,single", [(2000, 16, 7, 1), (3001, 40, 33, 2), (4000, 256, 64, 0)])
+def test_gradient_vs_oracle(dev, metric, n, d, k, single):
+    b = wl.make_small(n, d, k, seed=31 + d, singletons=single, sigma=1.5)
+    print(f"[bwd] metric={metric} N={n} D={d} K={k}", flush=True)
+    S, g = gpu_grad(dev, b.X, b.labels, k, metric)
+    ref = oracle.gradient(b.X.numpy(), b.labels.numpy(), k, metric)
+    _, S_ref = oracle.silhouette(b.X.numpy(), b.labels.numpy(), k, metric)
+    err = rel_l2(g, ref)
+    print(f"  S={S:.9f} ref={S_ref:.9f} rel_l2(dX)={err:.2e}", flush=True)
+    assert abs(S - S_ref) <= 1e-6
+    assert err <= 1e-4
+
+
+def test_gradient_large_k_global_path(dev):
+    # K (D+1) FP64 values beyond the LDS budget: global-atomic accumulation
+    b = wl.make_small(6000, 128, 200, seed=41, sigma=1.0)
+    S, g = gpu_grad(dev, b.X, b.labels, 200, "sqeuclid")
+    ref = oracle.gradient(b.X.numpy(), b.labels.numpy(), 200, "sqeuclid")
+    assert rel_l2(g, ref) <= 1e-4
+
+
+@pytest.mark.parametrize("metric", ["sqeuclid", "cosine"])
+def test_gradient_vs_finite_differences(dev, metric):
+    # central differences (h = 1e-3) of the FP64 oracle's S on 64 sampled coordinates away from
+    # kinks (|a - b| not small), against the GPU gradient
+    b = wl.make_small(20_000, 32, 10, seed=5, sigma=1.5)
+    X = b.X.numpy().astype(np.float64)
+    lab = b.labels.numpy()
+    _, g = gpu_grad(dev, b.X, b.labels, 10, metric)
+    _, _, a, bb, _ = oracle.silhouette(X, lab, 10, metric, details=True)
+    ok = np.flatnonzero(np.abs(a - bb) > 0.2 * np.maximum(a, bb))
+    rng = np.random.default_rng(5)
+    rows = rng.choice(ok, size=64, replace=False)
+    cols = rng.integers(0, X.shape[1], size=64)
+    h = 1e-3
+    fd = np.empty(64)
+    for t, (i, l) in enumerate(zip(rows, cols)):
+        Xp, Xm = X.copy(), X.copy()
+        Xp[i, l] += h
+        Xm[i, l] -= h
+        fd[t] = (oracle.silhouette(Xp, lab, 10, metric)[1] - oracle.silhouette(Xm, lab, 10, metric)[1]) / (2 * h)
+    got = g[rows, cols]
+    err = rel_l2(got, fd)
+    print(f"  FD rel_l2={err:.2e} max|fd|={np.abs(fd).max():.3e}", flush=True)
+    assert err <= 1e-4
+
+
+def test_gradient_flows_through_autograd(dev):
+    # S as a loss inside a torch graph: d(3 S + 1)/dX = 3 dS/dX
+    from paper_2303_14102_amd import binding as sil
+    b = wl.make_small(1500, 8, 5, seed=9)
+    Xd = b.X.to(dev).requires_grad_(True)
+    (3.0 * sil.SilhouetteFn.apply(Xd, b.labels.to(dev), 5, "sqeuclid") + 1.0).backward()
+    ref = oracle.gradient(b.X.numpy(), b.labels.numpy(), 5, "sqeuclid")
+    assert rel_l2(Xd.grad.cpu().numpy().astype(np.float64), 3.0 * ref) <= 1e-4
+
+
+def test_gradient_full_size_workload(dev):
+    # the differentiation workload at its full size: N = 1e6 points, D = 256, K = 64
+    from paper_2303_14102_amd import binding as sil
+    spec = wl.WORKLOADS["blobs-1m-d256-k64"]
+    b = wl.make_blobs(spec, dev)
+    print(f"[bwd-full] {spec.name}", flush=True)
+    Xd = b.X.requires_grad_(True)
+    S = sil.SilhouetteFn.apply(Xd, b.labels, spec.k, "sqeuclid")
+    S.backward()
+    torch.cuda.synchronize()
+    g = Xd.grad.cpu().numpy().astype(np.float64)
+    Xh = b.X.detach().cpu().numpy()
+    ref = oracle.gradient(Xh, b.labels.cpu().numpy(), spec.k, "sqeuclid")
+    err = rel_l2(g, ref)
+    print(f"  rel_l2(dX)={err:.2e}", flush=True)
+    assert err <= 1e-4
