@@ -22,6 +22,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"bf16": 2.5e15, "fp32": 157.3e12, "hbm": 8.0e12}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ["paper_2303_14102_amd/csrc/main_kernels.h", "paper_2303_14102_amd/csrc/main_bf16.hip",
+                  "paper_2303_14102_amd/csrc/main_f32.hip", "paper_2303_14102_amd/csrc/stats.hip"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter summary, or None
+    when it is missing or the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    e = t.get("kernels", {}).get(f"{kernel}@{workload}")
+    return None if e is None else e.get("hbm_bytes_per_launch")
 
 
 def parse():
@@ -37,7 +63,9 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the fp32-form comparison")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check on sampled points")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
-    ap.add_argument("--cpu-sample", type=int, default=200_000)
+    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a plain 2 GiB device copy (reference for the traffic counters)")
     ap.add_argument("--n", type=int, default=0, help="override N (testing only)")
     ap.add_argument("--k", type=int, default=0, help="override K (testing only)")
     return ap.parse_args()
@@ -171,16 +199,27 @@ def main():
     t_main = phases[2] * 1e-3
     peak = PEAK["fp32"] if args.form == "f32" else PEAK["bf16"]
     prods = 1 if args.form == "f32" else args.products
+    kname = "k_main_bf16" if args.form != "f32" else "k_main_f32"
     out["roofline"] = {"bound": "mfma", "achieved": useful / t_main / 1e12, "peak": peak / 1e12,
-                       "unit": "TFLOP/s", "frac": useful / t_main / peak, "traffic": None,
-                       "kernel": "k_main_bf16" if args.form != "f32" else "k_main_f32",
+                       "unit": "TFLOP/s", "frac": useful / t_main / peak,
+                       "traffic": measured_traffic(kname, spec.name),
+                       "kernel": kname,
                        "issued_frac": useful * prods / t_main / peak,
                        "note": "achieved = 2*N*D*K useful flops / mean duration of the fused kernel; "
                                "issued_frac counts every split product"}
     stats_bytes = spec.n * spec.d * X.element_size() + 4 * spec.n
     out["stats_pass"] = {"bound": "hbm", "algorithmic_bytes": stats_bytes,
                          "achieved_GBps": stats_bytes / (phases[0] * 1e-3) / 1e9,
-                         "frac": stats_bytes / (phases[0] * 1e-3) / PEAK["hbm"]}
+                         "frac": stats_bytes / (phases[0] * 1e-3) / PEAK["hbm"],
+                         "traffic": measured_traffic("k_segreduce_vec", spec.name)}
+
+    if args.calibrate:
+        # a plain device copy of known size: the reference for the FETCH_SIZE / WRITE_SIZE counters
+        src = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     if not args.no_fp32 and args.form != "f32":
         ws32 = sil.new_workspace(spec.n, spec.d, spec.k, args.metric, torch.float32, 0, dev)

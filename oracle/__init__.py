@@ -59,9 +59,10 @@ def _load():
     lib.orc_scores_at.argtypes = common + [P, P, P, P, I64, P, P, P, P]
     lib.orc_silhouette.argtypes = common + [P, P, P, P, P]
     lib.orc_brute_silhouette.argtypes = common + [P, P]
+    lib.orc_brute_scores_at.argtypes = common + [P, I64, P, P, P]
     lib.orc_gradient.argtypes = common + [P]
     for f in ("orc_cluster_stats", "orc_scores_at", "orc_silhouette", "orc_brute_silhouette",
-              "orc_gradient", "orc_num_threads"):
+              "orc_brute_scores_at", "orc_gradient", "orc_num_threads"):
         getattr(lib, f).restype = ctypes.c_int
     lib.orc_decode_bf16.argtypes = [ctypes.c_uint16]
     lib.orc_decode_bf16.restype = ctypes.c_double
@@ -149,6 +150,18 @@ def brute_silhouette(X, labels, K, metric="sqeuclid", col_scale=None):
     _check(_load().orc_brute_silhouette(_ptr(X), dt, _ptr(cs), _ptr(labels), N, D, K, m, _ptr(s),
                                         _ptr(S)))
     return s, float(S[0])
+
+
+def brute_scores_at(X, labels, K, idx, metric="sqeuclid", col_scale=None):
+    """The quadratic definition for the points ``idx`` only (each against all N points), binary64:
+    (s, a, b) f64[len(idx)]."""
+    X, dt, cs, labels, N, D, K, m = _prep(X, labels, K, metric, col_scale)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    n = len(idx)
+    s, a, b = np.zeros(n), np.zeros(n), np.zeros(n)
+    _check(_load().orc_brute_scores_at(_ptr(X), dt, _ptr(cs), _ptr(labels), N, D, K, m, _ptr(idx), n,
+                                       _ptr(s), _ptr(a), _ptr(b)))
+    return s, a, b
 
 
 def gradient(X, labels, K, metric="sqeuclid", col_scale=None):

@@ -384,6 +384,108 @@ done:
   return rc;
 }
 
+/*
+ * The quadratic definition for listed points only: for each listed point i, its distance to
+ * every other point j (Section II, Definition; cosine distance as in Eq.12), summed per cluster,
+ * then a_i, b_i and s_i exactly as in orc_brute_silhouette.  Rows are decoded on the fly, so the
+ * cost is O(n_idx * N * D) time and O(threads * K) memory: this checks single points of
+ * workloads too large for the full quadratic form.  The sum over j is split into one contiguous
+ * range per thread and the per-thread sums are added in thread order.  a, b may be NULL.
+ */
+int orc_brute_scores_at(const void* X, int dtype, const float* col_scale, const int32_t* labels,
+                        int64_t N, int32_t D, int32_t K, int metric, const int64_t* idx,
+                        int64_t n_idx, double* s, double* a, double* b) {
+  int rc = orc_check_args(X, dtype, col_scale, labels, N, D, K, metric);
+  if (rc) return rc;
+  for (int64_t t = 0; t < n_idx; ++t)
+    if (idx[t] < 0 || idx[t] >= N) return ORC_E_ARG;
+  int64_t* count = (int64_t*)calloc((size_t)K, sizeof(int64_t));
+  if (!count) return ORC_E_NOMEM;
+  for (int64_t j = 0; j < N; ++j) {
+    if (labels[j] < 0 || labels[j] >= K) { free(count); return ORC_E_LABEL; }
+    count[labels[j]] += 1;
+  }
+  if (orc_nonempty(count, K) < 2) { free(count); return ORC_E_FEW_CLUSTERS; }
+  int nthr = 1;
+#ifdef _OPENMP
+  nthr = omp_get_max_threads();
+#endif
+  double* part = (double*)malloc(sizeof(double) * (size_t)nthr * (size_t)K);
+  double* xi = (double*)malloc(sizeof(double) * (size_t)D);
+  if (!part || !xi) { free(count); free(part); free(xi); return ORC_E_NOMEM; }
+  for (int64_t t = 0; t < n_idx && rc == ORC_OK; ++t) {
+    const int64_t i = idx[t];
+    orc_row(X, dtype, col_scale, i, D, xi);
+    double ni = 0.0;
+    for (int32_t l = 0; l < D; ++l) ni += xi[l] * xi[l];
+    if (!isfinite(ni)) { rc = ORC_E_NONFINITE; break; }
+    if (metric == ORC_COSINE && ni == 0.0) { rc = ORC_E_ZERO_NORM; break; }
+    int bad = ORC_OK;
+    memset(part, 0, sizeof(double) * (size_t)nthr * (size_t)K);
+#pragma omp parallel num_threads(nthr)
+    {
+      int tid = 0, nt = 1;
+#ifdef _OPENMP
+      tid = omp_get_thread_num();
+      nt = omp_get_num_threads();
+#endif
+      double* sum = part + (size_t)tid * (size_t)K;
+      double* xj = (double*)malloc(sizeof(double) * (size_t)D);
+      if (!xj) {
+#pragma omp atomic write
+        bad = ORC_E_NOMEM;
+      } else {
+        const int64_t lo = N * tid / nt, hi = N * (tid + 1) / nt;
+        for (int64_t j = lo; j < hi; ++j) {
+          if (j == i) continue;
+          orc_row(X, dtype, col_scale, j, D, xj);
+          double d = 0.0;
+          if (metric == ORC_SQEUCLID) {
+            for (int32_t l = 0; l < D; ++l) d += (xi[l] - xj[l]) * (xi[l] - xj[l]);
+          } else {
+            double dot = 0.0, nj = 0.0;
+            for (int32_t l = 0; l < D; ++l) {
+              dot += xi[l] * xj[l];
+              nj += xj[l] * xj[l];
+            }
+            if (nj == 0.0) {
+#pragma omp atomic write
+              bad = ORC_E_ZERO_NORM;
+            }
+            d = 1.0 - dot / (sqrt(ni) * sqrt(nj));
+          }
+          if (!isfinite(d)) {
+#pragma omp atomic write
+            bad = ORC_E_NONFINITE;
+          }
+          sum[labels[j]] += d;
+        }
+      }
+      free(xj);
+    }
+    if (bad) { rc = bad; break; }
+    for (int th = 1; th < nthr; ++th)
+      for (int32_t k = 0; k < K; ++k) part[k] += part[(size_t)th * (size_t)K + k];
+    const int32_t o = labels[i];
+    double si = 0.0, ai = 0.0, bi = 0.0;
+    if (count[o] >= 2) {
+      ai = part[o] / (double)(count[o] - 1);
+      bi = INFINITY;
+      for (int32_t k = 0; k < K; ++k)
+        if (k != o && count[k] > 0 && part[k] / (double)count[k] < bi) bi = part[k] / (double)count[k];
+      const double mx = ai > bi ? ai : bi;
+      si = mx > 0.0 ? (bi - ai) / mx : 0.0;
+    }
+    s[t] = si;
+    if (a) a[t] = ai;
+    if (b) b[t] = bi;
+  }
+  free(count);
+  free(part);
+  free(xi);
+  return rc;
+}
+
 /* ---------------------------------------------------------------------------------------- */
 /* gradient of S with respect to X (labels held fixed); not in the paper, derived from Eq.11  */
 /* and Eq.18                                                                                 */

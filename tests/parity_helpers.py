@@ -1,0 +1,92 @@
+"""Shared pieces of the GPU parity tests: the per-point error bound of the kernel's arithmetic
+and the storage conversions.
+
+Per-point bound: with the cross term x'.mu'_k carried to a relative accuracy eps (fp32
+accumulation over D terms, or the bf16 hi/lo split with 1, 2 or 3 products),
+|db_i| <= 2 eps ||x'_i|| max_k ||mu'_k|| plus fp32 rounding of ||x'_i||^2 + c_k; a_i comes from
+the difference form in fp32; then |ds_i| <= 2 (|da_i| + |db_i|) / max(a_i, b_i).
+"""
+
+import numpy as np
+import torch
+
+from paper_2303_14102_amd import workloads as wl
+
+TOL_S_MEAN = {"f32": 1e-6, "bf16": 1e-4, "fp8": 1e-4}
+U32 = 2.0 ** -24
+
+
+def cross_term_eps(form, products, metric, centre, D):
+    """Relative accuracy of the computed cross term x'.mu'_k."""
+    acc = U32 * (D + 8)                      # fp32 accumulation (MFMA or the epilogue)
+    if form == "f32":
+        return acc
+    exact_x = metric == "sqeuclid" and not centre  # bf16/fp8 storage is exact in bf16 uncentred
+    mu_split = 2.0 ** -16                    # hi + lo carries ~16 bits of the mean
+    if products == 3:
+        return 2.0 ** -16 + acc
+    if products == 2:
+        return (mu_split if exact_x else 2.0 ** -8) + acc
+    return 2.0 ** -8 + (0.0 if exact_x else 2.0 ** -8) + acc
+
+
+def bound_from_stats(form, products, metric, centre, rows, stats, a, b):
+    """Bound on |s_i(GPU) - s_i(oracle)| for the given rows (binary64 values as stored), from
+    binary64 cluster statistics (count, V, psi) of the whole data set."""
+    count, V, psi = stats
+    rows = np.asarray(rows, np.float64)
+    D = rows.shape[1]
+    cnt = np.asarray(count, np.float64)
+    ne = cnt > 0
+    mu = V[ne] / cnt[ne, None]
+    if metric == "sqeuclid":
+        m = V.sum(0) / cnt.sum() if centre else np.zeros(D)
+        xp = rows - m
+        mup = mu - m
+        var = psi[ne] / cnt[ne] - (mu * mu).sum(1)
+        cmax = ((mup * mup).sum(1) + var).max()
+    else:
+        xp = rows / np.linalg.norm(rows, axis=1, keepdims=True)
+        mup = mu
+        cmax = 1.0
+    nx = np.linalg.norm(xp, axis=1)
+    eps = cross_term_eps(form, products, metric, centre, D)
+    db = 2 * eps * nx * np.linalg.norm(mup, axis=1).max() + 4 * U32 * (nx ** 2 + cmax)
+    da = 4 * U32 * (D + 8) * (a + np.abs(a))
+    return 2 * (da + db) / np.maximum(np.maximum(a, b), 1e-30) + 4 * U32
+
+
+def plain_stats(X, labels, K, metric):
+    """count, V, psi of a small data set with numpy (for the bound only)."""
+    X = np.asarray(X, np.float64)
+    cnt = np.bincount(labels, minlength=K)
+    V = np.zeros((K, X.shape[1]))
+    np.add.at(V, labels, X if metric == "sqeuclid" else X / np.linalg.norm(X, axis=1, keepdims=True))
+    psi = np.zeros(K)
+    if metric == "sqeuclid":
+        np.add.at(psi, labels, (X * X).sum(1))
+    return cnt, V, psi
+
+
+def per_point_bound(form, products, metric, centre, Xh, labels, K, a, b):
+    """Per-point bound for every row of a small data set."""
+    return bound_from_stats(form, products, metric, centre, Xh, plain_stats(Xh, labels, K, metric), a, b)
+
+
+def dequantised(codes, col_scale):
+    if codes.dtype == np.uint16:
+        return (codes.astype(np.uint32) << 16).view(np.float32)
+    if codes.dtype == np.uint8:
+        return torch.from_numpy(np.ascontiguousarray(codes)).view(torch.float8_e4m3fn).float().numpy() * col_scale
+    return codes
+
+
+def storage(X32: torch.Tensor, form: str):
+    """(X on device in the given storage, col_scale or None, host codes for the oracle)."""
+    if form == "f32":
+        return X32, None, wl.host_codes(X32)
+    if form == "bf16":
+        q = wl.to_bf16(X32)
+        return q, None, wl.host_codes(q)
+    q, sc = wl.to_fp8_e4m3(X32)
+    return q, sc, wl.host_codes(q)

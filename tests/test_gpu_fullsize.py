@@ -1,0 +1,138 @@
+"""Parity at the full sizes of the named workloads, through the same C-ABI entry points and launch
+configuration the benchmark times.
+
+  - blobs-10m-d64-k100 (N = 1e7, D = 64, K = 100, Zipf sizes with 3 singleton clusters, fp32):
+    every s_i against the whole FP64 oracle, S within 1e-6, plus the quadratic definition on a
+    few sampled points;
+  - blobs-50m-d128-k1000 (N = 5e7, D = 128, K = 1000): bf16 (BF16x3), fp8 e4m3 and fp32 storage.
+    The whole oracle is too slow here, so: cluster statistics over all rows against the oracle's,
+    s_i on 256 sampled points against the oracle's linear form (FP64 statistics of all rows),
+    s_i on 4 of them against the quadratic definition over all 5e7 rows, and S against the
+    FP64 mean of the returned s_i (a property that holds at any size).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2303_14102_amd import workloads as wl
+from parity_helpers import TOL_S_MEAN, bound_from_stats, dequantised, per_point_bound
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_14102_amd import _lib
+    _lib.load()  # fails loudly when the library is missing
+    return torch.device("cuda:0")
+
+
+def check_brute(codes, lab_h, K, metric, cs, idx, s_gpu, s_lin):
+    """The quadratic definition over all rows, for a few sampled points."""
+    s_bf, _, _ = oracle.brute_scores_at(codes, lab_h, K, idx, metric, col_scale=cs)
+    print(f"  brute-force points {idx.tolist()}: max|s_lin - s_brute|={np.abs(s_lin - s_bf).max():.2e} "
+          f"max|s_gpu - s_brute|={np.abs(s_gpu - s_bf).max():.2e}", flush=True)
+    np.testing.assert_allclose(s_lin, s_bf, rtol=0, atol=1e-9)
+    return s_bf
+
+
+@pytest.mark.parametrize("metric", ["sqeuclid", "cosine"])
+def test_plain_fp32_at_scale(dev, metric):
+    from paper_2303_14102_amd import binding as sil
+    spec = wl.WORKLOADS["blobs-10m-d64-k100"]
+    print(f"[full] {spec.name} metric={metric} fp32", flush=True)
+    b = wl.make_blobs(spec, dev)
+    s, S = sil.silhouette(b.X, b.labels, spec.k, metric, check_status=True)
+    torch.cuda.synchronize()
+    Xh = b.X.cpu().numpy()
+    lab_h = b.labels.cpu().numpy()
+    del b
+    s = s.cpu().numpy().astype(np.float64)
+    s_ref, S_ref, a, bb, _ = oracle.silhouette(Xh, lab_h, spec.k, metric, details=True)
+    bound = per_point_bound("f32", 0, metric, True, Xh, lab_h, spec.k, a, bb)
+    worst = np.abs(s - s_ref) / bound
+    print(f"  S={S.item():.12f} ref={S_ref:.12f} |dS|={abs(S.item() - S_ref):.2e} "
+          f"max|ds|={np.abs(s - s_ref).max():.2e} max(|ds|/bound)={worst.max():.3f}", flush=True)
+    assert np.all(np.abs(s - s_ref) <= bound), f"point {int(worst.argmax())} exceeds its bound"
+    assert abs(S.item() - S_ref) <= TOL_S_MEAN["f32"]
+    # singleton clusters give s = 0 exactly
+    cnt = np.bincount(lab_h, minlength=spec.k)
+    single = np.flatnonzero(cnt[lab_h] == 1)
+    assert len(single) == spec.singletons and np.all(s[single] == 0.0)
+    idx = np.random.default_rng(21).choice(spec.n, size=4, replace=False)
+    check_brute(Xh, lab_h, spec.k, metric, None, idx, s[idx], s_ref[idx])
+
+
+@pytest.fixture(scope="module")
+def big(dev):
+    spec = wl.WORKLOADS["blobs-50m-d128-k1000"]
+    print(f"[full] generating {spec.name}", flush=True)
+    b = wl.make_blobs(spec, dev)
+    torch.cuda.synchronize()
+    return spec, b
+
+
+BIG_CASES = [("sqeuclid", "bf16", 3), ("cosine", "bf16", 3), ("sqeuclid", "fp8", 3), ("sqeuclid", "f32", 0)]
+
+
+@pytest.mark.parametrize("metric,form,products", BIG_CASES, ids=lambda v: str(v))
+def test_precision_forms_at_scale(dev, big, metric, form, products):
+    from paper_2303_14102_amd import binding as sil
+    spec, b = big
+    print(f"[full] {spec.name} metric={metric} form={form} products={products}", flush=True)
+    sc = None
+    if form == "bf16":
+        Xd = wl.to_bf16(b.X)
+    elif form == "fp8":
+        Xd, sc = wl.to_fp8_e4m3(b.X)
+    else:
+        Xd = b.X
+    s, S = sil.silhouette(Xd, b.labels, spec.k, metric, products=products, col_scale=sc,
+                          check_status=True)
+    count_g, V_g, psi_g = sil.cluster_stats(Xd, b.labels, spec.k, metric, col_scale=sc)
+    torch.cuda.synchronize()
+    codes = wl.host_codes(Xd)
+    if Xd is not b.X:
+        del Xd
+    lab_h = b.labels.cpu().numpy()
+    cs = None if sc is None else sc.cpu().numpy()
+    s = s.cpu().numpy().astype(np.float64)
+
+    # cluster statistics over all rows.  Both sides sum n_k terms in binary64 (in different
+    # orders); the worst-case bound of either sum is n_k u sum|terms| <= n_k^2 u max|term|.
+    stats = oracle.cluster_stats(codes, lab_h, spec.k, metric, col_scale=cs)
+    assert np.array_equal(count_g.cpu().numpy(), stats[0])
+    u = 2.0 ** -53
+    nk = stats[0].astype(np.float64)
+    xmax = 1.0 if metric == "cosine" else 1.1 * float(b.X.abs().max())
+    V_tol = 2 * u * nk[:, None] ** 2 * xmax
+    assert np.all(np.abs(V_g.cpu().numpy() - stats[1]) <= V_tol)
+    if metric == "sqeuclid":
+        assert np.all(np.abs(psi_g.cpu().numpy() - stats[2]) <= 2 * u * nk * stats[2])
+
+    # sampled points against the oracle's linear form
+    idx = np.random.default_rng(7).choice(spec.n, size=256, replace=False)
+    s_lin, a, bb, _ = oracle.scores_at(codes, lab_h, spec.k, idx, stats, metric, col_scale=cs)
+    rows = dequantised(codes[idx], cs)
+    bound = bound_from_stats(form, products, metric, True, rows, stats, a, bb)
+    ds = np.abs(s[idx] - s_lin)
+    print(f"  S={S.item():.12f} sampled max|ds|={ds.max():.2e} max(|ds|/bound)={(ds / bound).max():.3f}",
+          flush=True)
+    assert np.all(ds <= bound), f"sampled point {int(idx[(ds / bound).argmax()])} exceeds its bound"
+
+    # the quadratic definition on a few of them
+    check_brute(codes, lab_h, spec.k, metric, cs, idx[:4], s[idx[:4]], s_lin[:4])
+
+    # S is the mean of the returned s_i (FP64 reduction of the fp32 values)
+    assert abs(S.item() - s.sum() / spec.n) <= 1e-12
+    # against the fp32 form on the unrounded points: this difference is mostly the rounding of
+    # the input itself (not the kernel's error), bounded for bf16 storage; fp8 is reported only
+    if form != "f32":
+        S32 = sil.silhouette(b.X, b.labels, spec.k, metric, check_status=True)[1].item()
+        print(f"  |S - S(fp32 form)|={abs(S.item() - S32):.2e}", flush=True)
+        if form == "bf16":
+            assert abs(S.item() - S32) <= TOL_S_MEAN[form]

@@ -4,11 +4,7 @@ Tolerances:
   - cluster sizes: exact;  Y / Omega / Psi: relative 1e-12 (FP64 sums in another order);
   - S: |dS| <= 1e-6 for fp32 storage, <= 1e-4 for bf16 / fp8 storage (oracle on the dequantised
     input);
-  - s_i: the error bound of the kernel's arithmetic, per point (``per_point_bound``).  With the
-    cross term x'.mu'_k carried to a relative accuracy eps (fp32 accumulation over D terms, or
-    the bf16 hi/lo split with 1, 2 or 3 products), |db_i| <= 2 eps ||x'_i|| max_k ||mu'_k|| plus
-    fp32 rounding of ||x'_i||^2 + c_k; a_i comes from the difference form in fp32; then
-    |ds_i| <= 2 (|da_i| + |db_i|) / max(a_i, b_i).
+  - s_i: the error bound of the kernel's arithmetic, per point (parity_helpers.per_point_bound).
 """
 
 import math
@@ -19,61 +15,9 @@ import torch
 
 import oracle
 from paper_2303_14102_amd import workloads as wl
+from parity_helpers import TOL_S_MEAN, U32, dequantised, per_point_bound, storage  # noqa: F401
 
 pytestmark = pytest.mark.gpu
-
-TOL_S_MEAN = {"f32": 1e-6, "bf16": 1e-4, "fp8": 1e-4}
-U32 = 2.0 ** -24
-
-
-def cross_term_eps(form, products, metric, centre, D):
-    """Relative accuracy of the computed cross term x'.mu'_k."""
-    acc = U32 * (D + 8)                      # fp32 accumulation (MFMA or the epilogue)
-    if form == "f32":
-        return acc
-    exact_x = metric == "sqeuclid" and not centre  # bf16/fp8 storage is exact in bf16 uncentred
-    mu_split = 2.0 ** -16                    # hi + lo carries ~16 bits of the mean
-    if products == 3:
-        return 2.0 ** -16 + acc
-    if products == 2:
-        return (mu_split if exact_x else 2.0 ** -8) + acc
-    return 2.0 ** -8 + (0.0 if exact_x else 2.0 ** -8) + acc
-
-
-def per_point_bound(form, products, metric, centre, Xh, labels, K, a, b):
-    """Per-point bound on |s_i(GPU) - s_i(oracle)| (module docstring)."""
-    X = np.asarray(Xh, np.float64)
-    D = X.shape[1]
-    cnt = np.bincount(labels, minlength=K).astype(np.float64)
-    ne = cnt > 0
-    sums = np.zeros((K, D))
-    np.add.at(sums, labels, X if metric == "sqeuclid" else X / np.linalg.norm(X, axis=1, keepdims=True))
-    mu = sums[ne] / cnt[ne, None]
-    if metric == "sqeuclid":
-        m = X.mean(0) if centre else np.zeros(D)
-        xp = X - m
-        mup = mu - m
-        sq = np.zeros(K)
-        np.add.at(sq, labels, (X * X).sum(1))
-        var = sq[ne] / cnt[ne] - (mu * mu).sum(1)
-        cmax = ((mup * mup).sum(1) + var).max()
-    else:
-        xp = X / np.linalg.norm(X, axis=1, keepdims=True)
-        mup = mu
-        cmax = 1.0
-    nx = np.linalg.norm(xp, axis=1)
-    eps = cross_term_eps(form, products, metric, centre, D)
-    db = 2 * eps * nx * np.linalg.norm(mup, axis=1).max() + 4 * U32 * (nx ** 2 + cmax)
-    da = 4 * U32 * (D + 8) * (a + np.abs(a))
-    return 2 * (da + db) / np.maximum(np.maximum(a, b), 1e-30) + 4 * U32
-
-
-def dequantised(codes, col_scale):
-    if codes.dtype == np.uint16:
-        return (codes.astype(np.uint32) << 16).view(np.float32)
-    if codes.dtype == np.uint8:
-        return torch.from_numpy(codes).view(torch.float8_e4m3fn).float().numpy() * col_scale
-    return codes
 
 
 @pytest.fixture(scope="module")
@@ -83,17 +27,6 @@ def dev():
     from paper_2303_14102_amd import _lib
     _lib.load()  # fails loudly when the library is missing
     return torch.device("cuda:0")
-
-
-def storage(X32: torch.Tensor, form: str):
-    """(X on device in the given storage, col_scale or None, host codes for the oracle)."""
-    if form == "f32":
-        return X32, None, wl.host_codes(X32)
-    if form == "bf16":
-        q = wl.to_bf16(X32)
-        return q, None, wl.host_codes(q)
-    q, sc = wl.to_fp8_e4m3(X32)
-    return q, sc, wl.host_codes(q)
 
 
 def run_case(dev, X32, labels, K, metric, form, products=0, centre=True):

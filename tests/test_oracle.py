@@ -222,6 +222,24 @@ def test_scores_at_matches_full(case):
     np.testing.assert_array_equal(s2, s[idx])
 
 
+@pytest.mark.parametrize("metric", ["sqeuclid", "cosine"])
+def test_brute_scores_at_matches_sklearn(metric):
+    # the per-point quadratic definition (used on sampled points of large workloads) against the
+    # library routine on the same points, including a singleton cluster
+    sk = pytest.importorskip("sklearn.metrics")
+    b = wl.make_small(700, 6, 9, seed=5, singletons=1)
+    X, lab = b.X.numpy().astype(np.float64), b.labels.numpy()
+    idx = np.array([0, 3, 77, 350, 699, 3])
+    s, a, bb = oracle.brute_scores_at(X, lab, 9, idx, metric)
+    ref = sk.silhouette_samples(X, lab, metric=SK_METRIC[metric])
+    np.testing.assert_allclose(s, ref[idx], rtol=1e-12, atol=1e-13)
+    s_full, _ = oracle.brute_silhouette(X, lab, 9, metric)
+    np.testing.assert_allclose(s, s_full[idx], rtol=1e-12, atol=1e-13)
+    s_lin, a_lin, b_lin, _ = oracle.scores_at(X, lab, 9, idx, oracle.cluster_stats(X, lab, 9, metric), metric)
+    np.testing.assert_allclose(a, a_lin, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(s, s_lin, rtol=1e-9, atol=1e-12)
+
+
 def test_expanded_form_vs_centred_form_at_offset():
     # Eq.11 expanded versus the centred form ||x - mu_k||^2 + sigma_k^2 (exact algebra),
     # evaluated in binary64 on data far from the origin
