@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="blobs-50m-d128-k1000")
+    ap.add_argument("--workload", default="blobs-50m-d128-k1000",
+                    help="a named blob workload, or ksweep (the batched k-sweep, its own JSON line)")
     ap.add_argument("--metric", default="sqeuclid", choices=["sqeuclid", "cosine"])
     ap.add_argument("--form", default="bf16", choices=["bf16", "fp8", "f32"])
     ap.add_argument("--products", type=int, default=3)
@@ -115,6 +116,88 @@ def cpu_baseline(spec, X_host_codes, labels_host, metric, col_scale, n_sample):
                       f"oracle (statistics pass + every point), {dt:.1f} s"}
 
 
+def bench_ksweep(args):
+    """The batched k-sweep: 32 data sets x 8 labelings in one tuned plan, timed as hipGraph replays."""
+    import numpy as np
+    import torch
+
+    from paper_2303_14102_amd import BatchedSilhouette
+    from paper_2303_14102_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    log("generating the k-sweep workload (32 data sets x 8 labelings)")
+    t0 = time.perf_counter()
+    data = wl.make_ksweep(device=dev)
+    probs = [(ds.X, lab, k, args.metric) for ds in data for k, lab in ds.labelings]
+    torch.cuda.synchronize()
+    n_points = sum(p[0].shape[0] for p in probs)
+    log(f"{len(probs)} problems, {n_points} points, generated in {time.perf_counter() - t0:.1f} s")
+    batch = BatchedSilhouette(probs)
+    t_main = batch.tune()
+    cfg = batch.config()
+    log(f"tuned: persistent launch {t_main:.3f} ms, {cfg}")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    batch.capture(side)
+    for _ in range(args.warmup):
+        batch.replay(side)
+    side.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(side)
+    for _ in range(args.steps):
+        batch.replay(side)
+    e1.record(side)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    st = batch.status()
+    if any(st):
+        raise RuntimeError(f"device status {st}")
+    # roofline of the persistent kernel: useful flops, and the per-problem roofline time summed
+    flops = sum(2.0 * p[0].shape[0] * p[0].shape[1] * p[2] for p in probs)
+    roof_t = sum(max(2.0 * p[0].shape[0] * p[0].shape[1] * p[2] / PEAK["fp32"],
+                     (p[0].shape[0] * (4 * p[0].shape[1] + 12)) / PEAK["hbm"]) for p in probs)
+    out = {
+        "metric": "Silhouette points/s, batched k-sweep (256 labelings, one persistent launch)",
+        "value": n_points / (ms * 1e-3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ksweep-32x8", "problems": len(probs), "points": n_points,
+                   "metric": args.metric, "tuned": cfg, "replay": "hipGraph"},
+        "roofline": {"bound": "mfma", "achieved": flops / (t_main * 1e-3) / 1e12, "peak": PEAK["fp32"] / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / (t_main * 1e-3) / PEAK["fp32"], "traffic": None,
+                     "kernel": "k_main_f32_batched", "kernel_ms": t_main,
+                     "summed_problem_roofline_ms": roof_t * 1e3,
+                     "frac_of_summed_roofline": roof_t * 1e3 / t_main},
+    }
+    if not args.no_cpu:
+        import oracle
+        # the oracle on whole problems, in batch order, until about 15 s of CPU time
+        t0 = time.perf_counter()
+        done = 0
+        used = 0
+        for X, lab, k, metric in probs:
+            if time.perf_counter() - t0 > 15.0:
+                break
+            oracle.silhouette(X.cpu().numpy(), lab.cpu().numpy(), k, metric)
+            done += X.shape[0]
+            used += 1
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": done / dt, "unit": "points/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"the first {used} problems of the batch ({done} points), whole FP64 "
+                                         f"oracle each, {dt:.1f} s (includes the host copies)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -127,6 +210,8 @@ def main():
     from paper_2303_14102_amd import binding as sil
     from paper_2303_14102_amd import workloads as wl
 
+    if args.workload == "ksweep":
+        return bench_ksweep(args)
     dev = torch.device("cuda:0")
     spec = wl.WORKLOADS[args.workload]
     if args.n:

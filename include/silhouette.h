@@ -158,6 +158,101 @@ const char* silhouette_strerror(int status);
 int silhouette_profile_begin(int32_t max_calls);
 int silhouette_profile_end(float* ms_sum, int32_t* ncalls);
 
+/* ---------------------------------------------------------------------------------------------
+ * Batched evaluation (a k-sweep: many labelings of one or several data sets).
+ *
+ * Each problem is the forward above (Section II, Eq.11 / Eq.18) on its own X, labels and K.  A
+ * batch runs every problem's statistics, tables, fused GEMM+epilogue and reduction in a fixed
+ * number of launches whatever the number of problems; the fused GEMM+epilogue of all problems is
+ * one persistent launch whose workgroups take row blocks of any problem from a work queue.
+ * Results are those of the single-problem entry points on the same inputs (fp32 storage).
+ *
+ * Limits per problem: dtype SIL_F32 only (SIL_E_DTYPE otherwise), 1 <= N <= 2^31 - 1,
+ * 1 <= D <= 128, 2 <= K <= 16384; 1 <= count <= 1024 problems.
+ * -------------------------------------------------------------------------------------------*/
+typedef struct sil_problem {
+  const void* X;          /* device, [N, D] row-major, storage `dtype` */
+  const int32_t* labels;  /* device, int32 [N] in [0, K) */
+  int64_t N;
+  int32_t D;
+  int32_t K;
+  int32_t dtype;          /* sil_dtype: SIL_F32 */
+  int32_t metric;         /* sil_metric */
+  float* s;               /* device, float32 [N], or NULL */
+  double* S;              /* device, one float64 */
+} sil_problem;
+
+/* Opaque host object: the problems, the workspace layout, the launch configuration chosen by
+ * the tuner, and an optional captured hipGraph.  It owns host memory only (a pinned staging
+ * buffer for the descriptors it uploads) and the graph. */
+typedef struct sil_plan sil_plan;
+
+/*
+ * Validates `count` problem descriptors (host array, copied) and creates a plan on the current
+ * device.  flags: SIL_FLAG_NO_CENTRE or 0 (applies to the squared Euclidean problems).  On
+ * success *plan is set (free it with silhouette_batched_free); otherwise *plan is NULL and a
+ * sil_status is returned.
+ */
+int silhouette_batched_plan(const sil_problem* problems, int32_t count, int32_t flags,
+                            sil_plan** plan);
+
+/* Device workspace bytes for the plan (256-byte aligned buffer owned by the caller; 0 if plan is
+ * NULL).  Between calls the workspace belongs to the plan: it keeps the uploaded descriptors. */
+size_t silhouette_batched_workspace_bytes(const sil_plan* plan);
+
+/*
+ * Runs every problem, asynchronously on `stream`.  The first call with a given workspace (and
+ * the first after tuning) uploads the descriptors and waits for that copy; later calls only
+ * launch kernels.  Device-detected data errors are per problem: that problem's S (and s) become
+ * NaN and silhouette_batched_status reports it; the other problems are unaffected.
+ */
+int silhouette_batched_run(sil_plan* plan, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Autotuner: runs the batch once, then times the persistent launch (events on `stream`, which it
+ * synchronises) over the plan's own problems while it varies, one at a time, the rows per work
+ * item of the shallow GEMM depths (128 or 256), the persistent grid (1, 2 or 3 workgroups per
+ * CU), the items taken per queue access (1, 2, 4) and the queue order (costliest first, or
+ * problem order), keeping each change that is faster.  Ends with a run in the chosen
+ * configuration; *best_ms (host, may be NULL) receives the persistent launch's time.  Drops a
+ * captured graph.
+ */
+int silhouette_batched_tune(sil_plan* plan, void* ws, size_t ws_bytes, void* stream,
+                            float* best_ms);
+
+/* The chosen configuration into out[0..5] (host): workgroups of the persistent grid, items per
+ * queue access, queue order (0 costliest first, 1 problem order), and 32-row blocks per wave
+ * for GEMM depths 16, 24, 40.  len must be >= 6. */
+int silhouette_batched_config(const sil_plan* plan, int32_t* out, int32_t len);
+
+/* Sets the configuration from cfg[0..5] (host, same layout as silhouette_batched_config), for
+ * instance one saved from an earlier tuning: grid 1..65536, items per access 1..64, order 0 or 1,
+ * blocks per wave 1 or 2.  SIL_E_ARG for values out of range.  Drops a captured graph; the next
+ * run uploads the descriptors again. */
+int silhouette_batched_set_config(sil_plan* plan, const int32_t* cfg, int32_t len);
+
+/*
+ * Captures one run into a hipGraph held by the plan (replacing an earlier one).  `stream` must
+ * not be the legacy default stream (NULL): SIL_E_ARG.  The descriptors are uploaded before the
+ * capture; the graph contains kernels only.  The graph is bound to `ws`: replay it only while
+ * the same workspace and the same X, labels, s, S buffers stay valid.
+ */
+int silhouette_batched_capture(sil_plan* plan, void* ws, size_t ws_bytes, void* stream);
+
+/* Launches the captured graph on `stream` (SIL_E_ARG if nothing was captured). */
+int silhouette_batched_replay(sil_plan* plan, void* stream);
+
+/*
+ * Waits for `stream`, then writes each problem's first device-detected error (SIL_OK if none)
+ * into status[count] (host) and returns the first non-zero one (SIL_OK if none, SIL_E_HIP if a
+ * copy failed).
+ */
+int silhouette_batched_status(const sil_plan* plan, const void* ws, int32_t* status,
+                              void* stream);
+
+/* Releases the plan, its graph and its staging buffer (NULL is ignored). */
+void silhouette_batched_free(sil_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,7 +36,23 @@ SIGNATURES = {
     "silhouette_cosine_backward": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "silhouette_profile_begin": (ctypes.c_int, [_I32]),
     "silhouette_profile_end": (ctypes.c_int, [_P, _P]),
+    "silhouette_batched_plan": (ctypes.c_int, [_P, _I32, _I32, _P]),
+    "silhouette_batched_workspace_bytes": (_SZ, [_P]),
+    "silhouette_batched_run": (ctypes.c_int, [_P, _P, _SZ, _P]),
+    "silhouette_batched_tune": (ctypes.c_int, [_P, _P, _SZ, _P, _P]),
+    "silhouette_batched_config": (ctypes.c_int, [_P, _P, _I32]),
+    "silhouette_batched_set_config": (ctypes.c_int, [_P, _P, _I32]),
+    "silhouette_batched_capture": (ctypes.c_int, [_P, _P, _SZ, _P]),
+    "silhouette_batched_replay": (ctypes.c_int, [_P, _P]),
+    "silhouette_batched_status": (ctypes.c_int, [_P, _P, _P, _P]),
+    "silhouette_batched_free": (None, [_P]),
 }
+
+
+class SilProblem(ctypes.Structure):
+    """struct sil_problem of include/silhouette.h."""
+    _fields_ = [("X", _P), ("labels", _P), ("N", _I64), ("D", _I32), ("K", _I32), ("dtype", _I32),
+                ("metric", _I32), ("s", _P), ("S", _P)]
 
 
 class SilhouetteError(RuntimeError):

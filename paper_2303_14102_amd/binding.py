@@ -151,3 +151,96 @@ class SilhouetteFn(torch.autograd.Function):
         X, labels, ws = ctx.saved_tensors
         dX = silhouette_backward(X, labels, ctx.K, ctx.metric, grad_S, ws, centre=ctx.centre)
         return dX, None, None, None, None
+
+
+class BatchedSilhouette:
+    """Many problems (for instance the labelings of a k-sweep) evaluated together.
+
+    problems: a list of (X, labels, K, metric) with X float32 [N, D] (D <= 128) and labels int32
+    [N] on one GPU.  Results land in ``self.S`` (float64 [len(problems)]) and, with want_s,
+    ``self.s[i]`` (float32 [N_i]).  The workspace is allocated here once and owned by the plan.
+    """
+
+    def __init__(self, problems, *, want_s: bool = True, centre: bool = True):
+        if not problems:
+            raise ValueError("no problems")
+        dev = problems[0][0].device
+        self.device = dev
+        self.problems = problems
+        self.S = torch.full((len(problems),), float("nan"), dtype=torch.float64, device=dev)
+        self.s = []
+        arr = (L.SilProblem * len(problems))()
+        for i, (X, labels, K, metric) in enumerate(problems):
+            _check_inputs(X, labels, None)
+            if X.dtype != torch.float32:
+                raise TypeError("batched problems take float32 X")
+            s = torch.empty(X.shape[0], dtype=torch.float32, device=dev) if want_s else None
+            self.s.append(s)
+            arr[i] = L.SilProblem(X.data_ptr(), labels.data_ptr(), X.shape[0], X.shape[1], int(K),
+                                  L.SIL_F32, METRIC[metric], 0 if s is None else s.data_ptr(),
+                                  self.S.data_ptr() + 8 * i)
+        self._arr = arr
+        plan = ctypes.c_void_p()
+        lib = L.load()
+        flags = 0 if centre else L.SIL_FLAG_NO_CENTRE
+        L.check(lib.silhouette_batched_plan(arr, len(problems), flags, ctypes.byref(plan)),
+                "silhouette_batched_plan")
+        self._plan = plan
+        self.workspace = torch.empty(lib.silhouette_batched_workspace_bytes(plan), dtype=torch.uint8,
+                                     device=dev)
+
+    def _ws(self):
+        return _ptr(self.workspace), self.workspace.numel()
+
+    def run(self, stream: Optional[torch.cuda.Stream] = None):
+        st = ctypes.c_void_p((stream or torch.cuda.current_stream(self.device)).cuda_stream)
+        L.check(L.load().silhouette_batched_run(self._plan, *self._ws(), st), "silhouette_batched_run")
+        return self.S
+
+    def tune(self) -> float:
+        """Autotune the persistent launch on these problems; returns its time in ms."""
+        ms = ctypes.c_float()
+        L.check(L.load().silhouette_batched_tune(self._plan, *self._ws(), _stream(self.device),
+                                                 ctypes.byref(ms)), "silhouette_batched_tune")
+        return ms.value
+
+    def config(self) -> dict:
+        out = (ctypes.c_int32 * 6)()
+        L.check(L.load().silhouette_batched_config(self._plan, out, 6), "silhouette_batched_config")
+        return {"grid": out[0], "grab": out[1], "order": ("cost", "problem")[out[2]],
+                "rows_per_item": {16: 128 * out[3], 24: 128 * out[4], 40: 128 * out[5]}}
+
+    def set_config(self, grid: int, grab: int = 1, order: str = "cost", rows_per_item=None):
+        """Pin the launch configuration (rows_per_item: {16|24|40: 128 or 256})."""
+        rpi = {16: 128, 24: 128, 40: 128, **(rows_per_item or {})}
+        cfg = (ctypes.c_int32 * 6)(grid, grab, {"cost": 0, "problem": 1}[order], rpi[16] // 128,
+                                   rpi[24] // 128, rpi[40] // 128)
+        L.check(L.load().silhouette_batched_set_config(self._plan, cfg, 6), "silhouette_batched_set_config")
+
+    def capture(self, stream: torch.cuda.Stream):
+        """Capture one run into a hipGraph on `stream` (a non-default stream)."""
+        L.check(L.load().silhouette_batched_capture(self._plan, *self._ws(),
+                                                    ctypes.c_void_p(stream.cuda_stream)),
+                "silhouette_batched_capture")
+
+    def replay(self, stream: Optional[torch.cuda.Stream] = None):
+        st = ctypes.c_void_p((stream or torch.cuda.current_stream(self.device)).cuda_stream)
+        L.check(L.load().silhouette_batched_replay(self._plan, st), "silhouette_batched_replay")
+        return self.S
+
+    def status(self):
+        """Per-problem device status (list of sil_status codes); waits for the current stream."""
+        out = (ctypes.c_int32 * len(self.problems))()
+        L.load().silhouette_batched_status(self._plan, _ptr(self.workspace), out, _stream(self.device))
+        return list(out)
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            L.load().silhouette_batched_free(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

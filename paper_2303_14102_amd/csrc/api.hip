@@ -109,7 +109,8 @@ struct Profile {
 static Profile g_prof;
 
 static void prof_record(int call, int point, hipStream_t st) {
-  if (g_prof.on && call >= 0) hipEventRecord(g_prof.ev[call * 5 + point], st);
+  // a failed record surfaces in silhouette_profile_end (elapsed time of that event)
+  if (g_prof.on && call >= 0) (void)hipEventRecord(g_prof.ev[call * 5 + point], st);
 }
 
 static int forward(int32_t metric, const void* X, int32_t dtype, const float* col_scale,
@@ -242,7 +243,7 @@ int silhouette_cluster_stats(const void* X, int32_t dtype, const float* col_scal
 int silhouette_profile_begin(int32_t max_calls) {
   if (max_calls < 1 || max_calls > 4096) return SIL_E_ARG;
   if (g_prof.cap < max_calls) {
-    for (int i = 0; i < g_prof.cap * 5; ++i) hipEventDestroy(g_prof.ev[i]);
+    for (int i = 0; i < g_prof.cap * 5; ++i) (void)hipEventDestroy(g_prof.ev[i]);
     delete[] g_prof.ev;
     g_prof.ev = new hipEvent_t[static_cast<size_t>(max_calls) * 5];
     for (int i = 0; i < max_calls * 5; ++i)

@@ -261,12 +261,16 @@ hipError_t launch_backward(const Problem& p, const WsLayout& L, const WsPtrs& w,
   if (lds) {
     const size_t shm = static_cast<size_t>(KW) * 8;
     if (p.metric == SIL_SQEUCLID) {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_accum<SIL_SQEUCLID>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm));
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_accum<SIL_SQEUCLID>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               static_cast<int>(shm));
+      if (e != hipSuccess) return e;
       kb_accum<SIL_SQEUCLID><<<nwg, 64 * kBwdWaves, shm, st>>>(a);
     } else {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_accum<SIL_COSINE>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm));
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_accum<SIL_COSINE>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               static_cast<int>(shm));
+      if (e != hipSuccess) return e;
       kb_accum<SIL_COSINE><<<nwg, 64 * kBwdWaves, shm, st>>>(a);
     }
     kb_reduce<<<static_cast<unsigned>(ceil_div(KW, 256)), 256, 0, st>>>(w.gpart, nwg, KW, w.gAB);

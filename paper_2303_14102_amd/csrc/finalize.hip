@@ -29,13 +29,11 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
 
 // Global mean (centring vector): one workgroup per column reduces the cluster sums in a fixed
 // order; zeros when not centring.
-__global__ __launch_bounds__(256) void k_gmean(const double* __restrict__ V,
-                                               const int32_t* __restrict__ hdr, int32_t K,
-                                               int32_t D, int32_t DP, int centre,
-                                               double* __restrict__ gmean,
-                                               float* __restrict__ mvec) {
+__device__ __forceinline__ void gmean_body(const double* __restrict__ V,
+                                           const int32_t* __restrict__ hdr, int32_t K, int32_t D,
+                                           int centre, double* __restrict__ gmean,
+                                           float* __restrict__ mvec, int l) {
   __shared__ double sh[256];
-  const int l = blockIdx.x;
   const int t = threadIdx.x;
   double m = 0.0;
   if (centre && l < D)
@@ -54,6 +52,13 @@ __global__ __launch_bounds__(256) void k_gmean(const double* __restrict__ V,
   }
 }
 
+__global__ __launch_bounds__(256) void k_gmean(const double* __restrict__ V,
+                                               const int32_t* __restrict__ hdr, int32_t K,
+                                               int32_t D, int centre, double* __restrict__ gmean,
+                                               float* __restrict__ mvec) {
+  gmean_body(V, hdr, K, D, centre, gmean, mvec, blockIdx.x);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -69,14 +74,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 constexpr double kEmptyC = 1.0e30;
 
 template <int METRIC, bool BF16TAB>
-__global__ __launch_bounds__(256) void k_finalize(
+__device__ __forceinline__ void finalize_body(
     const int32_t* __restrict__ count, const double* __restrict__ V,
     const double* __restrict__ psi, const double* __restrict__ gmean, int32_t K, int32_t Kpad,
     int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ atab,
-    float* __restrict__ avec, float* __restrict__ ascale) {
+    float* __restrict__ avec, float* __restrict__ ascale, int64_t bid) {
   constexpr double ALPHA = METRIC == SIL_SQEUCLID ? -2.0 : -1.0;
   const int lane = threadIdx.x & 63;
-  const int32_t k = static_cast<int32_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int32_t k = static_cast<int32_t>(bid) * 4 + (threadIdx.x >> 6);
   if (k >= Kpad) return;
   const int nrep = (RS + 63) / 64;
   float* bt32 = static_cast<float*>(btab);
@@ -139,10 +144,20 @@ __global__ __launch_bounds__(256) void k_finalize(
   }
 }
 
+template <int METRIC, bool BF16TAB>
+__global__ __launch_bounds__(256) void k_finalize(
+    const int32_t* __restrict__ count, const double* __restrict__ V,
+    const double* __restrict__ psi, const double* __restrict__ gmean, int32_t K, int32_t Kpad,
+    int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ atab,
+    float* __restrict__ avec, float* __restrict__ ascale) {
+  finalize_body<METRIC, BF16TAB>(count, V, psi, gmean, K, Kpad, D, DPX, RS, btab, atab, avec,
+                                 ascale, blockIdx.x);
+}
+
 hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
   const int centre = p.metric == SIL_SQEUCLID && !(p.flags & SIL_FLAG_NO_CENTRE);
-  k_gmean<<<static_cast<unsigned>(p.DPX), 256, 0, st>>>(w.V, w.hdr, p.K, p.D, p.DPX, centre,
-                                                        w.gmean, w.mvec);
+  k_gmean<<<static_cast<unsigned>(p.DPX), 256, 0, st>>>(w.V, w.hdr, p.K, p.D, centre, w.gmean,
+                                                        w.mvec);
   const unsigned nb = static_cast<unsigned>(ceil_div(p.Kpad, 4));
   const bool bf = p.dtype != SIL_F32;
 #define SIL_FIN(MT, BF)                                                                        \
@@ -158,6 +173,44 @@ hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w,
   }
 #undef SIL_FIN
   (void)L;
+  return hipGetLastError();
+}
+
+
+// ------------------------------------------------------------------------------------------
+// batched (fp32 tables; work item blockIdx.x of the phase, as in the batched statistics)
+
+__device__ __forceinline__ const BatchProblem& batch_item_fin(const BatchDev& b, int phase,
+                                                              int64_t* local) {
+  const int32_t* pre = b.prefix + phase * (b.n + 1);
+  const int32_t item = static_cast<int32_t>(blockIdx.x);
+  const int j = batch_locate(pre, b.n, item);
+  *local = item - pre[j];
+  return b.prob[j];
+}
+
+__global__ __launch_bounds__(256) void kb_gmean(BatchDev b) {
+  int64_t it;
+  const BatchProblem& q = batch_item_fin(b, BP_GMEAN, &it);
+  const int centre = q.metric == SIL_SQEUCLID && !(q.flags & SIL_FLAG_NO_CENTRE);
+  gmean_body(q.V, q.hdr, q.K, q.D, centre, q.gmean, q.mvec, static_cast<int>(it));
+}
+
+__global__ __launch_bounds__(256) void kb_fin(BatchDev b) {
+  int64_t it;
+  const BatchProblem& q = batch_item_fin(b, BP_FIN, &it);
+  const int32_t RS = table_stride(q.DPX, SIL_F32);
+  if (q.metric == SIL_SQEUCLID)
+    finalize_body<SIL_SQEUCLID, false>(q.count, q.V, q.psi, q.gmean, q.K, q.Kpad, q.D, q.DPX, RS,
+                                       q.btab, q.atab, q.avec, q.ascale, it);
+  else
+    finalize_body<SIL_COSINE, false>(q.count, q.V, q.psi, q.gmean, q.K, q.Kpad, q.D, q.DPX, RS,
+                                     q.btab, q.atab, q.avec, q.ascale, it);
+}
+
+hipError_t launch_finalize_batched(const BatchLaunch& b, hipStream_t st) {
+  kb_gmean<<<static_cast<unsigned>(b.items[BP_GMEAN]), 256, 0, st>>>(b.dev);
+  kb_fin<<<static_cast<unsigned>(b.items[BP_FIN]), 256, 0, st>>>(b.dev);
   return hipGetLastError();
 }
 

@@ -17,31 +17,46 @@ __device__ __forceinline__ double block_sum_1024(double v, double* sh) {
   return sh[0];
 }
 
-__global__ __launch_bounds__(1024) void k_reduce1(const double* __restrict__ bpart, int64_t nb,
-                                                  int64_t chunk, double* __restrict__ out) {
+__device__ __forceinline__ void reduce1_body(const double* __restrict__ bpart, int64_t nb,
+                                             int64_t chunk, double* __restrict__ out, int64_t bid) {
   __shared__ double sh[1024];
-  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t b0 = bid * chunk;
   const int64_t b1 = min(nb, b0 + chunk);
   double v = 0.0;
   for (int64_t i = b0 + threadIdx.x; i < b1; i += 1024) v += bpart[i];
   const double tot = block_sum_1024(v, sh);
-  if (threadIdx.x == 0) out[blockIdx.x] = tot;
+  if (threadIdx.x == 0) out[bid] = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_reduce2(const double* __restrict__ part, int n,
-                                                  int64_t N, const int32_t* __restrict__ hdr,
-                                                  double* __restrict__ S) {
+__global__ __launch_bounds__(1024) void k_reduce1(const double* __restrict__ bpart, int64_t nb,
+                                                  int64_t chunk, double* __restrict__ out) {
+  reduce1_body(bpart, nb, chunk, out, blockIdx.x);
+}
+
+__device__ __forceinline__ void reduce2_body(const double* __restrict__ part, int n, int64_t N,
+                                             const int32_t* __restrict__ hdr,
+                                             double* __restrict__ S) {
   __shared__ double sh[1024];
   const double v = static_cast<int>(threadIdx.x) < n ? part[threadIdx.x] : 0.0;
   const double tot = block_sum_1024(v, sh);
   if (threadIdx.x == 0) *S = hdr[0] != 0 ? __builtin_nan("") : tot / static_cast<double>(N);
 }
 
-__global__ void k_poison(const int32_t* __restrict__ hdr, float* __restrict__ s, int64_t N) {
+__global__ __launch_bounds__(1024) void k_reduce2(const double* __restrict__ part, int n,
+                                                  int64_t N, const int32_t* __restrict__ hdr,
+                                                  double* __restrict__ S) {
+  reduce2_body(part, n, N, hdr, S);
+}
+
+__device__ __forceinline__ void poison_body(const int32_t* __restrict__ hdr, float* __restrict__ s,
+                                            int64_t N, int64_t bid, int64_t nblk) {
   if (hdr[0] == 0) return;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride)
-    s[i] = __builtin_nanf("");
+  const int64_t stride = nblk * blockDim.x;
+  for (int64_t i = bid * blockDim.x + threadIdx.x; i < N; i += stride) s[i] = __builtin_nanf("");
+}
+
+__global__ void k_poison(const int32_t* __restrict__ hdr, float* __restrict__ s, int64_t N) {
+  poison_body(hdr, s, N, blockIdx.x, gridDim.x);
 }
 
 int main_rows_per_block(int dtype, int DPX, int products) {
@@ -83,13 +98,61 @@ hipError_t launch_main(const Problem& p, const WsLayout& L, const WsPtrs& w, hip
   return hipGetLastError();
 }
 
+void reduce_split(int64_t nblocks, int64_t* chunk, int32_t* n1) {
+  *chunk = ceil_div(nblocks, 1024) < 4096 ? 4096 : ceil_div(nblocks, 1024);
+  *n1 = static_cast<int32_t>(ceil_div(nblocks, *chunk));
+}
+
 hipError_t launch_reduce(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
   (void)L;
-  const int64_t chunk = ceil_div(p.nblocks, 1024) < 4096 ? 4096 : ceil_div(p.nblocks, 1024);
-  const int n1 = static_cast<int>(ceil_div(p.nblocks, chunk));
+  int64_t chunk;
+  int32_t n1;
+  reduce_split(p.nblocks, &chunk, &n1);
   k_reduce1<<<static_cast<unsigned>(n1), 1024, 0, st>>>(w.bpart, p.nblocks, chunk, w.bpart2);
   k_reduce2<<<1, 1024, 0, st>>>(w.bpart2, n1, p.N, w.hdr, p.S);
   if (p.s) k_poison<<<1024, 256, 0, st>>>(w.hdr, p.s, p.N);
+  return hipGetLastError();
+}
+
+
+// ------------------------------------------------------------------------------------------
+// batched reduction of S (work item blockIdx.x of the phase)
+
+__device__ __forceinline__ const BatchProblem& batch_item_red(const BatchDev& b, int phase,
+                                                              int64_t* local) {
+  const int32_t* pre = b.prefix + phase * (b.n + 1);
+  const int32_t item = static_cast<int32_t>(blockIdx.x);
+  const int j = batch_locate(pre, b.n, item);
+  *local = item - pre[j];
+  return b.prob[j];
+}
+
+__global__ __launch_bounds__(1024) void kb_red1(BatchDev b) {
+  int64_t it;
+  const BatchProblem& q = batch_item_red(b, BP_RED1, &it);
+  reduce1_body(q.bpart, q.nblocks, q.red_chunk, q.bpart2, it);
+}
+
+__global__ __launch_bounds__(1024) void kb_red2(BatchDev b) {
+  int64_t it;
+  const BatchProblem& q = batch_item_red(b, BP_RED2, &it);
+  reduce2_body(q.bpart2, q.red_n1, q.N, q.hdr, q.S);
+}
+
+__global__ __launch_bounds__(256) void kb_poison(BatchDev b) {
+  int64_t it;
+  const BatchProblem& q = batch_item_red(b, BP_POISON, &it);
+  if (!q.s) return;
+  const int64_t i0 = it * kPoisonPerItem;
+  const int64_t n = q.N - i0 < kPoisonPerItem ? q.N - i0 : kPoisonPerItem;
+  poison_body(q.hdr, q.s + i0, n, 0, 1);
+}
+
+hipError_t launch_reduce_batched(const BatchLaunch& b, hipStream_t st) {
+  kb_red1<<<static_cast<unsigned>(b.items[BP_RED1]), 1024, 0, st>>>(b.dev);
+  kb_red2<<<static_cast<unsigned>(b.items[BP_RED2]), 1024, 0, st>>>(b.dev);
+  if (b.items[BP_POISON] > 0)
+    kb_poison<<<static_cast<unsigned>(b.items[BP_POISON]), 256, 0, st>>>(b.dev);
   return hipGetLastError();
 }
 

@@ -1,0 +1,144 @@
+// Persistent fused GEMM + epilogue over a batch of problems (fp32 storage, D <= 128).
+//
+// One launch covers the row blocks of every problem.  A fixed grid of workgroups takes work
+// items from a queue (an integer counter in the workspace, advanced by `grab` items at a time);
+// item i of the queue is row block i - prefix[j] of problem order[j], where prefix is the
+// per-problem start of its items in queue order.  Every workgroup leaves the loop once the
+// counter passes the number of items, so the grid always drains.
+//
+// Each problem runs the same per-row-block body as the single-problem kernel, picked by its GEMM
+// depth, metric and rows per block.  The LDS is laid out for the deepest depth (136) with a
+// two-stage table ring, so that two workgroups fit one CU for every depth.  The queue position
+// of the next batch of items is fetched while the current batch is computed.
+#include "main_kernels.h"
+
+namespace sil {
+
+namespace {
+
+constexpr int kBatchDPXMax = 136;
+constexpr int kBatchRS = table_stride(kBatchDPXMax, SIL_F32);
+using RingMax = Ring<1, kBatchRS * 4, 2>;
+constexpr int kBatchNBMax = 2;
+
+// Values read back from LDS are the same in every lane; say so, so that the problem's fields are
+// fetched with scalar loads into scalar registers.
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ MainArgs batch_args(const BatchProblem& q) {
+  MainArgs a;
+  a.X = q.X;
+  a.col_scale = q.col_scale;
+  a.perm = q.perm;
+  a.lsorted = q.lsorted;
+  a.hdr = q.hdr;
+  a.N = q.N;
+  a.D = q.D;
+  a.K = q.K;
+  a.btab = q.btab;
+  a.piece = static_cast<int64_t>(q.Kpad) * table_stride(q.DPX, SIL_F32);
+  a.atab = q.atab;
+  a.avec = q.avec;
+  a.ascale = q.ascale;
+  a.mvec = q.mvec;
+  a.ntiles = q.Kpad / kColTile;
+  a.s = q.s;
+  a.bpart = q.bpart;
+  a.save_a = nullptr;
+  a.save_b = nullptr;
+  a.save_n = nullptr;
+  return a;
+}
+
+template <int METRIC>
+__device__ __forceinline__ void batch_body(const MainArgs& a, int DPX, int nb, int64_t wb,
+                                           int64_t nvalid, uint8_t* r0, uint8_t* r1,
+                                           float* lmin, int32_t* larg, int32_t* llab,
+                                           double* lbsum, int tid) {
+#define SIL_BODY(DP, NB)                                                                      \
+  main_f32_body<DP, NB, METRIC, false, 2>(a, wb, nvalid, r0, r1, r1, lmin, larg, llab, lbsum, tid)
+  switch (DPX) {
+    case 16:
+      if (nb == 2) SIL_BODY(16, 2);
+      else SIL_BODY(16, 1);
+      break;
+    case 24:
+      if (nb == 2) SIL_BODY(24, 2);
+      else SIL_BODY(24, 1);
+      break;
+    case 40:
+      if (nb == 2) SIL_BODY(40, 2);
+      else SIL_BODY(40, 1);
+      break;
+    case 72:
+      SIL_BODY(72, 1);
+      break;
+    default:
+      SIL_BODY(136, 1);
+      break;
+  }
+#undef SIL_BODY
+}
+
+__global__ __launch_bounds__(256, 2) void k_main_f32_batched(BatchDev b, int32_t total,
+                                                             int32_t grab) {
+  __shared__ __attribute__((aligned(16))) uint8_t ring0[RingMax::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t ring1[RingMax::STAGE_BYTES];
+  __shared__ float lds_min[kMainWaves * kBatchNBMax * 32];
+  __shared__ int32_t lds_arg[kMainWaves];
+  __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves * kBatchNBMax * 32];
+  __shared__ double lds_bsum[kMainWaves];
+  __shared__ int32_t pre[kBatchMaxProblems + 1];
+  __shared__ int32_t next_base;
+
+  const int n = b.n;
+  const int32_t* gpre = b.prefix + BP_MAIN * (n + 1);
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) pre[i] = gpre[i];
+  if (threadIdx.x == 0) next_base = atomicAdd(b.queue, grab);
+  __syncthreads();
+  int32_t base = uniform(next_base);
+  while (base < total) {
+    // fetch the next batch of items now; its value is needed only after this batch
+    int32_t nxt = 0;
+    if (threadIdx.x == 0) nxt = atomicAdd(b.queue, grab);
+    const int32_t end = base + grab < total ? base + grab : total;
+    for (int32_t it = base; it < end; ++it) {
+      const int j = uniform(batch_locate(pre, n, it));
+      const BatchProblem& q = b.prob[b.order[j]];
+      const MainArgs a = batch_args(q);
+      const int64_t wb = it - uniform(pre[j]);
+      const int64_t nvalid = q.hdr[1];
+      // an opaque copy of the thread index: keeps the body's lane-dependent addresses out of
+      // the loop (hoisting them would exceed the register budget)
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      if (q.metric == SIL_SQEUCLID)
+        batch_body<SIL_SQEUCLID>(a, q.DPX, q.nb, wb, nvalid, ring0, ring1, lds_min, lds_arg,
+                                 lds_lab, lds_bsum, tid);
+      else
+        batch_body<SIL_COSINE>(a, q.DPX, q.nb, wb, nvalid, ring0, ring1, lds_min, lds_arg,
+                               lds_lab, lds_bsum, tid);
+      // the body ends at a barrier on every path but the empty block's early exit
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) next_base = nxt;
+    __syncthreads();
+    base = uniform(next_base);
+    __syncthreads();  // next_base is rewritten by the next iteration
+  }
+}
+
+__global__ void k_queue_reset(int32_t* queue) {
+  if (threadIdx.x == 0) queue[0] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_main_batched(const BatchLaunch& b, hipStream_t st) {
+  k_queue_reset<<<1, 64, 0, st>>>(b.dev.queue);
+  k_main_f32_batched<<<static_cast<unsigned>(b.main_grid), 256, 0, st>>>(
+      b.dev, static_cast<int32_t>(b.items[BP_MAIN]), b.main_grab);
+  return hipGetLastError();
+}
+
+}  // namespace sil

@@ -418,7 +418,7 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Bloc
 // wave w moves 1 KB per instruction (lane l -> 16 bytes at LDS offset 16 l), IPW instructions
 // per wave and tile.
 
-template <int PIECES, int ROWBYTES>
+template <int PIECES, int ROWBYTES, int NS_MAX = 3>
 struct Ring {
   static constexpr int SLOTS_PER_PIECE = kColTile * ROWBYTES / 16;
   static constexpr int TOT = PIECES * SLOTS_PER_PIECE;  // 16-byte slots per tile
@@ -428,7 +428,7 @@ struct Ring {
   static constexpr int IPW_MIN = TOT / (64 * kMainWaves);
   static constexpr int STAGE_BYTES = TOT * 16;
   // three stages while two workgroups per CU still fit the 160 KB of LDS, else two
-  static constexpr int NSTAGE = 3 * STAGE_BYTES <= 52 * 1024 ? 3 : 2;
+  static constexpr int NSTAGE = NS_MAX >= 3 && 3 * STAGE_BYTES <= 52 * 1024 ? 3 : 2;
 };
 
 template <typename R>
@@ -637,23 +637,24 @@ __global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_bf16(MainArgs a
 // and B[col r][k(s,h)] with k(s,h) = 8(s/4) + 4h + s%4, so each lane's operands are whole
 // float4 chunks c = 2q + h.
 
-template <int DPX, int NB, int METRIC, bool SAVE>
-__global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_f32(MainArgs a) {
+// One row block (wb) of the fp32 kernel.  The LDS buffers come from the caller: ring0..2 the
+// table stages (ring2 unused with two stages), lds_min/lds_lab [kMainWaves][NB*32], lds_arg
+// [kMainWaves][SAVE ? NB*32 : 1], lds_bsum [kMainWaves].  NS_MAX caps the ring at two stages
+// where the caller provides only two.  tid is the thread's index in the workgroup; a caller
+// that runs the body in a loop passes it through an opaque copy, so that the lane-dependent
+// addresses are recomputed per block instead of being kept live across the loop.
+template <int DPX, int NB, int METRIC, bool SAVE, int NS_MAX>
+__device__ __forceinline__ void main_f32_body(const MainArgs& a, int64_t wb, int64_t nvalid,
+                                              uint8_t* ring0, uint8_t* ring1, uint8_t* ring2,
+                                              float* lds_min, int32_t* lds_arg, int32_t* lds_lab,
+                                              double* lds_bsum, int tid) {
   constexpr int NQ = DPX / 8;
   constexpr int RS = table_stride(DPX, SIL_F32);
-  using R = Ring<1, RS * 4>;
-  __shared__ __attribute__((aligned(16))) uint8_t ring0[R::STAGE_BYTES];
-  __shared__ __attribute__((aligned(16))) uint8_t ring1[R::STAGE_BYTES];
-  __shared__ __attribute__((aligned(16))) uint8_t ring2[R::NSTAGE == 3 ? R::STAGE_BYTES : 16];
-  __shared__ float lds_min[kMainWaves][NB * 32];
-  __shared__ int32_t lds_arg[kMainWaves][SAVE ? NB * 32 : 1];
-  __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves][NB * 32];
-  __shared__ double lds_bsum[kMainWaves];
+  using R = Ring<1, RS * 4, NS_MAX>;
+  constexpr int ARGW = SAVE ? NB * 32 : 1;
 
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wave = tid >> 6, lane = tid & 63;
   const int col = lane & 31, h = lane >> 5;
-  const int64_t nvalid = a.hdr[1];
-  const int64_t wb = blockIdx.x;
   const int64_t wg0 = wb * (kMainWaves * NB * 32);
   if (wg0 >= nvalid) {  // no valid position in this row block (uniform)
     if (tid == 0) a.bpart[wb] = 0.0;
@@ -662,8 +663,9 @@ __global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_f32(MainArgs a)
   // the first tiles' latency overlaps the prologue
   issue_first<R>(static_cast<const char*>(a.btab), 0, a.ntiles, ring0, ring1, wave, lane);
 
+  int32_t* lab_w = lds_lab + wave * NB * 32;
   Blocks<NB> B;
-  load_blocks<NB>(a, nvalid, wg0 + wave * NB * 32, lane, B, lds_lab[wave]);
+  load_blocks<NB>(a, nvalid, wg0 + wave * NB * 32, lane, B, lab_w);
 
   f32x4_t areg[NB][NQ];
   float nrow[NB], arow[NB];
@@ -708,7 +710,7 @@ __global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_f32(MainArgs a)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
       tile_min<SAVE>(acc[nb], mn[nb], arg[nb], B.mixed[nb], blk == B.town[nb], col, B.cown[nb],
-                     32 * blk, lds_lab[wave] + nb * 32, h);
+                     32 * blk, lab_w + nb * 32, h);
   };
 
   f32x16_t acc0[NB], acc1[NB];
@@ -722,8 +724,23 @@ __global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_f32(MainArgs a)
   epi(acc1, 2 * a.ntiles - 1);
 
   __syncthreads();
-  finish<NB, METRIC, SAVE>(a, wb, B, wave, lane, mn, arg, nrow, arow, lds_min[wave], lds_arg[wave],
-                           lds_bsum);
+  finish<NB, METRIC, SAVE>(a, wb, B, wave, lane, mn, arg, nrow, arow, lds_min + wave * NB * 32,
+                           lds_arg + wave * ARGW, lds_bsum);
+}
+
+template <int DPX, int NB, int METRIC, bool SAVE>
+__global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_f32(MainArgs a) {
+  constexpr int RS = table_stride(DPX, SIL_F32);
+  using R = Ring<1, RS * 4>;
+  __shared__ __attribute__((aligned(16))) uint8_t ring0[R::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t ring1[R::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t ring2[R::NSTAGE == 3 ? R::STAGE_BYTES : 16];
+  __shared__ float lds_min[kMainWaves * NB * 32];
+  __shared__ int32_t lds_arg[kMainWaves * (SAVE ? NB * 32 : 1)];
+  __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves * NB * 32];
+  __shared__ double lds_bsum[kMainWaves];
+  main_f32_body<DPX, NB, METRIC, SAVE, 3>(a, blockIdx.x, a.hdr[1], ring0, ring1, ring2, lds_min,
+                                          lds_arg, lds_lab, lds_bsum, threadIdx.x);
 }
 
 }  // namespace sil

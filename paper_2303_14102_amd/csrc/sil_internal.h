@@ -148,4 +148,102 @@ hipError_t launch_backward(const Problem& p, const WsLayout& L, const WsPtrs& w,
 int bwd_accum_workgroups(int64_t N);
 bool bwd_fits_lds(int32_t K, int32_t D);
 
+// ------------------------------------------------------------------------------------------
+// batched evaluation: many problems (labelings of one or several data sets) per launch
+
+constexpr int kBatchMaxProblems = 1024;
+constexpr int kBatchMaxD = 128;  // fp32 storage, GEMM depth <= 136
+
+// One problem of a batch as the kernels see it (device memory, written by the plan).
+struct BatchProblem {
+  const void* X;
+  const float* col_scale;
+  const int32_t* labels;
+  float* s;
+  double* S;
+  int64_t N;
+  int32_t D, DPX, K, Kpad;
+  int32_t dtype, metric, flags, nb;  // nb: 32-row blocks per wave of the fused kernel
+  int64_t nseg, nblocks, zero_words;
+  int32_t Gv;        // lanes per row of the 16-byte statistics reduction, 0 for the generic one
+  int32_t G, E;      // lanes per row and columns per lane of the generic reduction
+  int32_t red_n1;    // first-stage workgroups of the S reduction
+  int64_t red_chunk; // partials per first-stage workgroup
+  int32_t* hdr;
+  int32_t* count;
+  int32_t* offset;
+  int32_t* cursor;
+  double* V;
+  double* psi;
+  double* segpart;
+  int32_t* perm;
+  int32_t* lsorted;
+  double* gmean;
+  float* mvec;
+  void* btab;
+  float* atab;
+  float* avec;
+  float* ascale;
+  double* bpart;
+  double* bpart2;
+};
+
+// Phases of a batched run; each is one launch over the work items of every problem.
+enum BatchPhase {
+  BP_ZERO = 0,  // clear the per-problem counters and sums (4096 words per item)
+  BP_HIST,      // label histogram and scatter (kChunk labels per item)
+  BP_SCAN,      // cluster offsets (one item)
+  BP_SEG,       // segmented reduction (4 segments per item)
+  BP_COMBINE,   // runs across segments (256 (cluster, column) pairs per item)
+  BP_GMEAN,     // centring vector (one item per GEMM depth column)
+  BP_FIN,       // tables (4 clusters per item)
+  BP_MAIN,      // fused GEMM + epilogue (one 128*nb-row block per item), queue order
+  BP_RED1,      // first stage of the S reduction
+  BP_RED2,      // second stage (one item)
+  BP_POISON,    // NaN outputs of failed problems (65536 points per item)
+  BP_COUNT
+};
+constexpr int kZeroWordsPerItem = 4096;
+constexpr int kPoisonPerItem = 65536;
+
+struct BatchDev {
+  const BatchProblem* prob;  // [n]
+  const int32_t* prefix;     // [BP_COUNT][n + 1] first work item of each problem, per phase
+  const int32_t* order;      // [n] problem at each queue position of BP_MAIN
+  int32_t* queue;            // [64] work counter of the persistent kernel (word 0)
+  int32_t n;
+};
+
+// Work-item position -> (problem index into the phase's order, item within the problem).
+__device__ __forceinline__ int batch_locate(const int32_t* __restrict__ pre, int n, int32_t item) {
+  int lo = 0, hi = n;  // pre[lo] <= item < pre[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+struct BatchLaunch {
+  BatchDev dev;
+  int64_t items[BP_COUNT];  // total work items per phase
+  int32_t maxK;
+  int32_t main_grid;        // workgroups of the persistent kernel
+  int32_t main_grab;        // work items taken per queue access
+  int32_t metric_mask;      // bit m set when some problem uses metric m
+};
+
+// lanes per row of the statistics reduction: Gv for 16-byte chunks (0 when D does not split into
+// a power-of-two number of them), else G lanes of E columns each
+void stats_lanes(int32_t D, int32_t dtype, int32_t* Gv, int32_t* G, int32_t* E);
+hipError_t launch_stats_batched(const BatchLaunch& b, hipStream_t st);
+hipError_t launch_finalize_batched(const BatchLaunch& b, hipStream_t st);
+hipError_t launch_main_batched(const BatchLaunch& b, hipStream_t st);
+hipError_t launch_reduce_batched(const BatchLaunch& b, hipStream_t st);
+// first-stage split of the S reduction over nblocks partials
+void reduce_split(int64_t nblocks, int64_t* chunk, int32_t* n1);
+
 }  // namespace sil

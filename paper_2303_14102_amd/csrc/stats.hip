@@ -59,20 +59,22 @@ __device__ __forceinline__ double load_elem(const void* X, const float* col_scal
 
 // ------------------------------------------------------------------------------------------
 
+__device__ __forceinline__ void fill_zero_body(uint32_t* __restrict__ p, int64_t n_words,
+                                               int64_t bid, int64_t nblk) {
+  const int64_t stride = nblk * blockDim.x;
+  for (int64_t i = bid * blockDim.x + threadIdx.x; i < n_words; i += stride) p[i] = 0u;
+}
+
 __global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n_words) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n_words;
-       i += stride)
-    p[i] = 0u;
+  fill_zero_body(p, n_words, blockIdx.x, gridDim.x);
 }
 
 // Label histogram; labels outside [0, K) are skipped and reported.
-__global__ __launch_bounds__(256) void k_hist(const int32_t* __restrict__ labels, int64_t N,
-                                              int32_t K, int32_t* __restrict__ count,
-                                              int32_t* __restrict__ hdr) {
-  extern __shared__ int32_t sh[];
+__device__ __forceinline__ void hist_body(const int32_t* __restrict__ labels, int64_t N, int32_t K,
+                                          int32_t* __restrict__ count, int32_t* __restrict__ hdr,
+                                          int64_t bid, int32_t* sh) {
   const bool in_lds = K <= kLdsHistMaxK;
-  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kChunk;
+  const int64_t c0 = bid * kChunk;
   const int64_t c1 = min(N, c0 + static_cast<int64_t>(kChunk));
   if (in_lds) {
     for (int k = threadIdx.x; k < K; k += blockDim.x) sh[k] = 0;
@@ -98,12 +100,18 @@ __global__ __launch_bounds__(256) void k_hist(const int32_t* __restrict__ labels
   }
 }
 
+__global__ __launch_bounds__(256) void k_hist(const int32_t* __restrict__ labels, int64_t N,
+                                              int32_t K, int32_t* __restrict__ count,
+                                              int32_t* __restrict__ hdr) {
+  extern __shared__ int32_t sh_dyn[];
+  hist_body(labels, N, K, count, hdr, blockIdx.x, sh_dyn);
+}
+
 // Exclusive prefix of the cluster sizes, scatter cursors, number of valid points and of
 // non-empty clusters.  One workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count, int32_t K,
-                                               int32_t* __restrict__ offset,
-                                               int32_t* __restrict__ cursor,
-                                               int32_t* __restrict__ hdr) {
+__device__ __forceinline__ void scan_body(const int32_t* __restrict__ count, int32_t K,
+                                          int32_t* __restrict__ offset, int32_t* __restrict__ cursor,
+                                          int32_t* __restrict__ hdr) {
   __shared__ int32_t part[1024];
   __shared__ int32_t nz[1024];
   const int t = threadIdx.x;
@@ -140,14 +148,21 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count
   }
 }
 
+__global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count, int32_t K,
+                                               int32_t* __restrict__ offset,
+                                               int32_t* __restrict__ cursor,
+                                               int32_t* __restrict__ hdr) {
+  scan_body(count, K, offset, cursor, hdr);
+}
+
 // Scatter row ids into their cluster's range of the sorted order.
-__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ labels, int64_t N,
-                                                 int32_t K, int32_t* __restrict__ cursor,
-                                                 int32_t* __restrict__ perm,
-                                                 int32_t* __restrict__ lsorted) {
-  extern __shared__ int32_t sh[];
+__device__ __forceinline__ void scatter_body(const int32_t* __restrict__ labels, int64_t N,
+                                             int32_t K, int32_t* __restrict__ cursor,
+                                             int32_t* __restrict__ perm,
+                                             int32_t* __restrict__ lsorted, int64_t bid,
+                                             int32_t* sh) {
   const bool in_lds = K <= kLdsHistMaxK;
-  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kChunk;
+  const int64_t c0 = bid * kChunk;
   const int64_t c1 = min(N, c0 + static_cast<int64_t>(kChunk));
   if (in_lds) {
     for (int k = threadIdx.x; k < K; k += blockDim.x) sh[k] = 0;
@@ -181,6 +196,14 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ lab
   }
 }
 
+__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ labels, int64_t N,
+                                                 int32_t K, int32_t* __restrict__ cursor,
+                                                 int32_t* __restrict__ perm,
+                                                 int32_t* __restrict__ lsorted) {
+  extern __shared__ int32_t sh_dyn[];
+  scatter_body(labels, N, K, cursor, perm, lsorted, blockIdx.x, sh_dyn);
+}
+
 // Cluster whose sorted range contains position q (0 <= q < offset[K]): the largest k with
 // offset[k] <= q, which skips empty clusters.
 __device__ __forceinline__ int32_t find_cluster(const int32_t* __restrict__ offset, int32_t K,
@@ -203,13 +226,13 @@ __device__ __forceinline__ double shfl_xor_f64(double v, int m) {
 // One wave per segment of kSegLen sorted positions.  A group of G lanes handles one row at a
 // time (lane covers E consecutive columns), RPW = 64/G rows per step.
 template <int DT, int METRIC>
-__global__ __launch_bounds__(256) void k_segreduce(
+__device__ __forceinline__ void segreduce_body(
     const void* __restrict__ X, const float* __restrict__ col_scale,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ offset, int32_t K, int32_t D,
     int G, int E, int64_t nseg, double* __restrict__ V, double* __restrict__ psi,
-    double* __restrict__ segpart, int32_t* __restrict__ hdr) {
+    double* __restrict__ segpart, int32_t* __restrict__ hdr, int64_t bid) {
   const int lane = threadIdx.x & 63;
-  const int64_t seg = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int64_t seg = bid * 4 + (threadIdx.x >> 6);
   if (seg >= nseg) return;
   const int64_t nvalid = hdr[1];
   const int64_t p0 = seg * kSegLen;
@@ -292,6 +315,16 @@ __global__ __launch_bounds__(256) void k_segreduce(
   if (zero_norm) set_status(hdr, SIL_E_ZERO_NORM);
 }
 
+template <int DT, int METRIC>
+__global__ __launch_bounds__(256) void k_segreduce(
+    const void* __restrict__ X, const float* __restrict__ col_scale,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ offset, int32_t K, int32_t D,
+    int G, int E, int64_t nseg, double* __restrict__ V, double* __restrict__ psi,
+    double* __restrict__ segpart, int32_t* __restrict__ hdr) {
+  segreduce_body<DT, METRIC>(X, col_scale, perm, offset, K, D, G, E, nseg, V, psi, segpart, hdr,
+                             blockIdx.x);
+}
+
 // Same reduction with 16-byte row chunks and U rows in flight per lane: a lane holds E = 16 /
 // sizeof(element) consecutive columns (fp32 4, bf16 8, fp8 16), a group of G = D / E lanes one
 // row (G a power of two <= 64), RPW = 64 / G rows per wave step, U steps per batch.  A batch
@@ -320,16 +353,16 @@ __device__ __forceinline__ void decode16(u32x4_s raw, const float* __restrict__ 
 }
 
 template <int DT, int METRIC>
-__global__ __launch_bounds__(256) void k_segreduce_vec(
+__device__ __forceinline__ void segreduce_vec_body(
     const void* __restrict__ X, const float* __restrict__ col_scale,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ offset, int32_t K, int32_t D,
     int G, int64_t nseg, double* __restrict__ V, double* __restrict__ psi,
-    double* __restrict__ segpart, int32_t* __restrict__ hdr) {
+    double* __restrict__ segpart, int32_t* __restrict__ hdr, int64_t bid) {
   constexpr int E = DT == SIL_F32 ? 4 : DT == SIL_BF16 ? 8 : 16;
   constexpr int ESZ = 16 / E;
   constexpr int U = DT == SIL_FP8_E4M3 ? 4 : 8;  // rows in flight per lane
   const int lane = threadIdx.x & 63;
-  const int64_t seg = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int64_t seg = bid * 4 + (threadIdx.x >> 6);
   if (seg >= nseg) return;
   const int64_t nvalid = hdr[1];
   const int64_t p0 = seg * kSegLen;
@@ -440,13 +473,23 @@ __global__ __launch_bounds__(256) void k_segreduce_vec(
   if (zero_norm) set_status(hdr, SIL_E_ZERO_NORM);
 }
 
+template <int DT, int METRIC>
+__global__ __launch_bounds__(256) void k_segreduce_vec(
+    const void* __restrict__ X, const float* __restrict__ col_scale,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ offset, int32_t K, int32_t D,
+    int G, int64_t nseg, double* __restrict__ V, double* __restrict__ psi,
+    double* __restrict__ segpart, int32_t* __restrict__ hdr) {
+  segreduce_vec_body<DT, METRIC>(X, col_scale, perm, offset, K, D, G, nseg, V, psi, segpart, hdr,
+                                 blockIdx.x);
+}
+
 // Sums of clusters whose sorted range spans several segments.  One thread per (cluster,
 // column), column D being Psi.
-__global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ offset, int32_t K,
-                                                 int32_t D, const double* __restrict__ segpart,
-                                                 double* __restrict__ V,
-                                                 double* __restrict__ psi) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void combine_body(const int32_t* __restrict__ offset, int32_t K,
+                                             int32_t D, const double* __restrict__ segpart,
+                                             double* __restrict__ V, double* __restrict__ psi,
+                                             int64_t bid) {
+  const int64_t t = bid * blockDim.x + threadIdx.x;
   const int64_t W = D + 1;
   if (t >= static_cast<int64_t>(K) * W) return;
   const int32_t k = static_cast<int32_t>(t / W);
@@ -466,14 +509,14 @@ __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ off
     psi[k] = sum;
 }
 
-// ------------------------------------------------------------------------------------------
-
-static void lanes_per_row(int D, int* G, int* E) {
-  int g = 1;
-  while (g < D && g < 64) g <<= 1;
-  *G = g;
-  *E = static_cast<int>(ceil_div(D, g));
+__global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ offset, int32_t K,
+                                                 int32_t D, const double* __restrict__ segpart,
+                                                 double* __restrict__ V,
+                                                 double* __restrict__ psi) {
+  combine_body(offset, K, D, segpart, V, psi, blockIdx.x);
 }
+
+// ------------------------------------------------------------------------------------------
 
 hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
   // zero: header .. segpart are contiguous in the layout; zero [hdr, perm)
@@ -488,12 +531,9 @@ hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hi
   k_scatter<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.cursor, w.perm, w.lsorted);
   const unsigned nblk = static_cast<unsigned>(ceil_div(L.nseg, 4));
   // 16-byte chunks when a row splits into a power-of-two number of them
-  const int esz = p.dtype == SIL_F32 ? 4 : p.dtype == SIL_BF16 ? 2 : 1;
-  const int per16 = 16 / esz;
-  const int Gv = p.D % per16 == 0 ? p.D / per16 : 0;
-  const bool vec = Gv >= 1 && Gv <= 64 && (Gv & (Gv - 1)) == 0;
-  int G, E;
-  lanes_per_row(p.D, &G, &E);
+  int32_t Gv, G, E;
+  stats_lanes(p.D, p.dtype, &Gv, &G, &E);
+  const bool vec = Gv != 0;
 #define SIL_SEG(DT, MT)                                                                         \
   do {                                                                                          \
     if (vec)                                                                                    \
@@ -517,6 +557,98 @@ hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hi
   const int64_t nt = static_cast<int64_t>(p.K) * (p.D + 1);
   k_combine<<<static_cast<unsigned>(ceil_div(nt, 256)), 256, 0, st>>>(w.offset, p.K, p.D,
                                                                        w.segpart, w.V, w.psi);
+  return hipGetLastError();
+}
+
+
+// ------------------------------------------------------------------------------------------
+// batched statistics: every launch covers the work items of all problems of a batch; work item
+// blockIdx.x belongs to the problem whose range in the phase's prefix contains it
+
+__device__ __forceinline__ const BatchProblem& batch_item(const BatchDev& b, int phase,
+                                                          int64_t* local) {
+  const int32_t* pre = b.prefix + phase * (b.n + 1);
+  const int32_t item = static_cast<int32_t>(blockIdx.x);
+  const int j = batch_locate(pre, b.n, item);
+  *local = item - pre[j];
+  return b.prob[j];
+}
+
+__global__ __launch_bounds__(256) void kb_zero(BatchDev b) {
+  int64_t it;
+  const BatchProblem& q = batch_item(b, BP_ZERO, &it);
+  const int64_t w0 = it * kZeroWordsPerItem;
+  const int64_t n = q.zero_words - w0 < kZeroWordsPerItem ? q.zero_words - w0 : kZeroWordsPerItem;
+  fill_zero_body(reinterpret_cast<uint32_t*>(q.hdr) + w0, n, 0, 1);
+}
+
+__global__ __launch_bounds__(256) void kb_hist(BatchDev b) {
+  extern __shared__ int32_t sh_dyn[];
+  int64_t it;
+  const BatchProblem& q = batch_item(b, BP_HIST, &it);
+  hist_body(q.labels, q.N, q.K, q.count, q.hdr, it, sh_dyn);
+}
+
+__global__ __launch_bounds__(1024) void kb_scan(BatchDev b) {
+  int64_t it;
+  const BatchProblem& q = batch_item(b, BP_SCAN, &it);
+  scan_body(q.count, q.K, q.offset, q.cursor, q.hdr);
+}
+
+__global__ __launch_bounds__(256) void kb_scatter(BatchDev b) {
+  extern __shared__ int32_t sh_dyn[];
+  int64_t it;
+  const BatchProblem& q = batch_item(b, BP_HIST, &it);
+  scatter_body(q.labels, q.N, q.K, q.cursor, q.perm, q.lsorted, it, sh_dyn);
+}
+
+// fp32 storage only (the batched path's storage type)
+__global__ __launch_bounds__(256) void kb_seg(BatchDev b) {
+  int64_t it;
+  const BatchProblem& q = batch_item(b, BP_SEG, &it);
+  if (q.metric == SIL_SQEUCLID) {
+    if (q.Gv)
+      segreduce_vec_body<SIL_F32, SIL_SQEUCLID>(q.X, q.col_scale, q.perm, q.offset, q.K, q.D, q.Gv,
+                                                q.nseg, q.V, q.psi, q.segpart, q.hdr, it);
+    else
+      segreduce_body<SIL_F32, SIL_SQEUCLID>(q.X, q.col_scale, q.perm, q.offset, q.K, q.D, q.G, q.E,
+                                            q.nseg, q.V, q.psi, q.segpart, q.hdr, it);
+  } else {
+    if (q.Gv)
+      segreduce_vec_body<SIL_F32, SIL_COSINE>(q.X, q.col_scale, q.perm, q.offset, q.K, q.D, q.Gv,
+                                              q.nseg, q.V, q.psi, q.segpart, q.hdr, it);
+    else
+      segreduce_body<SIL_F32, SIL_COSINE>(q.X, q.col_scale, q.perm, q.offset, q.K, q.D, q.G, q.E,
+                                          q.nseg, q.V, q.psi, q.segpart, q.hdr, it);
+  }
+}
+
+__global__ __launch_bounds__(256) void kb_combine(BatchDev b) {
+  int64_t it;
+  const BatchProblem& q = batch_item(b, BP_COMBINE, &it);
+  combine_body(q.offset, q.K, q.D, q.segpart, q.V, q.psi, it);
+}
+
+// Lanes per row of the generic reduction for D columns (shared with the batch planner).
+void stats_lanes(int32_t D, int32_t dtype, int32_t* Gv, int32_t* G, int32_t* E) {
+  const int esz = dtype == SIL_F32 ? 4 : dtype == SIL_BF16 ? 2 : 1;
+  const int per16 = 16 / esz;
+  const int g = D % per16 == 0 ? D / per16 : 0;
+  *Gv = (g >= 1 && g <= 64 && (g & (g - 1)) == 0) ? g : 0;
+  int gg = 1;
+  while (gg < D && gg < 64) gg <<= 1;
+  *G = gg;
+  *E = static_cast<int32_t>(ceil_div(D, gg));
+}
+
+hipError_t launch_stats_batched(const BatchLaunch& b, hipStream_t st) {
+  const size_t lds = static_cast<size_t>(b.maxK) * 4;
+  kb_zero<<<static_cast<unsigned>(b.items[BP_ZERO]), 256, 0, st>>>(b.dev);
+  kb_hist<<<static_cast<unsigned>(b.items[BP_HIST]), 256, lds, st>>>(b.dev);
+  kb_scan<<<static_cast<unsigned>(b.items[BP_SCAN]), 1024, 0, st>>>(b.dev);
+  kb_scatter<<<static_cast<unsigned>(b.items[BP_HIST]), 256, lds, st>>>(b.dev);
+  kb_seg<<<static_cast<unsigned>(b.items[BP_SEG]), 256, 0, st>>>(b.dev);
+  kb_combine<<<static_cast<unsigned>(b.items[BP_COMBINE]), 256, 0, st>>>(b.dev);
   return hipGetLastError();
 }
 

@@ -202,6 +202,55 @@ def host_codes(X: torch.Tensor) -> np.ndarray:
     raise TypeError(X.dtype)
 
 
+# --------------------------------------------------------------------------------------------
+# k-sweep: several labelings of each of several data sets
+
+
+@dataclasses.dataclass
+class SweepDataset:
+    X: torch.Tensor                 # [N, D] float32 on the device
+    blob: np.ndarray                # true blob id of every row (host)
+    labelings: list                 # [(K, labels int32 [N] on the device)]
+
+
+def ksweep_labels(blob: np.ndarray, n_blobs: int, k: int, relabel: float,
+                  rng: np.random.Generator) -> np.ndarray:
+    """Merge blobs into k clusters (blob b -> floor(b k / n_blobs)), then move exactly
+    round(relabel N) rows to a cluster drawn uniformly from the other k - 1."""
+    lab = (blob.astype(np.int64) * k // n_blobs).astype(np.int32)
+    m = int(round(relabel * len(blob)))
+    if m:
+        rows = rng.choice(len(blob), size=m, replace=False)
+        r = rng.integers(0, k - 1, size=m).astype(np.int32)
+        lab[rows] = r + (r >= lab[rows])
+    return lab
+
+
+def make_ksweep(n_datasets: int = 32, labelings: int = 8, n_lo: int = 10_000, n_hi: int = 2_000_000,
+                dims=(16, 32, 64, 128), n_blobs: int = 256, k_lo: int = 2, k_hi: int = 256,
+                sigma: float = 1.0, relabel: float = 0.05, seed0: int = 1000,
+                device: str | torch.device = "cpu") -> list:
+    """The batched k-sweep workload: data set d (seed seed0 + d) has N ~ U_int[n_lo, n_hi] points
+    in D ~ U(dims) dimensions drawn as n_blobs Gaussian blobs (centres U[-10, 10]^D, Dirichlet(1)
+    sizes, sigma); each of its `labelings` labelings has K log-uniform in [k_lo, k_hi] (integer)
+    and merges the blobs into K clusters, with relabel noise."""
+    out = []
+    for d in range(n_datasets):
+        rng = np.random.Generator(np.random.PCG64(seed0 + d))
+        n = int(rng.integers(n_lo, n_hi + 1))
+        dim = int(rng.choice(np.asarray(dims)))
+        spec = BlobSpec(f"ksweep-{d}", n, dim, n_blobs, sigma, "dirichlet", relabel=0.0, seed=seed0 + d)
+        b = make_blobs(spec, device)
+        blob = b.labels.cpu().numpy()
+        labs = []
+        for _ in range(labelings):
+            k = int(np.clip(np.round(np.exp(rng.uniform(np.log(k_lo), np.log(k_hi)))), k_lo, k_hi))
+            lab = ksweep_labels(blob, n_blobs, k, relabel, rng)
+            labs.append((k, torch.from_numpy(lab).to(device)))
+        out.append(SweepDataset(b.X, blob, labs))
+    return out
+
+
 def expected_size_bytes(spec: BlobSpec, bytes_per_elem: int) -> int:
     return spec.n * spec.d * bytes_per_elem + 4 * spec.n
 
@@ -211,4 +260,5 @@ def fits(spec: BlobSpec, free_bytes: int, bytes_per_elem: int = 4) -> bool:
 
 
 __all__ = ["BlobSpec", "WORKLOADS", "Blobs", "make_blobs", "make_small", "make_labels", "scaled",
-           "cluster_sizes", "to_bf16", "to_fp8_e4m3", "host_codes", "FP8_E4M3_MAX"]
+           "cluster_sizes", "to_bf16", "to_fp8_e4m3", "host_codes", "FP8_E4M3_MAX", "SweepDataset",
+           "ksweep_labels", "make_ksweep"]

@@ -80,3 +80,42 @@ def test_host_argument_errors_launch_nothing(lib):
 def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, 99):
         assert isinstance(lib.silhouette_strerror(code), bytes)
+
+
+def test_batched_plan_host_checks(lib):
+    # descriptor checks happen before any device query; nothing is launched
+    from paper_2303_14102_amd import _lib
+    fake = 0x1000
+
+    def plan(probs, flags=0):
+        arr = (_lib.SilProblem * max(1, len(probs)))(*probs)
+        out = ctypes.c_void_p(123)
+        rc = lib.silhouette_batched_plan(arr, len(probs), flags, ctypes.byref(out))
+        assert out.value is None  # no plan on failure
+        return rc
+
+    ok = dict(X=fake, labels=fake, N=100, D=16, K=4, dtype=_lib.SIL_F32, metric=0, s=0, S=fake)
+
+    def P(**kw):
+        return _lib.SilProblem(**{**ok, **kw})
+
+    assert plan([]) == -1                                   # no problems
+    assert plan([P()] * 1025) == -1                         # too many
+    assert plan([P(D=129)]) == -1                           # deeper than the batched kernel
+    assert plan([P(D=0)]) == -1
+    assert plan([P(K=1)]) == -1
+    assert plan([P(K=16385)]) == -1
+    assert plan([P(N=0)]) == -1
+    assert plan([P(N=2**31)]) == -1
+    assert plan([P(metric=2)]) == -1
+    assert plan([P(X=0)]) == -1
+    assert plan([P(labels=0)]) == -1
+    assert plan([P(S=0)]) == -1
+    assert plan([P(), P(dtype=_lib.SIL_BF16)]) == -2        # fp32 storage only
+    assert plan([P()], flags=_lib.SIL_FLAG_SAVE_FOR_GRAD) == -1
+    assert lib.silhouette_batched_plan(None, 1, 0, ctypes.byref(ctypes.c_void_p())) == -1
+    assert lib.silhouette_batched_workspace_bytes(None) == 0
+    assert lib.silhouette_batched_run(None, ctypes.c_void_p(fake), 1, None) == -1
+    assert lib.silhouette_batched_replay(None, None) == -1
+    assert lib.silhouette_batched_set_config(None, None, 6) == -1
+    lib.silhouette_batched_free(None)
