@@ -158,6 +158,53 @@ struct Blocks {
   int32_t cown[NB];    // uniform block: lane column of the own cluster (wave-uniform)
 };
 
+// Row ids and labels of a wave's row blocks, loaded ahead of the block that uses them.
+template <int NB>
+struct RowPre {
+  int32_t row[NB];
+  int32_t lab[NB];
+};
+
+// Loads the row ids and labels of sorted positions p0 + 32 nb + lane%32.  Positions are
+// valid below N: when every label is in range the sort covers all N rows; otherwise the
+// result is replaced by NaN and only the addresses must stay in bounds, so row ids are
+// clamped to [0, N) and labels outside [0, K) become -1.
+template <int NB>
+__device__ __forceinline__ RowPre<NB> fetch_rows(const MainArgs& a, int64_t p0, int lane) {
+  RowPre<NB> pre;
+  const int r = lane & 31;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t pos = p0 + nb * 32 + r;
+    const bool ok = pos < a.N;
+    pre.row[nb] = ok ? a.perm[pos] : 0;
+    pre.lab[nb] = ok ? a.lsorted[pos] : -1;
+  }
+  return pre;
+}
+
+template <int NB>
+__device__ __forceinline__ void make_blocks(const MainArgs& a, const RowPre<NB>& pre, int64_t p0,
+                                            int lane, Blocks<NB>& B, int32_t* lds_lab) {
+  const int r = lane & 31;
+  B.p0 = p0;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t pos = p0 + nb * 32 + r;
+    B.ok[nb] = pos < a.N;
+    const int32_t rw = pre.row[nb];
+    B.row[nb] = (rw >= 0 && rw < a.N) ? rw : 0;
+    int32_t o = B.ok[nb] ? pre.lab[nb] : -1;
+    if (o < 0 || o >= a.K) o = -1;
+    B.lab[nb] = o;
+    const int32_t o0 = __shfl(o, 0, 64);
+    B.mixed[nb] = !__all(o == o0 || o < 0);
+    B.town[nb] = o0 >> 5;
+    B.cown[nb] = o0 & 31;
+    if (lane < 32) lds_lab[nb * 32 + r] = o;  // labels of the block for the mixed-block path
+  }
+}
+
 template <int NB>
 __device__ __forceinline__ void load_blocks(const MainArgs& a, int64_t nvalid, int64_t p0,
                                             int lane, Blocks<NB>& B, int32_t* lds_lab) {
@@ -232,6 +279,19 @@ __device__ __forceinline__ void decode_raw(typename RawChunk<DT>::T raw,
   for (int e = 0; e < W; ++e) out[e] = valid ? out[e] : 0.0f;
 }
 
+// W consecutive floats from a 16-byte aligned address.
+template <int W>
+__device__ __forceinline__ void load_f32w(const float* __restrict__ p, float* out) {
+#pragma unroll
+  for (int i = 0; i < W / 4; ++i) {
+    const f32x4_t v = *reinterpret_cast<const f32x4_t*>(p + 4 * i);
+    out[4 * i] = v[0];
+    out[4 * i + 1] = v[1];
+    out[4 * i + 2] = v[2];
+    out[4 * i + 3] = v[3];
+  }
+}
+
 template <int DT, int W, int NQ, int NB, int METRIC, int NC, typename Emit>
 __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B, int lane,
                                          float (&nrow)[NB], float (&arow)[NB], Emit&& emit) {
@@ -275,15 +335,20 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int c0 = (2 * q + h) * W;
+      // the chunk's centring values and own-cluster mean: W consecutive floats at a multiple of
+      // W (mvec and atab rows hold DPX floats, 256-byte aligned regions), so whole-vector loads
+      float mv[W], at[W];
+      if constexpr (METRIC == SIL_SQEUCLID) load_f32w<W>(a.mvec + c0, mv);
+      load_f32w<W>(a.atab + orow + c0, at);
       float v[W];
 #pragma unroll
       for (int e = 0; e < W; ++e) {
         if constexpr (METRIC == SIL_COSINE)
           v[e] = xv[q][e] * inv;
         else
-          v[e] = ok ? xv[q][e] - a.mvec[c0 + e] : 0.0f;  // mvec is zero when not centring
+          v[e] = ok ? xv[q][e] - mv[e] : 0.0f;  // mvec is zero when not centring
         nx = fmaf(v[e], v[e], nx);
-        const float dd = v[e] - a.atab[orow + c0 + e];
+        const float dd = v[e] - at[e];
         ad = fmaf(dd, dd, ad);
         const int idx = c0 + e;
         if (idx >= a.D && idx < a.D + NC) v[e] = 1.0f;  // carries c_k through the GEMM
@@ -346,6 +411,25 @@ __device__ __forceinline__ void tile_min(const f32x16_t& acc, float (&mn)[16], i
   }
 }
 
+// Minimum over the 32 lanes of each half of the wave, in every lane of that half: data-parallel
+// lane moves fused into the min within 16-lane rows (swap neighbours, swap pairs, mirror
+// within 8, mirror within 16), then a swizzle that exchanges lane i and i ^ 16.
+template <int CTRL>
+__device__ __forceinline__ float dpp_min(float v) {
+  const int o = __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, 0xf, 0xf,
+                                            false);
+  return fminf(v, __int_as_float(o));
+}
+
+__device__ __forceinline__ float min_over_half(float v) {
+  v = dpp_min<0xb1>(v);   // quad_perm [1,0,3,2]
+  v = dpp_min<0x4e>(v);   // quad_perm [2,3,0,1]
+  v = dpp_min<0x141>(v);  // row_half_mirror
+  v = dpp_min<0x140>(v);  // row_mirror
+  const int o = __builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401f);  // lane ^ 16 in 32
+  return fminf(v, __int_as_float(o));
+}
+
 // After the sweep: row minima across the 32 lanes of each half, then s_i per row (written to
 // the row's original index) and the workgroup's sum of s_i.
 template <int NB, int METRIC, bool SAVE>
@@ -358,18 +442,18 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Bloc
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
+      if constexpr (SAVE) {  // minimum and its (lowest) cluster id
 #pragma unroll
-      for (int off = 1; off < 32; off <<= 1) {
-        const float ov = __shfl_xor(mn[nb][j], off, 64);
-        if constexpr (SAVE) {
+        for (int off = 1; off < 32; off <<= 1) {
+          const float ov = __shfl_xor(mn[nb][j], off, 64);
           const int32_t oa = __shfl_xor(arg[nb][j], off, 64);
           if (ov < mn[nb][j] || (ov == mn[nb][j] && oa < arg[nb][j])) {
             mn[nb][j] = ov;
             arg[nb][j] = oa;
           }
-        } else {
-          mn[nb][j] = fminf(mn[nb][j], ov);
         }
+      } else {
+        mn[nb][j] = min_over_half(mn[nb][j]);
       }
       if (col == 0) {
         lds_min[nb * 32 + out_row(j, h)] = mn[nb][j];
@@ -505,34 +589,29 @@ __device__ __forceinline__ void sweep(const char* bt, int64_t piece_bytes, int n
 // bf16 MFMA family (X stored bf16 or fp8).  v_mfma_f32_32x32x16_bf16: lane (r, h) supplies
 // A[row r][16s + 8h .. +8] and B[col r][16s + 8h .. +8] for k-step s.
 
+// One row block (wb) of the bf16 kernel, given the wave's row ids and labels (pre) and with
+// the first table tiles already issued into the ring.  When next_wb >= 0 the first tiles of
+// the next block are issued once every wave is past the sweep, so that their latency overlaps
+// this block's finish and the next block's prologue.  LDS buffers and tid as in main_f32_body.
 template <int DPX, int NB, int P, int DT, int METRIC, bool SAVE>
-__global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_bf16(MainArgs a) {
+__device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb, bool has_next,
+                                               const RowPre<NB>& pre, uint8_t* ring0,
+                                               uint8_t* ring1, uint8_t* ring2, float* lds_min,
+                                               int32_t* lds_arg, int32_t* lds_lab,
+                                               double* lds_bsum, int tid) {
   constexpr int S = DPX / 16;
   constexpr int NPC = P >= 2 ? 2 : 1;
   constexpr int RS = table_stride(DPX, SIL_BF16);
   using R = Ring<NPC, RS * 2>;
-  __shared__ __attribute__((aligned(16))) uint8_t ring0[R::STAGE_BYTES];
-  __shared__ __attribute__((aligned(16))) uint8_t ring1[R::STAGE_BYTES];
-  __shared__ __attribute__((aligned(16))) uint8_t ring2[R::NSTAGE == 3 ? R::STAGE_BYTES : 16];
-  __shared__ float lds_min[kMainWaves][NB * 32];
-  __shared__ int32_t lds_arg[kMainWaves][SAVE ? NB * 32 : 1];
-  __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves][NB * 32];
-  __shared__ double lds_bsum[kMainWaves];
+  constexpr int ARGW = SAVE ? NB * 32 : 1;
 
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wave = tid >> 6, lane = tid & 63;
   const int col = lane & 31, h = lane >> 5;
-  const int64_t nvalid = a.hdr[1];
-  const int64_t wb = blockIdx.x;
   const int64_t wg0 = wb * (kMainWaves * NB * 32);
-  if (wg0 >= nvalid) {  // no valid position in this row block (uniform)
-    if (tid == 0) a.bpart[wb] = 0.0;
-    return;
-  }
-  // the first tiles' latency overlaps the prologue
-  issue_first<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, wave, lane);
+  int32_t* lab_w = lds_lab + wave * NB * 32;
 
   Blocks<NB> B;
-  load_blocks<NB>(a, nvalid, wg0 + wave * NB * 32, lane, B, lds_lab[wave]);
+  make_blocks<NB>(a, pre, wg0 + wave * NB * 32, lane, B, lab_w);
 
   u32x4_t ahi[NB][S];
   u32x4_t alo[NB][P == 3 ? S : 1];
@@ -621,15 +700,45 @@ __global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_bf16(MainArgs a
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       tile_min<SAVE>(acc0[nb], mn[nb], arg[nb], B.mixed[nb], 2 * t == B.town[nb], col, B.cown[nb],
-                     64 * t, lds_lab[wave] + nb * 32, h);
+                     64 * t, lab_w + nb * 32, h);
       tile_min<SAVE>(acc1[nb], mn[nb], arg[nb], B.mixed[nb], 2 * t + 1 == B.town[nb], col,
-                     B.cown[nb], 64 * t + 32, lds_lab[wave] + nb * 32, h);
+                     B.cown[nb], 64 * t + 32, lab_w + nb * 32, h);
     }
   });
 
   __syncthreads();
-  finish<NB, METRIC, SAVE>(a, wb, B, wave, lane, mn, arg, nrow, arow, lds_min[wave], lds_arg[wave],
-                           lds_bsum);
+  // every wave is past its last read of the ring: start the next block's first tiles
+  if (has_next)
+    issue_first<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, wave,
+                   lane);
+  finish<NB, METRIC, SAVE>(a, wb, B, wave, lane, mn, arg, nrow, arow, lds_min + wave * NB * 32,
+                           lds_arg + wave * ARGW, lds_bsum);
+}
+
+// One row block per workgroup.  (A persistent variant that took blocks g, g + G, ... and loaded
+// the next block's rows ahead was slower: workgroups sharing a CU stay in phase, so their
+// prologues coincide and neither feeds the matrix cores.)
+template <int DPX, int NB, int P, int DT, int METRIC, bool SAVE>
+__global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_bf16(MainArgs a) {
+  constexpr int NPC = P >= 2 ? 2 : 1;
+  constexpr int RS = table_stride(DPX, SIL_BF16);
+  using R = Ring<NPC, RS * 2>;
+  __shared__ __attribute__((aligned(16))) uint8_t ring0[R::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t ring1[R::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t ring2[R::NSTAGE == 3 ? R::STAGE_BYTES : 16];
+  __shared__ float lds_min[kMainWaves * NB * 32];
+  __shared__ int32_t lds_arg[kMainWaves * (SAVE ? NB * 32 : 1)];
+  __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves * NB * 32];
+  __shared__ double lds_bsum[kMainWaves];
+
+  constexpr int64_t ROWS = kMainWaves * NB * 32;
+  const int64_t wb = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the first tiles' latency overlaps the prologue
+  issue_first<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, wave, lane);
+  const RowPre<NB> pre = fetch_rows<NB>(a, wb * ROWS + wave * NB * 32, lane);
+  main_bf16_body<DPX, NB, P, DT, METRIC, SAVE>(a, wb, false, pre, ring0, ring1, ring2, lds_min,
+                                               lds_arg, lds_lab, lds_bsum, threadIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------
