@@ -89,12 +89,13 @@ hipError_t launch_main(const Problem& p, const WsLayout& L, const WsPtrs& w, hip
   m.save_b = w.save_b;
   m.save_n = w.save_n;
   const unsigned grid = static_cast<unsigned>(p.nblocks);
-  if (p.dtype == SIL_F32)
+  if (p.dtype == SIL_F32) {
     launch_main_f32(m, p.DPX, p.metric, (p.flags & SIL_FLAG_SAVE_FOR_GRAD) != 0, grid, st);
-  else if (p.dtype == SIL_BF16)
+  } else if (p.dtype == SIL_BF16) {
     launch_main_bf16(m, p.DPX, p.metric, p.products, grid, st);
-  else
+  } else {
     launch_main_fp8(m, p.DPX, p.metric, p.products, grid, st);
+  }
   return hipGetLastError();
 }
 

@@ -14,18 +14,18 @@
 
 namespace sil {
 
-namespace {
-
-constexpr int kBatchDPXMax = 136;
+static constexpr int kBatchDPXMax = 136;
 constexpr int kBatchRS = table_stride(kBatchDPXMax, SIL_F32);
 using RingMax = Ring<1, kBatchRS * 4, 2>;
 constexpr int kBatchNBMax = 2;
 
 // Values read back from LDS are the same in every lane; say so, so that the problem's fields are
 // fetched with scalar loads into scalar registers.
-__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+static __device__ __forceinline__ int32_t uniform(int32_t v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
 
-__device__ __forceinline__ MainArgs batch_args(const BatchProblem& q) {
+static __device__ __forceinline__ MainArgs batch_args(const BatchProblem& q) {
   MainArgs a;
   a.X = q.X;
   a.col_scale = q.col_scale;
@@ -131,8 +131,6 @@ __global__ __launch_bounds__(256, 2) void k_main_f32_batched(BatchDev b, int32_t
 __global__ void k_queue_reset(int32_t* queue) {
   if (threadIdx.x == 0) queue[0] = 0;
 }
-
-}  // namespace
 
 hipError_t launch_main_batched(const BatchLaunch& b, hipStream_t st) {
   k_queue_reset<<<1, 64, 0, st>>>(b.dev.queue);

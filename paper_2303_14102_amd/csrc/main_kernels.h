@@ -590,11 +590,10 @@ __device__ __forceinline__ void sweep(const char* bt, int64_t piece_bytes, int n
 // A[row r][16s + 8h .. +8] and B[col r][16s + 8h .. +8] for k-step s.
 
 // One row block (wb) of the bf16 kernel, given the wave's row ids and labels (pre) and with
-// the first table tiles already issued into the ring.  When next_wb >= 0 the first tiles of
-// the next block are issued once every wave is past the sweep, so that their latency overlaps
-// this block's finish and the next block's prologue.  LDS buffers and tid as in main_f32_body.
+// the block's first table tiles already issued into the ring.  LDS buffers and tid as in
+// main_f32_body.
 template <int DPX, int NB, int P, int DT, int METRIC, bool SAVE>
-__device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb, bool has_next,
+__device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
                                                const RowPre<NB>& pre, uint8_t* ring0,
                                                uint8_t* ring1, uint8_t* ring2, float* lds_min,
                                                int32_t* lds_arg, int32_t* lds_lab,
@@ -644,80 +643,77 @@ __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb, bo
       arg[nb][j] = -1;
     }
 
-  // B fragments of k-step s for both 32-cluster blocks of the tile: [block][piece]
-  struct Frag { bf16x8_t v[2][2]; };
-  auto bfrag = [&](const uint8_t* st, int s) __attribute__((always_inline)) {
+  // B fragments of k-step s of one 32-cluster block: [piece]
+  struct Frag { bf16x8_t v[2]; };
+  auto bfrag = [&](const uint8_t* st, int cb, int s) __attribute__((always_inline)) {
     Frag f;
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      const int off = ((cb * 32 + col) * RS + 16 * s + 8 * h) * 2;
-      f.v[cb][0] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(st + off));
-      if constexpr (P >= 2)
-        f.v[cb][1] = __builtin_bit_cast(bf16x8_t,
-                                        *reinterpret_cast<const u32x4_t*>(st + R::SLOTS_PER_PIECE * 16 + off));
-    }
+    const int off = ((cb * 32 + col) * RS + 16 * s + 8 * h) * 2;
+    f.v[0] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(st + off));
+    if constexpr (P >= 2)
+      f.v[1] = __builtin_bit_cast(bf16x8_t,
+                                  *reinterpret_cast<const u32x4_t*>(st + R::SLOTS_PER_PIECE * 16 + off));
     return f;
   };
   constexpr int LA = S >= 3 ? 2 : 1;  // k-steps of table fragments read ahead
 
-  f32x16_t acc0[NB], acc1[NB];
-  sweep<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, ring2, wave, lane,
-           [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
+  // All k-steps of one 32-cluster block into acc: hi.hi (+ hi.lo) (+ lo.hi) per step.
+  auto gemm = [&](const uint8_t* st, int cb, f32x16_t (&acc)[NB], auto&& after_first_read)
+      __attribute__((always_inline)) {
     Frag f[LA + 1];
-    f[0] = bfrag(st, 0);
-    prefetch();
+    f[0] = bfrag(st, cb, 0);
+    after_first_read();
 #pragma unroll
-    for (int s = 1; s < LA; ++s) f[s] = bfrag(st, s);
+    for (int s = 1; s < LA; ++s) f[s] = bfrag(st, cb, s);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      if (s + LA < S) f[(s + LA) % (LA + 1)] = bfrag(st, s + LA);
+      if (s + LA < S) f[(s + LA) % (LA + 1)] = bfrag(st, cb, s + LA);
       // keep the read-ahead ahead: the scheduler would otherwise sink the reads next to
       // their first use and wait for them there
       __builtin_amdgcn_sched_barrier(0);
       const Frag& g = f[s % (LA + 1)];
-      // the two blocks' accumulation chains interleaved: independent MFMAs back to back
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const bf16x8_t ah = __builtin_bit_cast(bf16x8_t, ahi[nb][s]);
-        if (s == 0) {
-          acc0[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[0][0], f32x16_t{}, 0, 0, 0);
-          acc1[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[1][0], f32x16_t{}, 0, 0, 0);
-        } else {
-          acc0[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[0][0], acc0[nb], 0, 0, 0);
-          acc1[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[1][0], acc1[nb], 0, 0, 0);
-        }
-        if constexpr (P >= 2) {
-          acc0[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[0][1], acc0[nb], 0, 0, 0);
-          acc1[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[1][1], acc1[nb], 0, 0, 0);
-        }
+        if (s == 0)
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[0], f32x16_t{}, 0, 0, 0);
+        else
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[0], acc[nb], 0, 0, 0);
+        if constexpr (P >= 2)
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, g.v[1], acc[nb], 0, 0, 0);
         if constexpr (P == 3) {
           const bf16x8_t al = __builtin_bit_cast(bf16x8_t, alo[nb][s]);
-          acc0[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, g.v[0][0], acc0[nb], 0, 0, 0);
-          acc1[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, g.v[1][0], acc1[nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, g.v[0], acc[nb], 0, 0, 0);
         }
       }
     }
+  };
+  // Running minimum over 32-cluster block blk (global index) of the tile sweep.
+  auto epi = [&](const f32x16_t (&acc)[NB], int blk) __attribute__((always_inline)) {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      tile_min<SAVE>(acc0[nb], mn[nb], arg[nb], B.mixed[nb], 2 * t == B.town[nb], col, B.cown[nb],
-                     64 * t, lab_w + nb * 32, h);
-      tile_min<SAVE>(acc1[nb], mn[nb], arg[nb], B.mixed[nb], 2 * t + 1 == B.town[nb], col,
-                     B.cown[nb], 64 * t + 32, lab_w + nb * 32, h);
-    }
+    for (int nb = 0; nb < NB; ++nb)
+      tile_min<SAVE>(acc[nb], mn[nb], arg[nb], B.mixed[nb], blk == B.town[nb], col, B.cown[nb],
+                     32 * blk, lab_w + nb * 32, h);
+  };
+
+  // Per tile: block 0's MFMAs, the previous block 1's minimum (under them), block 1's MFMAs,
+  // block 0's minimum (under them).
+  f32x16_t acc0[NB], acc1[NB];
+  sweep<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, ring2, wave, lane,
+           [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
+    gemm(st, 0, acc0, prefetch);
+    if (t > 0) epi(acc1, 2 * t - 1);
+    gemm(st, 1, acc1, [] {});
+    epi(acc0, 2 * t);
   });
+  epi(acc1, 2 * a.ntiles - 1);
 
   __syncthreads();
-  // every wave is past its last read of the ring: start the next block's first tiles
-  if (has_next)
-    issue_first<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, wave,
-                   lane);
   finish<NB, METRIC, SAVE>(a, wb, B, wave, lane, mn, arg, nrow, arow, lds_min + wave * NB * 32,
                            lds_arg + wave * ARGW, lds_bsum);
 }
 
-// One row block per workgroup.  (A persistent variant that took blocks g, g + G, ... and loaded
-// the next block's rows ahead was slower: workgroups sharing a CU stay in phase, so their
-// prologues coincide and neither feeds the matrix cores.)
+// One row block per workgroup; two workgroups share a CU, so that one's prologue and finish
+// run under the other's sweep.
 template <int DPX, int NB, int P, int DT, int METRIC, bool SAVE>
 __global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_bf16(MainArgs a) {
   constexpr int NPC = P >= 2 ? 2 : 1;
@@ -737,8 +733,8 @@ __global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_bf16(MainArgs a
   // the first tiles' latency overlaps the prologue
   issue_first<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, wave, lane);
   const RowPre<NB> pre = fetch_rows<NB>(a, wb * ROWS + wave * NB * 32, lane);
-  main_bf16_body<DPX, NB, P, DT, METRIC, SAVE>(a, wb, false, pre, ring0, ring1, ring2, lds_min,
-                                               lds_arg, lds_lab, lds_bsum, threadIdx.x);
+  main_bf16_body<DPX, NB, P, DT, METRIC, SAVE>(a, wb, pre, ring0, ring1, ring2, lds_min, lds_arg,
+                                               lds_lab, lds_bsum, threadIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------

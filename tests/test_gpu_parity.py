@@ -120,6 +120,25 @@ def test_forward_parity(dev, case, metric, form, products):
     assert np.all(s[sizes[b.labels.numpy()] == 1] == 0.0)
 
 
+# larger problems: ragged N over ~1000 workgroups, 4 to 16 cluster tiles, every precision form,
+# many blocks that straddle a cluster boundary
+LARGER_CASES = [
+    # (N, D, K, metric, form, products, singletons, seed)
+    (150_001, 64, 300, "sqeuclid", "bf16", 3, 1, 61),
+    (140_333, 72, 257, "cosine", "bf16", 2, 0, 62),
+    (131_200, 128, 400, "sqeuclid", "fp8", 3, 2, 63),
+    (133_333, 48, 256, "sqeuclid", "bf16", 1, 0, 64),
+    (135_000, 128, 1000, "cosine", "bf16", 3, 1, 65),
+]
+
+
+@pytest.mark.parametrize("case", LARGER_CASES, ids=lambda c: f"N{c[0]}-D{c[1]}-K{c[2]}-{c[3]}-{c[4]}-P{c[5]}")
+def test_larger_parity(dev, case):
+    n, d, k, metric, form, products, single, seed = case
+    b = wl.make_small(n, d, k, seed=seed, singletons=single)
+    run_case(dev, b.X, b.labels, k, metric, form, products)
+
+
 def test_uncentred_and_offset_data(dev):
     # far from the origin, centring keeps the bf16 cross term accurate; fp32 too
     b = wl.make_small(4_000, 32, 20, seed=21)
