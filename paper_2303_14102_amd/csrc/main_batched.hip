@@ -7,7 +7,8 @@
 // counter passes the number of items, so the grid always drains.
 //
 // Each problem runs the same per-row-block body as the single-problem kernel, picked by its GEMM
-// depth, metric and rows per block.  The LDS is laid out for the deepest depth (136) with a
+// depth, metric and rows per block.  The next item's row ids and labels are loaded while the
+// current item runs (within a batch of queue items).  The LDS is laid out for the deepest depth (136) with a
 // two-stage table ring, so that two workgroups fit one CU for every depth.  The queue position
 // of the next batch of items is fetched while the current batch is computed.
 #include "main_kernels.h"
@@ -50,13 +51,46 @@ static __device__ __forceinline__ MainArgs batch_args(const BatchProblem& q) {
   return a;
 }
 
+// Row ids and labels of block wb of problem q for this wave (q.nb blocks of 32 rows).
+static __device__ __forceinline__ RowPre<kBatchNBMax> batch_rows(const BatchProblem& q, int64_t wb,
+                                                                 int wave, int lane) {
+  MainArgs a;
+  a.perm = q.perm;
+  a.lsorted = q.lsorted;
+  a.N = q.N;
+  const int64_t p0 = wb * (kMainWaves * 32 * q.nb) + wave * 32 * q.nb;
+  RowPre<kBatchNBMax> pre;
+  const RowPre<1> r0 = fetch_rows<1>(a, p0, lane);
+  pre.row[0] = r0.row[0];
+  pre.lab[0] = r0.lab[0];
+  pre.row[1] = 0;
+  pre.lab[1] = -1;
+  if (q.nb == 2) {
+    const RowPre<1> r1 = fetch_rows<1>(a, p0 + 32, lane);
+    pre.row[1] = r1.row[0];
+    pre.lab[1] = r1.lab[0];
+  }
+  return pre;
+}
+
+// First table tiles of the block, then the block body, for the problem's depth and rows.
 template <int METRIC>
 __device__ __forceinline__ void batch_body(const MainArgs& a, int DPX, int nb, int64_t wb,
-                                           int64_t nvalid, uint8_t* r0, uint8_t* r1,
-                                           float* lmin, int32_t* larg, int32_t* llab,
+                                           const RowPre<kBatchNBMax>& pre, uint8_t* r0,
+                                           uint8_t* r1, float* lmin, int32_t* larg, int32_t* llab,
                                            double* lbsum, int tid) {
+  const int wave = tid >> 6, lane = tid & 63;
 #define SIL_BODY(DP, NB)                                                                      \
-  main_f32_body<DP, NB, METRIC, false, 2>(a, wb, nvalid, r0, r1, r1, lmin, larg, llab, lbsum, tid)
+  do {                                                                                        \
+    issue_first<f32_ring<DP, 2>>(static_cast<const char*>(a.btab), 0, a.ntiles, r0, r1, wave, \
+                                 lane);                                                       \
+    RowPre<NB> p;                                                                             \
+    for (int i = 0; i < NB; ++i) {                                                            \
+      p.row[i] = pre.row[i];                                                                  \
+      p.lab[i] = pre.lab[i];                                                                  \
+    }                                                                                         \
+    main_f32_body<DP, NB, METRIC, false, 2>(a, wb, p, r0, r1, r1, lmin, larg, llab, lbsum, tid); \
+  } while (0)
   switch (DPX) {
     case 16:
       if (nb == 2) SIL_BODY(16, 2);
@@ -88,12 +122,12 @@ __global__ __launch_bounds__(256, 2) void k_main_f32_batched(BatchDev b, int32_t
   __shared__ int32_t lds_arg[kMainWaves];
   __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves * kBatchNBMax * 32];
   __shared__ double lds_bsum[kMainWaves];
-  __shared__ int32_t pre[kBatchMaxProblems + 1];
+  __shared__ int32_t pre_items[kBatchMaxProblems + 1];
   __shared__ int32_t next_base;
 
   const int n = b.n;
   const int32_t* gpre = b.prefix + BP_MAIN * (n + 1);
-  for (int i = threadIdx.x; i <= n; i += blockDim.x) pre[i] = gpre[i];
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) pre_items[i] = gpre[i];
   if (threadIdx.x == 0) next_base = atomicAdd(b.queue, grab);
   __syncthreads();
   int32_t base = uniform(next_base);
@@ -102,24 +136,32 @@ __global__ __launch_bounds__(256, 2) void k_main_f32_batched(BatchDev b, int32_t
     int32_t nxt = 0;
     if (threadIdx.x == 0) nxt = atomicAdd(b.queue, grab);
     const int32_t end = base + grab < total ? base + grab : total;
+    const int wave0 = threadIdx.x >> 6, lane0 = threadIdx.x & 63;
+    int jc = uniform(batch_locate(pre_items, n, base));
+    RowPre<kBatchNBMax> rows = batch_rows(b.prob[b.order[jc]], base - pre_items[jc], wave0, lane0);
     for (int32_t it = base; it < end; ++it) {
-      const int j = uniform(batch_locate(pre, n, it));
-      const BatchProblem& q = b.prob[b.order[j]];
+      const BatchProblem& q = b.prob[b.order[jc]];
+      const int64_t wb = it - uniform(pre_items[jc]);
+      // the next item's row ids and labels load while this item runs
+      RowPre<kBatchNBMax> nrows = rows;
+      int jn = jc;
+      if (it + 1 < end) {
+        jn = uniform(batch_locate(pre_items, n, it + 1));
+        nrows = batch_rows(b.prob[b.order[jn]], it + 1 - pre_items[jn], wave0, lane0);
+      }
       const MainArgs a = batch_args(q);
-      const int64_t wb = it - uniform(pre[j]);
-      const int64_t nvalid = q.hdr[1];
       // an opaque copy of the thread index: keeps the body's lane-dependent addresses out of
       // the loop (hoisting them would exceed the register budget)
       int tid = threadIdx.x;
       asm volatile("" : "+v"(tid));
       if (q.metric == SIL_SQEUCLID)
-        batch_body<SIL_SQEUCLID>(a, q.DPX, q.nb, wb, nvalid, ring0, ring1, lds_min, lds_arg,
+        batch_body<SIL_SQEUCLID>(a, q.DPX, q.nb, wb, rows, ring0, ring1, lds_min, lds_arg,
                                  lds_lab, lds_bsum, tid);
       else
-        batch_body<SIL_COSINE>(a, q.DPX, q.nb, wb, nvalid, ring0, ring1, lds_min, lds_arg,
-                               lds_lab, lds_bsum, tid);
-      // the body ends at a barrier on every path but the empty block's early exit
-      __syncthreads();
+        batch_body<SIL_COSINE>(a, q.DPX, q.nb, wb, rows, ring0, ring1, lds_min, lds_arg, lds_lab,
+                               lds_bsum, tid);
+      rows = nrows;
+      jc = jn;
     }
     if (threadIdx.x == 0) next_base = nxt;
     __syncthreads();

@@ -205,27 +205,6 @@ __device__ __forceinline__ void make_blocks(const MainArgs& a, const RowPre<NB>&
   }
 }
 
-template <int NB>
-__device__ __forceinline__ void load_blocks(const MainArgs& a, int64_t nvalid, int64_t p0,
-                                            int lane, Blocks<NB>& B, int32_t* lds_lab) {
-  const int r = lane & 31;
-  B.p0 = p0;
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int64_t pos = p0 + nb * 32 + r;
-    B.ok[nb] = pos < nvalid;
-    B.row[nb] = B.ok[nb] ? a.perm[pos] : 0;
-    int32_t o = B.ok[nb] ? a.lsorted[pos] : -1;
-    if (o >= a.K) o = -1;
-    B.lab[nb] = o;
-    const int32_t o0 = __shfl(o, 0, 64);
-    B.mixed[nb] = !__all(o == o0 || o < 0);
-    B.town[nb] = o0 >> 5;
-    B.cown[nb] = o0 & 31;
-    if (lane < 32) lds_lab[nb * 32 + r] = o;  // labels of the block for the mixed-block path
-  }
-}
-
 // ------------------------------------------------------------------------------------------
 // Prologue shared by both kernel families.  Lane (r = lane%32, h = lane/32) holds, for each of
 // its NB row blocks, the chunks c = 2q + h (q < NQ) of W elements of row r: it decodes them,
@@ -742,35 +721,34 @@ __global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_bf16(MainArgs a
 // and B[col r][k(s,h)] with k(s,h) = 8(s/4) + 4h + s%4, so each lane's operands are whole
 // float4 chunks c = 2q + h.
 
-// One row block (wb) of the fp32 kernel.  The LDS buffers come from the caller: ring0..2 the
-// table stages (ring2 unused with two stages), lds_min/lds_lab [kMainWaves][NB*32], lds_arg
-// [kMainWaves][SAVE ? NB*32 : 1], lds_bsum [kMainWaves].  NS_MAX caps the ring at two stages
-// where the caller provides only two.  tid is the thread's index in the workgroup; a caller
-// that runs the body in a loop passes it through an opaque copy, so that the lane-dependent
-// addresses are recomputed per block instead of being kept live across the loop.
+// One row block (wb) of the fp32 kernel, given the wave's row ids and labels (pre) and with
+// the block's first table tiles already issued into the ring (f32_ring<DPX, NS_MAX>).  The LDS
+// buffers come from the caller: ring0..2 the table stages (ring2 unused with two stages),
+// lds_min/lds_lab [kMainWaves][NB*32], lds_arg [kMainWaves][SAVE ? NB*32 : 1], lds_bsum
+// [kMainWaves].  NS_MAX caps the ring at two stages where the caller provides only two.  tid
+// is the thread's index in the workgroup; a caller that runs the body in a loop passes it
+// through an opaque copy, so that the lane-dependent addresses are recomputed per block
+// instead of being kept live across the loop.
+template <int DPX, int NS_MAX>
+using f32_ring = Ring<1, table_stride(DPX, SIL_F32) * 4, NS_MAX>;
+
 template <int DPX, int NB, int METRIC, bool SAVE, int NS_MAX>
-__device__ __forceinline__ void main_f32_body(const MainArgs& a, int64_t wb, int64_t nvalid,
+__device__ __forceinline__ void main_f32_body(const MainArgs& a, int64_t wb, const RowPre<NB>& pre,
                                               uint8_t* ring0, uint8_t* ring1, uint8_t* ring2,
                                               float* lds_min, int32_t* lds_arg, int32_t* lds_lab,
                                               double* lds_bsum, int tid) {
   constexpr int NQ = DPX / 8;
   constexpr int RS = table_stride(DPX, SIL_F32);
-  using R = Ring<1, RS * 4, NS_MAX>;
+  using R = f32_ring<DPX, NS_MAX>;
   constexpr int ARGW = SAVE ? NB * 32 : 1;
 
   const int wave = tid >> 6, lane = tid & 63;
   const int col = lane & 31, h = lane >> 5;
   const int64_t wg0 = wb * (kMainWaves * NB * 32);
-  if (wg0 >= nvalid) {  // no valid position in this row block (uniform)
-    if (tid == 0) a.bpart[wb] = 0.0;
-    return;
-  }
-  // the first tiles' latency overlaps the prologue
-  issue_first<R>(static_cast<const char*>(a.btab), 0, a.ntiles, ring0, ring1, wave, lane);
 
   int32_t* lab_w = lds_lab + wave * NB * 32;
   Blocks<NB> B;
-  load_blocks<NB>(a, nvalid, wg0 + wave * NB * 32, lane, B, lab_w);
+  make_blocks<NB>(a, pre, wg0 + wave * NB * 32, lane, B, lab_w);
 
   f32x4_t areg[NB][NQ];
   float nrow[NB], arow[NB];
@@ -844,8 +822,14 @@ __global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_f32(MainArgs a)
   __shared__ int32_t lds_arg[kMainWaves * (SAVE ? NB * 32 : 1)];
   __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves * NB * 32];
   __shared__ double lds_bsum[kMainWaves];
-  main_f32_body<DPX, NB, METRIC, SAVE, 3>(a, blockIdx.x, a.hdr[1], ring0, ring1, ring2, lds_min,
-                                          lds_arg, lds_lab, lds_bsum, threadIdx.x);
+  constexpr int64_t ROWS = kMainWaves * NB * 32;
+  const int64_t wb = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the first tiles' latency overlaps the prologue
+  issue_first<R>(static_cast<const char*>(a.btab), 0, a.ntiles, ring0, ring1, wave, lane);
+  const RowPre<NB> pre = fetch_rows<NB>(a, wb * ROWS + wave * NB * 32, lane);
+  main_f32_body<DPX, NB, METRIC, SAVE, 3>(a, wb, pre, ring0, ring1, ring2, lds_min, lds_arg,
+                                          lds_lab, lds_bsum, threadIdx.x);
 }
 
 }  // namespace sil
