@@ -82,8 +82,8 @@ __device__ __forceinline__ void batch_body(const MainArgs& a, int DPX, int nb, i
   const int wave = tid >> 6, lane = tid & 63;
 #define SIL_BODY(DP, NB)                                                                      \
   do {                                                                                        \
-    issue_first<f32_ring<DP, 2>>(static_cast<const char*>(a.btab), 0, a.ntiles, r0, r1, wave, \
-                                 lane);                                                       \
+    issue_first<f32_ring<DP, 2>>(static_cast<const char*>(a.btab), a.piece * 4, a.ntiles, r0,  \
+                                 r1, wave, lane);                                             \
     RowPre<NB> p;                                                                             \
     for (int i = 0; i < NB; ++i) {                                                            \
       p.row[i] = pre.row[i];                                                                  \

@@ -481,8 +481,9 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Bloc
 // wave w moves 1 KB per instruction (lane l -> 16 bytes at LDS offset 16 l), IPW instructions
 // per wave and tile.
 
-template <int PIECES, int ROWBYTES, int NS_MAX = 3>
+template <int PIECES_, int ROWBYTES, int NS_MAX = 3>
 struct Ring {
+  static constexpr int PIECES = PIECES_;
   static constexpr int SLOTS_PER_PIECE = kColTile * ROWBYTES / 16;
   static constexpr int TOT = PIECES * SLOTS_PER_PIECE;  // 16-byte slots per tile
   static constexpr int IPW = (TOT + 64 * kMainWaves - 1) / (64 * kMainWaves);
@@ -494,21 +495,26 @@ struct Ring {
   static constexpr int NSTAGE = NS_MAX >= 3 && 3 * STAGE_BYTES <= 52 * 1024 ? 3 : 2;
 };
 
+// Tile t into an LDS stage; piece_bytes is the byte size of one piece of the table (every piece
+// holds all ntiles tiles).  The table is read through a buffer resource (the buffer form of
+// the global -> LDS load): unlike the flat-encoded global form, it leaves the compiler's count
+// of outstanding LDS reads exact, so that fragment reads are waited for one by one instead of
+// all at once.  The resource spans the table's PIECES pieces (at most 2^31 bytes).
 template <typename R>
 __device__ __forceinline__ void issue_tile(const char* __restrict__ base, int64_t piece_bytes,
                                            int t, uint8_t* stage, int wave, int lane) {
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char*>(base), 0, static_cast<int>(piece_bytes * R::PIECES), 0x00020000);
 #pragma unroll
   for (int i = 0; i < R::IPW; ++i) {
     const int blk = i * kMainWaves + wave;
     const int q = blk * 64 + lane;
     if (blk * 64 < R::TOT) {
       const int pc = q / R::SLOTS_PER_PIECE, w = q % R::SLOTS_PER_PIECE;
-      const char* src = base + pc * piece_bytes + static_cast<int64_t>(t) * R::SLOTS_PER_PIECE * 16 +
-                        static_cast<int64_t>(w) * 16;
+      const int off = static_cast<int>(pc * piece_bytes) + t * R::SLOTS_PER_PIECE * 16 + w * 16;
       if (q < R::TOT)
-        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
-                                         (__attribute__((address_space(3))) void*)(stage + blk * 1024),
-                                         16, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rsrc, (__attribute__((address_space(3))) void*)(stage + blk * 1024), 16, off, 0, 0, 0);
     }
   }
 }
@@ -797,7 +803,7 @@ __device__ __forceinline__ void main_f32_body(const MainArgs& a, int64_t wb, con
   };
 
   f32x16_t acc0[NB], acc1[NB];
-  sweep<R>(static_cast<const char*>(a.btab), 0, a.ntiles, ring0, ring1, ring2, wave, lane,
+  sweep<R>(static_cast<const char*>(a.btab), a.piece * 4, a.ntiles, ring0, ring1, ring2, wave, lane,
            [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
     gemm(st, 0, acc0, prefetch);
     if (t > 0) epi(acc1, 2 * t - 1);
@@ -826,7 +832,7 @@ __global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_f32(MainArgs a)
   const int64_t wb = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // the first tiles' latency overlaps the prologue
-  issue_first<R>(static_cast<const char*>(a.btab), 0, a.ntiles, ring0, ring1, wave, lane);
+  issue_first<R>(static_cast<const char*>(a.btab), a.piece * 4, a.ntiles, ring0, ring1, wave, lane);
   const RowPre<NB> pre = fetch_rows<NB>(a, wb * ROWS + wave * NB * 32, lane);
   main_f32_body<DPX, NB, METRIC, SAVE, 3>(a, wb, pre, ring0, ring1, ring2, lds_min, lds_arg,
                                           lds_lab, lds_bsum, threadIdx.x);
