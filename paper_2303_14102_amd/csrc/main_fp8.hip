@@ -3,14 +3,21 @@
 
 namespace sil {
 
+// 64-cluster tiles (the 32-cluster form of the bf16 launcher spills here: the fp8 decode holds
+// more registers).
+template <int DPX, int P, int METRIC>
+static void run_p(const MainArgs& m, unsigned grid, hipStream_t st) {
+  k_main_bf16<DPX, bf16_nb(DPX, P), P, SIL_FP8_E4M3, METRIC, false><<<grid, 256, 0, st>>>(m);
+}
+
 template <int DPX, int METRIC>
 static void run_dp(const MainArgs& m, int products, unsigned grid, hipStream_t st) {
   if (products == 1)
-    k_main_bf16<DPX, bf16_nb(DPX, 1), 1, SIL_FP8_E4M3, METRIC, false><<<grid, 256, 0, st>>>(m);
+    run_p<DPX, 1, METRIC>(m, grid, st);
   else if (products == 2)
-    k_main_bf16<DPX, bf16_nb(DPX, 2), 2, SIL_FP8_E4M3, METRIC, false><<<grid, 256, 0, st>>>(m);
+    run_p<DPX, 2, METRIC>(m, grid, st);
   else
-    k_main_bf16<DPX, bf16_nb(DPX, 3), 3, SIL_FP8_E4M3, METRIC, false><<<grid, 256, 0, st>>>(m);
+    run_p<DPX, 3, METRIC>(m, grid, st);
 }
 
 template <int METRIC>

@@ -481,10 +481,10 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Bloc
 // wave w moves 1 KB per instruction (lane l -> 16 bytes at LDS offset 16 l), IPW instructions
 // per wave and tile.
 
-template <int PIECES_, int ROWBYTES, int NS_MAX = 3>
+template <int PIECES_, int ROWBYTES, int NS_MAX = 3, int COLS = kColTile>
 struct Ring {
   static constexpr int PIECES = PIECES_;
-  static constexpr int SLOTS_PER_PIECE = kColTile * ROWBYTES / 16;
+  static constexpr int SLOTS_PER_PIECE = COLS * ROWBYTES / 16;
   static constexpr int TOT = PIECES * SLOTS_PER_PIECE;  // 16-byte slots per tile
   static constexpr int IPW = (TOT + 64 * kMainWaves - 1) / (64 * kMainWaves);
   // fewest instructions any wave issues per tile: waiting until at most this many are in
@@ -577,7 +577,7 @@ __device__ __forceinline__ void sweep(const char* bt, int64_t piece_bytes, int n
 // One row block (wb) of the bf16 kernel, given the wave's row ids and labels (pre) and with
 // the block's first table tiles already issued into the ring.  LDS buffers and tid as in
 // main_f32_body.
-template <int DPX, int NB, int P, int DT, int METRIC, bool SAVE>
+template <int DPX, int NB, int P, int DT, int METRIC, bool SAVE, int TC = kColTile>
 __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
                                                const RowPre<NB>& pre, uint8_t* ring0,
                                                uint8_t* ring1, uint8_t* ring2, float* lds_min,
@@ -586,7 +586,7 @@ __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
   constexpr int S = DPX / 16;
   constexpr int NPC = P >= 2 ? 2 : 1;
   constexpr int RS = table_stride(DPX, SIL_BF16);
-  using R = Ring<NPC, RS * 2>;
+  using R = Ring<NPC, RS * 2, 3, TC>;
   constexpr int ARGW = SAVE ? NB * 32 : 1;
 
   const int wave = tid >> 6, lane = tid & 63;
@@ -680,17 +680,29 @@ __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
                      32 * blk, lab_w + nb * 32, h);
   };
 
-  // Per tile: block 0's MFMAs, the previous block 1's minimum (under them), block 1's MFMAs,
-  // block 0's minimum (under them).
-  f32x16_t acc0[NB], acc1[NB];
-  sweep<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, ring2, wave, lane,
-           [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
-    gemm(st, 0, acc0, prefetch);
-    if (t > 0) epi(acc1, 2 * t - 1);
-    gemm(st, 1, acc1, [] {});
-    epi(acc0, 2 * t);
-  });
-  epi(acc1, 2 * a.ntiles - 1);
+  if constexpr (TC == 64) {
+    // Per tile: block 0's MFMAs, the previous block 1's minimum (under them), block 1's MFMAs,
+    // block 0's minimum (under them).
+    f32x16_t acc0[NB], acc1[NB];
+    sweep<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, ring2, wave,
+             lane, [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
+      gemm(st, 0, acc0, prefetch);
+      if (t > 0) epi(acc1, 2 * t - 1);
+      gemm(st, 1, acc1, [] {});
+      epi(acc0, 2 * t);
+    });
+    epi(acc1, 2 * a.ntiles - 1);
+  } else {
+    // 32-cluster tiles (one block each): the other workgroups' waves on the SIMD fill the gap
+    // of each minimum
+    static_assert(TC == 32, "tiles of 32 or 64 clusters");
+    f32x16_t acc0[NB];
+    sweep<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, ring2, wave,
+             lane, [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
+      gemm(st, 0, acc0, prefetch);
+      epi(acc0, t);
+    });
+  }
 
   __syncthreads();
   finish<NB, METRIC, SAVE>(a, wb, B, wave, lane, mn, arg, nrow, arow, lds_min + wave * NB * 32,
@@ -699,11 +711,13 @@ __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
 
 // One row block per workgroup; two workgroups share a CU, so that one's prologue and finish
 // run under the other's sweep.
-template <int DPX, int NB, int P, int DT, int METRIC, bool SAVE>
-__global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_bf16(MainArgs a) {
+// TC: clusters per table tile, 64 (two workgroups per CU) or 32 (three per CU: the ring is half
+// as large and the kernel fits 168 registers; a.ntiles counts tiles of TC clusters).
+template <int DPX, int NB, int P, int DT, int METRIC, bool SAVE, int TC = kColTile>
+__global__ __launch_bounds__(256, DPX > 144 ? 1 : (TC == 32 ? 3 : 2)) void k_main_bf16(MainArgs a) {
   constexpr int NPC = P >= 2 ? 2 : 1;
   constexpr int RS = table_stride(DPX, SIL_BF16);
-  using R = Ring<NPC, RS * 2>;
+  using R = Ring<NPC, RS * 2, 3, TC>;
   __shared__ __attribute__((aligned(16))) uint8_t ring0[R::STAGE_BYTES];
   __shared__ __attribute__((aligned(16))) uint8_t ring1[R::STAGE_BYTES];
   __shared__ __attribute__((aligned(16))) uint8_t ring2[R::NSTAGE == 3 ? R::STAGE_BYTES : 16];
@@ -718,8 +732,8 @@ __global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_bf16(MainArgs a
   // the first tiles' latency overlaps the prologue
   issue_first<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, wave, lane);
   const RowPre<NB> pre = fetch_rows<NB>(a, wb * ROWS + wave * NB * 32, lane);
-  main_bf16_body<DPX, NB, P, DT, METRIC, SAVE>(a, wb, pre, ring0, ring1, ring2, lds_min, lds_arg,
-                                               lds_lab, lds_bsum, threadIdx.x);
+  main_bf16_body<DPX, NB, P, DT, METRIC, SAVE, TC>(a, wb, pre, ring0, ring1, ring2, lds_min,
+                                                   lds_arg, lds_lab, lds_bsum, threadIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------
