@@ -62,7 +62,14 @@ enum {
   SIL_FLAG_NO_CENTRE = 1 << 0,
   /* Keep a_i, b_i and the neighbouring cluster id of every point in the workspace, as the
    * backward entry points need them (fp32 storage only; SIL_E_DTYPE otherwise). */
-  SIL_FLAG_SAVE_FOR_GRAD = 1 << 1
+  SIL_FLAG_SAVE_FOR_GRAD = 1 << 1,
+  /* Squared Euclidean only: the approximate Euclidean Silhouette that the paper names among its
+   * limitations (Section V) -- each point-to-cluster mean distance is taken as the square root of
+   * the mean squared distance, so a_i and b_i become their square roots before Eq.1.  This is
+   * not the exact Euclidean Silhouette (by Jensen's inequality each root is at least the mean
+   * Euclidean distance; they agree when all of a point's distances to a cluster are equal).
+   * SIL_E_ARG with the cosine entry point or with SIL_FLAG_SAVE_FOR_GRAD. */
+  SIL_FLAG_EUCLID_APPROX = 1 << 2
 };
 
 /*
@@ -189,7 +196,8 @@ typedef struct sil_plan sil_plan;
 
 /*
  * Validates `count` problem descriptors (host array, copied) and creates a plan on the current
- * device.  flags: SIL_FLAG_NO_CENTRE or 0 (applies to the squared Euclidean problems).  On
+ * device.  flags: SIL_FLAG_NO_CENTRE and SIL_FLAG_EUCLID_APPROX bits (both apply to the squared
+ * Euclidean problems only).  On
  * success *plan is set (free it with silhouette_batched_free); otherwise *plan is NULL and a
  * sil_status is returned.
  */

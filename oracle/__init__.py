@@ -23,7 +23,8 @@ _SO = os.path.join(HERE, "_silhouette_oracle.so")
 
 F32, BF16, FP8_E4M3, F64 = 0, 1, 2, 3
 SQEUCLID, COSINE = 0, 1
-METRICS = {"sqeuclid": SQEUCLID, "cosine": COSINE}
+EUCLID_APPROX = 2  # square roots of the point-to-cluster mean squared distances (Section V)
+METRICS = {"sqeuclid": SQEUCLID, "cosine": COSINE, "euclid_approx": EUCLID_APPROX}
 
 ERRORS = {
     -1: "bad argument",

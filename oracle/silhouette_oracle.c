@@ -34,7 +34,7 @@
 #endif
 
 enum { ORC_F32 = 0, ORC_BF16 = 1, ORC_FP8_E4M3 = 2, ORC_F64 = 3 };
-enum { ORC_SQEUCLID = 0, ORC_COSINE = 1 };
+enum { ORC_SQEUCLID = 0, ORC_COSINE = 1, ORC_EUCLID_APPROX = 2 };
 enum {
   ORC_OK = 0,
   ORC_E_ARG = -1,
@@ -107,7 +107,7 @@ static int orc_check_args(const void* X, int dtype, const float* col_scale, cons
   if (!X || !labels || N < 1 || D < 1 || K < 1) return ORC_E_ARG;
   if (dtype < ORC_F32 || dtype > ORC_F64) return ORC_E_ARG;
   if (dtype == ORC_FP8_E4M3 && !col_scale) return ORC_E_ARG;
-  if (metric != ORC_SQEUCLID && metric != ORC_COSINE) return ORC_E_ARG;
+  if (metric != ORC_SQEUCLID && metric != ORC_COSINE && metric != ORC_EUCLID_APPROX) return ORC_E_ARG;
   return ORC_OK;
 }
 
@@ -145,7 +145,7 @@ int orc_cluster_stats(const void* X, int dtype, const float* col_scale, const in
     }
     if (rc) break;
     count[k] += 1;
-    if (metric == ORC_SQEUCLID) {
+    if (metric != ORC_COSINE) {
       for (int32_t l = 0; l < D; ++l) V[(int64_t)k * D + l] += x[l];
       psi[k] += xi;
     } else {
@@ -179,7 +179,7 @@ static void orc_point_means(const double* x, int32_t D, int32_t K, int metric,
     if (count[k] == 0) { m[k] = NAN; continue; }
     double nk = (double)count[k];
     double dot = 0.0;
-    if (metric == ORC_SQEUCLID) {
+    if (metric != ORC_COSINE) {
       for (int32_t l = 0; l < D; ++l) dot += V[(int64_t)k * D + l] * x[l];
       m[k] = xi + psi[k] / nk - 2.0 * dot / nk;
     } else {
@@ -194,11 +194,13 @@ static void orc_point_means(const double* x, int32_t D, int32_t K, int metric,
  *   a_i = max(0, m_o * N_o / (N_o - 1))                 (own cluster, other members only)
  *   b_i = max(0, min_{k != o, N_k >= 1} m_k)            (neighbouring cluster, Section II)
  *   s_i = (b_i - a_i) / max(a_i, b_i)                   (Eq.1; equal to Eq.2)
- * with s_i = 0 for a singleton own cluster or when max(a_i, b_i) = 0.  nbr receives the lowest
+ * with s_i = 0 for a singleton own cluster or when max(a_i, b_i) = 0.  With root set (the
+ * approximate Euclidean form of Section V: the square root of each point-to-cluster mean squared
+ * distance) a_i and b_i are replaced by their square roots before Eq.1.  nbr receives the lowest
  * cluster id attaining b_i.  Returns s_i.
  */
 static double orc_point_score(const double* m, int32_t K, int32_t o, const int64_t* count,
-                              double* a_out, double* b_out, int32_t* nbr_out) {
+                              int root, double* a_out, double* b_out, int32_t* nbr_out) {
   double b = INFINITY;
   int32_t nbr = -1;
   for (int32_t k = 0; k < K; ++k) {
@@ -207,9 +209,11 @@ static double orc_point_score(const double* m, int32_t K, int32_t o, const int64
   }
   if (b < 0.0) b = 0.0;
   double a = 0.0, s = 0.0;
+  if (root) b = sqrt(b);
   if (count[o] >= 2) {
     a = m[o] * (double)count[o] / (double)(count[o] - 1);
     if (a < 0.0) a = 0.0;
+    if (root) a = sqrt(a);
     double mx = a > b ? a : b;
     s = mx > 0.0 ? (b - a) / mx : 0.0;
   }
@@ -254,8 +258,8 @@ int orc_scores_at(const void* X, int dtype, const float* col_scale, const int32_
         int64_t i = idx[t];
         orc_row(X, dtype, col_scale, i, D, x);
         orc_point_means(x, D, K, metric, count, V, psi, m);
-        s[t] = orc_point_score(m, K, labels[i], count, a ? a + t : NULL, b ? b + t : NULL,
-                               nbr ? nbr + t : NULL);
+        s[t] = orc_point_score(m, K, labels[i], count, metric == ORC_EUCLID_APPROX,
+                               a ? a + t : NULL, b ? b + t : NULL, nbr ? nbr + t : NULL);
       }
     }
     free(x);
@@ -345,7 +349,7 @@ int orc_brute_silhouette(const void* X, int dtype, const float* col_scale, const
             if (j == i) continue;
             const double* xj = all + j * (int64_t)D;
             double d = 0.0;
-            if (metric == ORC_SQEUCLID) {
+            if (metric != ORC_COSINE) {
               for (int32_t l = 0; l < D; ++l) d += (xi[l] - xj[l]) * (xi[l] - xj[l]);
             } else {
               double dot = 0.0, ni = 0.0, nj = 0.0;
@@ -365,6 +369,10 @@ int orc_brute_silhouette(const void* X, int dtype, const float* col_scale, const
             double b = INFINITY;
             for (int32_t k = 0; k < K; ++k)
               if (k != o && count[k] > 0 && sum[k] / (double)count[k] < b) b = sum[k] / (double)count[k];
+            if (metric == ORC_EUCLID_APPROX) {  /* roots of the mean squared distances */
+              a = sqrt(a);
+              b = sqrt(b);
+            }
             double mx = a > b ? a : b;
             si = mx > 0.0 ? (b - a) / mx : 0.0;
           }
@@ -440,7 +448,7 @@ int orc_brute_scores_at(const void* X, int dtype, const float* col_scale, const 
           if (j == i) continue;
           orc_row(X, dtype, col_scale, j, D, xj);
           double d = 0.0;
-          if (metric == ORC_SQEUCLID) {
+          if (metric != ORC_COSINE) {
             for (int32_t l = 0; l < D; ++l) d += (xi[l] - xj[l]) * (xi[l] - xj[l]);
           } else {
             double dot = 0.0, nj = 0.0;
@@ -473,6 +481,10 @@ int orc_brute_scores_at(const void* X, int dtype, const float* col_scale, const 
       bi = INFINITY;
       for (int32_t k = 0; k < K; ++k)
         if (k != o && count[k] > 0 && part[k] / (double)count[k] < bi) bi = part[k] / (double)count[k];
+      if (metric == ORC_EUCLID_APPROX) {  /* roots of the mean squared distances */
+        ai = sqrt(ai);
+        bi = sqrt(bi);
+      }
       const double mx = ai > bi ? ai : bi;
       si = mx > 0.0 ? (bi - ai) / mx : 0.0;
     }
@@ -505,6 +517,7 @@ int orc_brute_scores_at(const void* X, int dtype, const float* col_scale, const 
  */
 int orc_gradient(const void* X, int dtype, const float* col_scale, const int32_t* labels,
                  int64_t N, int32_t D, int32_t K, int metric, double* dX) {
+  if (metric == ORC_EUCLID_APPROX) return ORC_E_ARG;
   int rc = orc_check_args(X, dtype, col_scale, labels, N, D, K, metric);
   if (rc) return rc;
   int64_t* count = (int64_t*)malloc(sizeof(int64_t) * (size_t)K);

@@ -62,17 +62,20 @@ def new_workspace(N: int, D: int, K: int, metric: str, dtype, flags: int, device
 
 def silhouette(X: torch.Tensor, labels: torch.Tensor, K: int, metric: str = "sqeuclid", *,
                products: int = 0, centre: bool = True, col_scale: Optional[torch.Tensor] = None,
-               want_s: bool = True, save_for_grad: bool = False,
+               want_s: bool = True, save_for_grad: bool = False, euclid_approx: bool = False,
                workspace: Optional[torch.Tensor] = None, check_status: bool = False):
     """Per-point s_i (float32 [N] or None) and the mean S (float64 0-d tensor on the device).
 
     products: bf16/fp8 cross-term products (1, 2, 3; 0 = library default).  centre: subtract
-    the global mean first (squared Euclidean only).  workspace: a uint8 device tensor of at least
-    workspace_bytes(...) bytes, reused across calls; allocated here when None.
+    the global mean first (squared Euclidean only).  euclid_approx: the approximate Euclidean
+    form (square roots of the point-to-cluster mean squared distances; squared Euclidean only).
+    workspace: a uint8 device tensor of at least workspace_bytes(...) bytes, reused across
+    calls; allocated here when None.
     """
     _check_inputs(X, labels, col_scale)
     N, D = X.shape
-    flags = (0 if centre else L.SIL_FLAG_NO_CENTRE) | (L.SIL_FLAG_SAVE_FOR_GRAD if save_for_grad else 0)
+    flags = ((0 if centre else L.SIL_FLAG_NO_CENTRE) | (L.SIL_FLAG_SAVE_FOR_GRAD if save_for_grad else 0)
+             | (L.SIL_FLAG_EUCLID_APPROX if euclid_approx else 0))
     if workspace is None:
         workspace = new_workspace(N, D, K, metric, X.dtype, flags, X.device)
     s = torch.empty(N, dtype=torch.float32, device=X.device) if want_s else None
@@ -161,7 +164,8 @@ class BatchedSilhouette:
     ``self.s[i]`` (float32 [N_i]).  The workspace is allocated here once and owned by the plan.
     """
 
-    def __init__(self, problems, *, want_s: bool = True, centre: bool = True):
+    def __init__(self, problems, *, want_s: bool = True, centre: bool = True,
+                 euclid_approx: bool = False):
         if not problems:
             raise ValueError("no problems")
         dev = problems[0][0].device
@@ -182,7 +186,7 @@ class BatchedSilhouette:
         self._arr = arr
         plan = ctypes.c_void_p()
         lib = L.load()
-        flags = 0 if centre else L.SIL_FLAG_NO_CENTRE
+        flags = (0 if centre else L.SIL_FLAG_NO_CENTRE) | (L.SIL_FLAG_EUCLID_APPROX if euclid_approx else 0)
         L.check(lib.silhouette_batched_plan(arr, len(problems), flags, ctypes.byref(plan)),
                 "silhouette_batched_plan")
         self._plan = plan

@@ -122,6 +122,9 @@ static int forward(int32_t metric, const void* X, int32_t dtype, const float* co
   if (!S) return SIL_E_ARG;
   if (products == 0) products = 3;
   if (products < 1 || products > 3) return SIL_E_ARG;
+  if ((flags & SIL_FLAG_EUCLID_APPROX) &&
+      (metric != SIL_SQEUCLID || (flags & SIL_FLAG_SAVE_FOR_GRAD)))
+    return SIL_E_ARG;
   const WsPtrs w = carve(L, ws);
   if ((flags & SIL_FLAG_SAVE_FOR_GRAD) && dtype != SIL_F32) return SIL_E_DTYPE;
   const int64_t nblocks = ceil_div(N, main_rows_per_block(dtype, L.DPX, products));
@@ -145,6 +148,7 @@ static int backward(int32_t metric, const void* X, int32_t dtype, const float* c
                     const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t flags,
                     const double* gS, float* dX, void* ws, size_t ws_bytes, void* stream) {
   WsLayout L;
+  if (flags & SIL_FLAG_EUCLID_APPROX) return SIL_E_ARG;
   flags |= SIL_FLAG_SAVE_FOR_GRAD;
   int rc = check_common(X, dtype, col_scale, labels, N, D, K, metric, ws, ws_bytes, flags, &L);
   if (rc) return rc;

@@ -78,12 +78,13 @@ size_t build_header(sil_plan* P, void* ws) {
     q.Kpad = L.Kpad;
     q.dtype = SIL_F32;
     q.metric = u.metric;
-    q.flags = P->flags;
+    q.flags = u.metric == SIL_COSINE ? (P->flags & ~SIL_FLAG_EUCLID_APPROX) : P->flags;
     q.nb = P->nb[i];
     q.nseg = L.nseg;
     q.nblocks = ceil_div(L.N, kMainWaves * 32 * q.nb);
     q.zero_words = static_cast<int64_t>((L.perm - L.hdr) / 4);
     stats_lanes(L.D, SIL_F32, &q.Gv, &q.G, &q.E);
+    q.rowch = u.metric == SIL_SQEUCLID ? row_chunk(L.D, SIL_F32) : 0;
     reduce_split(q.nblocks, &q.red_chunk, &q.red_n1);
     q.hdr = w.hdr;
     q.count = w.count;
@@ -210,7 +211,7 @@ int silhouette_batched_plan(const sil_problem* problems, int32_t count, int32_t 
   if (!plan) return SIL_E_ARG;
   *plan = nullptr;
   if (!problems || count < 1 || count > kBatchMaxProblems) return SIL_E_ARG;
-  if (flags & ~SIL_FLAG_NO_CENTRE) return SIL_E_ARG;
+  if (flags & ~(SIL_FLAG_NO_CENTRE | SIL_FLAG_EUCLID_APPROX)) return SIL_E_ARG;
   for (int i = 0; i < count; ++i) {
     const sil_problem& u = problems[i];
     if (!u.X || !u.labels || !u.S) return SIL_E_ARG;
@@ -247,7 +248,7 @@ int silhouette_batched_plan(const sil_problem* problems, int32_t count, int32_t 
   P->hdr_bytes = o;
   for (int i = 0; i < count; ++i) {
     const sil_problem& u = problems[i];
-    const int32_t fl = u.metric == SIL_COSINE ? 0 : (flags & SIL_FLAG_NO_CENTRE);
+    const int32_t fl = u.metric == SIL_COSINE ? 0 : (flags & (SIL_FLAG_NO_CENTRE | SIL_FLAG_EUCLID_APPROX));
     P->L.push_back(make_layout(u.N, u.D, u.K, u.metric, SIL_F32, fl));
     P->off.push_back(o);
     o = align256(o + P->L.back().total);

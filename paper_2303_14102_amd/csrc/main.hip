@@ -83,6 +83,7 @@ hipError_t launch_main(const Problem& p, const WsLayout& L, const WsPtrs& w, hip
   m.ascale = w.ascale;
   m.mvec = w.mvec;
   m.ntiles = p.Kpad / kColTile;
+  m.root = (p.metric == SIL_SQEUCLID && (p.flags & SIL_FLAG_EUCLID_APPROX)) ? 1 : 0;
   m.s = p.s;
   m.bpart = w.bpart;
   m.save_a = w.save_a;

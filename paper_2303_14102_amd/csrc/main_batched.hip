@@ -43,6 +43,7 @@ static __device__ __forceinline__ MainArgs batch_args(const BatchProblem& q) {
   a.ascale = q.ascale;
   a.mvec = q.mvec;
   a.ntiles = q.Kpad / kColTile;
+  a.root = (q.metric == SIL_SQEUCLID && (q.flags & SIL_FLAG_EUCLID_APPROX)) ? 1 : 0;
   a.s = q.s;
   a.bpart = q.bpart;
   a.save_a = nullptr;

@@ -58,6 +58,7 @@ struct MainArgs {
   const float* ascale;
   const float* mvec;       // [DPX] centring vector (zeros when not centring)
   int32_t ntiles;
+  int32_t root;            // approximate Euclidean form: square roots of a_i and b_i
   float* s;
   double* bpart;
   float* save_a;
@@ -451,7 +452,11 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Bloc
     float b = lds_min[nb * 32 + r];
     if constexpr (METRIC == SIL_SQEUCLID) b += nrow[nb];
     b = fmaxf(b, 0.0f);
-    const float av = fmaxf(arow[nb], 0.0f);
+    float av = fmaxf(arow[nb], 0.0f);
+    if (METRIC == SIL_SQEUCLID && a.root) {  // the mean distances' square roots
+      b = sqrtf(b);
+      av = sqrtf(av);
+    }
     float s = 0.0f;
     if (o >= 0 && a.ascale[o] > 0.0f) {
       const float mx = fmaxf(av, b);

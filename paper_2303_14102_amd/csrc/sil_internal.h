@@ -166,6 +166,7 @@ struct BatchProblem {
   int32_t dtype, metric, flags, nb;  // nb: 32-row blocks per wave of the fused kernel
   int64_t nseg, nblocks, zero_words;
   int32_t Gv;        // lanes per row of the 16-byte statistics reduction, 0 for the generic one
+  int32_t rowch;     // bytes per lane of the whole-wave row reduction, 0 when not used
   int32_t G, E;      // lanes per row and columns per lane of the generic reduction
   int32_t red_n1;    // first-stage workgroups of the S reduction
   int64_t red_chunk; // partials per first-stage workgroup
@@ -239,6 +240,8 @@ struct BatchLaunch {
 // lanes per row of the statistics reduction: Gv for 16-byte chunks (0 when D does not split into
 // a power-of-two number of them), else G lanes of E columns each
 void stats_lanes(int32_t D, int32_t dtype, int32_t* Gv, int32_t* G, int32_t* E);
+// bytes per lane when a whole wave reads one row of the statistics pass (0: not that kernel)
+int row_chunk(int32_t D, int32_t dtype);
 hipError_t launch_stats_batched(const BatchLaunch& b, hipStream_t st);
 hipError_t launch_finalize_batched(const BatchLaunch& b, hipStream_t st);
 hipError_t launch_main_batched(const BatchLaunch& b, hipStream_t st);

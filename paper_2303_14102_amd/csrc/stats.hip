@@ -483,6 +483,149 @@ __global__ __launch_bounds__(256) void k_segreduce_vec(
                                  blockIdx.x);
 }
 
+// Squared Euclidean statistics of fp32 or bf16 rows of RB = 64 * CH bytes (CH = 4, 8 or 16):
+// the whole wave reads one row per step, lane l holding the CH bytes at offset l * CH, so a lane
+// always owns the same E = CH / sizeof(element) columns and every lane sees the same row.  The
+// sorted positions are wave-uniform: row ids come from scalar loads of perm, run boundaries are
+// scalar branches, and Psi is reduced across the wave only when a run is stored.  Batches of U
+// rows are double-buffered: the rows of batch t + 1 and the ids of batch t + 2 are in flight
+// while batch t is accumulated.  Runs are stored as in k_segreduce.
+template <int DT, int CH>
+__device__ __forceinline__ void segreduce_row_body(
+    const void* __restrict__ X, const int32_t* __restrict__ perm, const int32_t* __restrict__ offset, int32_t K, int32_t D,
+    int64_t nseg, double* __restrict__ V, double* __restrict__ psi,
+    double* __restrict__ segpart, int32_t* __restrict__ hdr, int64_t bid) {
+  static_assert(DT == SIL_F32 || DT == SIL_BF16, "fp32 or bf16 rows");
+  constexpr int ESZ = DT == SIL_F32 ? 4 : 2;
+  constexpr int E = CH / ESZ;
+  constexpr int NW = CH / 4;
+  constexpr int U = NW == 1 ? 16 : NW == 2 ? 8 : 4;
+  constexpr int64_t RB = 64 * CH;
+  typedef uint32_t chunk_t __attribute__((ext_vector_type(NW == 1 ? 2 : NW)));
+  const int lane = threadIdx.x & 63;
+  const int64_t seg = bid * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (seg >= nseg) return;
+  const int64_t nvalid = hdr[1];
+  const int64_t p0 = seg * kSegLen;
+  const int64_t p1 = min(nvalid, p0 + static_cast<int64_t>(kSegLen));
+  if (p0 >= p1) return;
+  const char* Xl = static_cast<const char*>(X) + lane * CH;
+
+  int32_t kc = find_cluster(offset, K, p0);
+  int64_t rs = offset[kc], re = offset[kc + 1];
+  double acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = 0.0;
+  double accq = 0.0;
+  bool bad_value = false;
+
+  auto flush = [&]() __attribute__((always_inline)) {
+    for (int off = 1; off < 64; off <<= 1) accq += shfl_xor_f64(accq, off);
+    double* dst;
+    double* dpsi;
+    if (rs >= p0 && re <= p1) {
+      dst = V + static_cast<int64_t>(kc) * D;
+      dpsi = psi + kc;
+    } else {
+      const int slot = rs <= p0 ? 0 : 1;
+      dst = segpart + (seg * 2 + slot) * static_cast<int64_t>(D + 1);
+      dpsi = dst + D;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[lane * E + e] = acc[e];
+    if (lane == 0) *dpsi = accq;
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = 0.0;
+    accq = 0.0;
+  };
+
+  auto add_row = [&](chunk_t raw) __attribute__((always_inline)) {
+    double x[E];
+#pragma unroll
+    for (int w = 0; w < (NW == 1 ? 1 : NW); ++w) {
+      if constexpr (DT == SIL_F32) {
+        x[w] = static_cast<double>(__uint_as_float(raw[w]));
+      } else if constexpr (DT == SIL_BF16) {
+        x[2 * w] = static_cast<double>(__uint_as_float(raw[w] << 16));
+        x[2 * w + 1] = static_cast<double>(__uint_as_float(raw[w] & 0xffff0000u));
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      bad_value |= !isfinite(x[e]);
+      acc[e] += x[e];
+      accq = fma(x[e], x[e], accq);
+    }
+  };
+
+  // ids of the U positions from p; past p1 the last valid id is repeated and its row is loaded
+  // but never accumulated
+  auto fetch_ids = [&](int64_t p, int32_t* ids) __attribute__((always_inline)) {
+    if (p + U <= p1) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) ids[u] = perm[p + u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) ids[u] = perm[min(p + u, p1 - 1)];
+    }
+  };
+  auto fetch_rows = [&](const int32_t* ids, chunk_t* raw) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const char* src = Xl + static_cast<int64_t>(ids[u]) * RB;
+      if constexpr (NW == 1)
+        raw[u] = chunk_t{*reinterpret_cast<const uint32_t*>(src), 0u};
+      else
+        raw[u] = *reinterpret_cast<const chunk_t*>(src);
+    }
+  };
+
+  // The loads of the next batch are issued unconditionally (the last batch prefetches rows it
+  // never uses) so that every iteration has the same loads in flight and the waits for batch t
+  // leave batch t + 1 outstanding.
+  int32_t ids[U];
+  chunk_t raw[U];
+  fetch_ids(p0, ids);
+  fetch_rows(ids, raw);
+  fetch_ids(p0 + U, ids);
+  for (int64_t p = p0; p < p1; p += U) {
+    chunk_t nxt[U];
+    fetch_rows(ids, nxt);
+    fetch_ids(p + 2 * U, ids);
+    if (p + U <= re && p + U <= p1) {  // the whole batch belongs to the current run
+#pragma unroll
+      for (int u = 0; u < U; ++u) add_row(raw[u]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t pos = p + u;
+        if (pos < p1) {
+          while (pos >= re) {  // uniform: the run ends before this row
+            flush();
+            kc = find_cluster(offset, K, re);
+            rs = offset[kc];
+            re = offset[kc + 1];
+          }
+          add_row(raw[u]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) raw[u] = nxt[u];
+  }
+  flush();
+  if (bad_value) set_status(hdr, SIL_E_NONFINITE);
+}
+
+template <int DT, int CH>
+__global__ __launch_bounds__(256) void k_segreduce_row(
+    const void* __restrict__ X, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ offset, int32_t K, int32_t D, int64_t nseg,
+    double* __restrict__ V, double* __restrict__ psi, double* __restrict__ segpart,
+    int32_t* __restrict__ hdr) {
+  segreduce_row_body<DT, CH>(X, perm, offset, K, D, nseg, V, psi, segpart, hdr, blockIdx.x);
+}
+
 // Sums of clusters whose sorted range spans several segments.  One thread per (cluster,
 // column), column D being Psi.
 __device__ __forceinline__ void combine_body(const int32_t* __restrict__ offset, int32_t K,
@@ -518,6 +661,22 @@ __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ off
 
 // ------------------------------------------------------------------------------------------
 
+template <int DT>
+static void launch_seg_row(const Problem& p, const WsLayout& L, const WsPtrs& w, int ch,
+                           unsigned nblk, hipStream_t st) {
+  if constexpr (DT != SIL_FP8_E4M3) {
+    if (ch == 4)
+      k_segreduce_row<DT, 4><<<nblk, 256, 0, st>>>(p.X, w.perm, w.offset, p.K, p.D,
+                                                   L.nseg, w.V, w.psi, w.segpart, w.hdr);
+    else if (ch == 8)
+      k_segreduce_row<DT, 8><<<nblk, 256, 0, st>>>(p.X, w.perm, w.offset, p.K, p.D,
+                                                   L.nseg, w.V, w.psi, w.segpart, w.hdr);
+    else
+      k_segreduce_row<DT, 16><<<nblk, 256, 0, st>>>(p.X, w.perm, w.offset, p.K, p.D,
+                                                    L.nseg, w.V, w.psi, w.segpart, w.hdr);
+  }
+}
+
 hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
   // zero: header .. segpart are contiguous in the layout; zero [hdr, perm)
   const int64_t words = static_cast<int64_t>((L.perm - L.hdr) / 4);
@@ -534,9 +693,13 @@ hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hi
   int32_t Gv, G, E;
   stats_lanes(p.D, p.dtype, &Gv, &G, &E);
   const bool vec = Gv != 0;
+  // whole-wave rows (squared Euclidean, fp32 or bf16 rows of 256, 512 or 1024 bytes)
+  const int rowch = p.metric == SIL_SQEUCLID ? row_chunk(p.D, p.dtype) : 0;
 #define SIL_SEG(DT, MT)                                                                         \
   do {                                                                                          \
-    if (vec)                                                                                    \
+    if (rowch && MT == SIL_SQEUCLID)                                                            \
+      launch_seg_row<DT>(p, L, w, rowch, nblk, st);                                             \
+    else if (vec)                                                                               \
       k_segreduce_vec<DT, MT><<<nblk, 256, 0, st>>>(p.X, p.col_scale, w.perm, w.offset, p.K,    \
                                                     p.D, Gv, L.nseg, w.V, w.psi, w.segpart,     \
                                                     w.hdr);                                     \
@@ -607,7 +770,13 @@ __global__ __launch_bounds__(256) void kb_seg(BatchDev b) {
   int64_t it;
   const BatchProblem& q = batch_item(b, BP_SEG, &it);
   if (q.metric == SIL_SQEUCLID) {
-    if (q.Gv)
+    if (q.rowch == 4)
+      segreduce_row_body<SIL_F32, 4>(q.X, q.perm, q.offset, q.K, q.D, q.nseg, q.V, q.psi,
+                                     q.segpart, q.hdr, it);
+    else if (q.rowch == 8)
+      segreduce_row_body<SIL_F32, 8>(q.X, q.perm, q.offset, q.K, q.D, q.nseg, q.V, q.psi,
+                                     q.segpart, q.hdr, it);
+    else if (q.Gv)
       segreduce_vec_body<SIL_F32, SIL_SQEUCLID>(q.X, q.col_scale, q.perm, q.offset, q.K, q.D, q.Gv,
                                                 q.nseg, q.V, q.psi, q.segpart, q.hdr, it);
     else
@@ -627,6 +796,14 @@ __global__ __launch_bounds__(256) void kb_combine(BatchDev b) {
   int64_t it;
   const BatchProblem& q = batch_item(b, BP_COMBINE, &it);
   combine_body(q.offset, q.K, q.D, q.segpart, q.V, q.psi, it);
+}
+
+// Bytes per lane of the whole-wave row reduction (fp32 or bf16 rows of 256, 512 or 1024 bytes),
+// else 0.
+int row_chunk(int32_t D, int32_t dtype) {
+  if (dtype != SIL_F32 && dtype != SIL_BF16) return 0;
+  const int64_t rb = static_cast<int64_t>(D) * (dtype == SIL_F32 ? 4 : 2);
+  return (rb == 256 || rb == 512 || rb == 1024) ? static_cast<int>(rb / 64) : 0;
 }
 
 // Lanes per row of the generic reduction for D columns (shared with the batch planner).

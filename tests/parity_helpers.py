@@ -30,9 +30,12 @@ def cross_term_eps(form, products, metric, centre, D):
     return 2.0 ** -8 + (0.0 if exact_x else 2.0 ** -8) + acc
 
 
-def bound_from_stats(form, products, metric, centre, rows, stats, a, b):
+def bound_from_stats(form, products, metric, centre, rows, stats, a, b, root=False):
     """Bound on |s_i(GPU) - s_i(oracle)| for the given rows (binary64 values as stored), from
-    binary64 cluster statistics (count, V, psi) of the whole data set."""
+    binary64 cluster statistics (count, V, psi) of the whole data set.  root: the approximate
+    Euclidean form, where a and b (the oracle's, already square roots) are roots of the mean
+    squared distances: the squared quantities' error bounds pass through the square root as
+    interval widths."""
     count, V, psi = stats
     rows = np.asarray(rows, np.float64)
     D = rows.shape[1]
@@ -51,12 +54,20 @@ def bound_from_stats(form, products, metric, centre, rows, stats, a, b):
         cmax = 1.0
     nx = np.linalg.norm(xp, axis=1)
     eps = cross_term_eps(form, products, metric, centre, D)
+    if root:  # the squared quantities and their bounds, then the roots' interval widths
+        a2, b2 = np.asarray(a) ** 2, np.asarray(b) ** 2
+        db2 = 2 * eps * nx * np.linalg.norm(mup, axis=1).max() + 4 * U32 * (nx ** 2 + cmax)
+        da2 = 4 * U32 * (D + 8) * (a2 + np.abs(a2))
+        da = np.sqrt(a2 + da2) - np.sqrt(np.maximum(a2 - da2, 0.0))
+        db = np.sqrt(b2 + db2) - np.sqrt(np.maximum(b2 - db2, 0.0))
+        return 2 * (da + db) / np.maximum(np.maximum(a, b), 1e-30) + 4 * U32
     db = 2 * eps * nx * np.linalg.norm(mup, axis=1).max() + 4 * U32 * (nx ** 2 + cmax)
     da = 4 * U32 * (D + 8) * (a + np.abs(a))
     return 2 * (da + db) / np.maximum(np.maximum(a, b), 1e-30) + 4 * U32
 
 
 def plain_stats(X, labels, K, metric):
+    metric = "sqeuclid" if metric == "euclid_approx" else metric
     """count, V, psi of a small data set with numpy (for the bound only)."""
     X = np.asarray(X, np.float64)
     cnt = np.bincount(labels, minlength=K)
@@ -69,8 +80,10 @@ def plain_stats(X, labels, K, metric):
 
 
 def per_point_bound(form, products, metric, centre, Xh, labels, K, a, b):
-    """Per-point bound for every row of a small data set."""
-    return bound_from_stats(form, products, metric, centre, Xh, plain_stats(Xh, labels, K, metric), a, b)
+    """Per-point bound for every row of a small data set (metric may be euclid_approx)."""
+    root = metric == "euclid_approx"
+    m = "sqeuclid" if root else metric
+    return bound_from_stats(form, products, m, centre, Xh, plain_stats(Xh, labels, K, m), a, b, root)
 
 
 def dequantised(codes, col_scale):

@@ -75,6 +75,14 @@ def test_host_argument_errors_launch_nothing(lib):
         assert fn(fake, 0, None, fake, 10, 4, 2, 0, 0, None, None, ws, 1 << 30, None) == -1  # S NULL
         # backward saves exist for fp32 storage only
         assert fn(fake, 1, None, fake, 10, 4, 2, 0, _lib.SIL_FLAG_SAVE_FOR_GRAD, None, fake, ws, 1 << 30, None) == -2
+        # the approximate Euclidean form has no backward
+        approx_save = _lib.SIL_FLAG_EUCLID_APPROX | _lib.SIL_FLAG_SAVE_FOR_GRAD
+        assert fn(fake, 0, None, fake, 10, 4, 2, 0, approx_save, None, fake, ws, 1 << 30, None) == -1
+    # ... and is a squared Euclidean form
+    assert lib.silhouette_cosine(fake, 0, None, fake, 10, 4, 2, 0, _lib.SIL_FLAG_EUCLID_APPROX, None, fake, ws,
+                                 1 << 30, None) == -1
+    for bw in (lib.silhouette_sqeuclid_backward, lib.silhouette_cosine_backward):
+        assert bw(fake, 0, None, fake, 10, 4, 2, _lib.SIL_FLAG_EUCLID_APPROX, fake, fake, ws, 1 << 30, None) == -1
 
 
 def test_strerror(lib):
@@ -113,6 +121,7 @@ def test_batched_plan_host_checks(lib):
     assert plan([P(S=0)]) == -1
     assert plan([P(), P(dtype=_lib.SIL_BF16)]) == -2        # fp32 storage only
     assert plan([P()], flags=_lib.SIL_FLAG_SAVE_FOR_GRAD) == -1
+    assert plan([P()], flags=1 << 3) == -1                  # unknown flag bit
     assert lib.silhouette_batched_plan(None, 1, 0, ctypes.byref(ctypes.c_void_p())) == -1
     assert lib.silhouette_batched_workspace_bytes(None) == 0
     assert lib.silhouette_batched_run(None, ctypes.c_void_p(fake), 1, None) == -1

@@ -155,6 +155,26 @@ def test_graph_capture_and_replay(dev, mixed):
     check_against_oracle(batch, expect, "after replays")
 
 
+def test_batched_euclid_approx(dev, mixed):
+    # the approximate Euclidean flag applies to the squared Euclidean problems of the batch; the
+    # cosine problems ignore it
+    from paper_2303_14102_amd import BatchedSilhouette
+    probs, refs, _ = mixed
+    batch = BatchedSilhouette(probs, euclid_approx=True)
+    batch.run()
+    torch.cuda.synchronize()
+    assert batch.status() == [0] * len(probs)
+    S = batch.S.cpu().numpy()
+    for i, (X, lab, k, metric) in enumerate(refs):
+        m = "euclid_approx" if metric == "sqeuclid" else metric
+        s_ref, S_ref, a, b, _ = oracle.silhouette(X, lab, k, m, details=True)
+        bound = per_point_bound("f32", 0, m, True, X, lab, k, a, b)
+        ds = np.abs(batch.s[i].cpu().numpy().astype(np.float64) - s_ref)
+        assert np.all(ds <= bound), f"problem {i} ({MIXED[i]}): point {int((ds / bound).argmax())}"
+        assert abs(S[i] - S_ref) <= TOL_S_MEAN["f32"], f"problem {i}: S {S[i]} vs {S_ref}"
+    batch.close()
+
+
 def test_error_in_one_problem_is_isolated(dev):
     from paper_2303_14102_amd import BatchedSilhouette
     good = wl.make_small(2_000, 16, 10, seed=50)

@@ -74,6 +74,49 @@ def test_stats_parity(dev, metric, form):
     np.testing.assert_allclose(psi.cpu().numpy(), p_ref, rtol=1e-12, atol=0)
 
 
+# squared Euclidean statistics of rows of 256, 512 or 1024 bytes (the whole-wave row reduction)
+ROW_CASES = [(128, "bf16"), (256, "bf16"), (64, "f32"), (128, "f32"), (256, "f32")]
+
+
+def row_case_labels(rng):
+    # cluster sizes that put run boundaries on segment borders (4096 positions), on batch borders
+    # (16, 8 or 4 rows), one row either side of them, and runs shorter than a batch; then the
+    # cluster ids are shuffled and the rows permuted
+    sizes = [4096, 4080, 16, 1, 15, 8192, 3, 4093, 2, 1, 12000, 17, 4, 4, 4, 4, 9000, 5, 4095]
+    sizes += list(rng.integers(1, 40, size=200)) + [0, 0, 7000]
+    K = len(sizes)
+    ids = rng.permutation(K)
+    lab = np.repeat(ids, sizes).astype(np.int32)
+    return lab[rng.permutation(len(lab))], K
+
+
+@pytest.mark.parametrize("D,form", ROW_CASES, ids=lambda v: str(v))
+def test_stats_row_reduction(dev, D, form):
+    from paper_2303_14102_amd import binding as sil
+    rng = np.random.default_rng(D + len(form))
+    lab, K = row_case_labels(rng)
+    X = torch.from_numpy(rng.standard_normal((len(lab), D)).astype(np.float32) * 3 + 1)
+    Xd, sc, codes = storage(X.to(dev), form)
+    print(f"[stats-row] N={len(lab)} D={D} K={K} form={form}", flush=True)
+    count, V, psi = sil.cluster_stats(Xd, torch.from_numpy(lab).to(dev), K, "sqeuclid")
+    c_ref, V_ref, p_ref = oracle.cluster_stats(codes, lab, K, "sqeuclid")
+    assert np.array_equal(count.cpu().numpy(), c_ref)
+    scale = np.abs(V_ref).max()
+    np.testing.assert_allclose(V.cpu().numpy(), V_ref, rtol=1e-12, atol=1e-12 * scale)
+    np.testing.assert_allclose(psi.cpu().numpy(), p_ref, rtol=1e-12, atol=0)
+
+
+def test_stats_row_reduction_nonfinite(dev):
+    from paper_2303_14102_amd import _lib
+    from paper_2303_14102_amd import binding as sil
+    b = wl.make_small(9_000, 128, 6, seed=9)
+    X = b.X.clone()
+    X[4321, 77] = float("inf")
+    with pytest.raises(_lib.SilhouetteError) as e:
+        sil.silhouette(X.to(dev).to(torch.bfloat16), b.labels.to(dev), 6, check_status=True)
+    assert e.value.code == -6
+
+
 def test_stats_large_clusters_span_segments(dev):
     # a few clusters of ~1e5 points: every cluster crosses many segment borders
     from paper_2303_14102_amd import binding as sil
@@ -137,6 +180,48 @@ def test_larger_parity(dev, case):
     n, d, k, metric, form, products, single, seed = case
     b = wl.make_small(n, d, k, seed=seed, singletons=single)
     run_case(dev, b.X, b.labels, k, metric, form, products)
+
+
+# approximate Euclidean form (square roots of the point-to-cluster mean squared distances)
+APPROX_CASES = [
+    # (N, D, K, form, products, singletons, seed)
+    (5_037, 40, 70, "f32", 0, 2, 71),
+    (3_001, 128, 100, "bf16", 3, 1, 72),
+    (4_099, 16, 33, "fp8", 3, 1, 73),
+    (140_001, 64, 300, "bf16", 3, 0, 74),
+]
+
+
+@pytest.mark.parametrize("case", APPROX_CASES, ids=lambda c: f"N{c[0]}-D{c[1]}-K{c[2]}-{c[3]}")
+def test_euclid_approx_parity(dev, case):
+    from paper_2303_14102_amd import binding as sil
+    n, d, k, form, products, single, seed = case
+    b = wl.make_small(n, d, k, seed=seed, singletons=single)
+    Xd, sc, codes = storage(b.X.to(dev), form)
+    print(f"[approx] N={n} D={d} K={k} form={form}", flush=True)
+    s, S = sil.silhouette(Xd, b.labels.to(dev), k, "sqeuclid", products=products, col_scale=sc,
+                          euclid_approx=True, check_status=True)
+    cs = None if sc is None else sc.cpu().numpy()
+    lab_h = b.labels.numpy()
+    s_ref, S_ref, a, bb, _ = oracle.silhouette(codes, lab_h, k, "euclid_approx", col_scale=cs, details=True)
+    bound = per_point_bound(form, products, "euclid_approx", True, dequantised(codes, cs), lab_h, k, a, bb)
+    s = s.cpu().numpy().astype(np.float64)
+    ds = np.abs(s - s_ref)
+    print(f"  S={S.item():.10f} ref={S_ref:.10f} max|ds|={ds.max():.2e} max(|ds|/bound)={(ds / bound).max():.3f}",
+          flush=True)
+    assert np.all(ds <= bound)
+    assert abs(S.item() - S_ref) <= TOL_S_MEAN[form]
+
+
+def test_euclid_approx_argument_errors(dev):
+    from paper_2303_14102_amd import _lib
+    from paper_2303_14102_amd import binding as sil
+    b = wl.make_small(500, 8, 4, seed=75)
+    X, lab = b.X.to(dev), b.labels.to(dev)
+    for kw in (dict(metric="cosine"), dict(metric="sqeuclid", save_for_grad=True)):
+        with pytest.raises(_lib.SilhouetteError) as e:
+            sil.silhouette(X, lab, 4, euclid_approx=True, **kw)
+        assert e.value.code == -1
 
 
 def test_uncentred_and_offset_data(dev):

@@ -240,6 +240,56 @@ def test_brute_scores_at_matches_sklearn(metric):
     np.testing.assert_allclose(s, s_lin, rtol=1e-9, atol=1e-12)
 
 
+# ---------------------------------------------------------------------------------------------
+# approximate Euclidean form (Section V): square roots of the point-to-cluster mean squared
+# distances
+
+
+def test_euclid_approx_equals_exact_where_distances_to_a_cluster_are_equal():
+    # cluster j = {r_j e_j, -r_j e_j} on its own axis: every distance from a point to the members
+    # of a cluster is the same, so the root of the mean squared distance is the mean distance and
+    # the approximation equals the exact Euclidean Silhouette (scikit-learn); plus a singleton
+    sk = pytest.importorskip("sklearn.metrics")
+    rng = np.random.default_rng(17)
+    K = 6
+    r = rng.uniform(0.5, 4.0, size=K)
+    X = np.zeros((2 * K + 1, K + 1))
+    lab = np.zeros(2 * K + 1, np.int32)
+    for j in range(K):
+        X[2 * j, j], X[2 * j + 1, j] = r[j], -r[j]
+        lab[2 * j] = lab[2 * j + 1] = j
+    X[2 * K, K] = 2.5          # alone in cluster K
+    lab[2 * K] = K
+    s, S = oracle.silhouette(X, lab, K + 1, "euclid_approx")
+    ref = sk.silhouette_samples(X, lab, metric="euclidean")
+    np.testing.assert_allclose(s, ref, rtol=0, atol=1e-13)
+    assert s[-1] == 0.0 and len(set(np.round(s[:-1], 6))) > 3  # non-trivial values
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_euclid_approx_definition_and_jensen(seed):
+    # the linear form equals the quadratic definition of the approximation, and each root of a
+    # mean squared distance is at least the mean Euclidean distance (Jensen), so a' >= a, b' >= b
+    rng = np.random.default_rng(300 + seed)
+    X, labels, K = _random_case(rng, n=250, d=5, k=6, unused=1)
+    s, S, a, b, _ = oracle.silhouette(X, labels, K, "euclid_approx", details=True)
+    sb, Sb = oracle.brute_silhouette(X, labels, K, "euclid_approx")
+    np.testing.assert_allclose(s, sb, rtol=0, atol=1e-10)
+    dist = np.sqrt(((X[:, None, :] - X[None, :, :]) ** 2).sum(-1))
+    cnt = np.bincount(labels, minlength=K)
+    for i in range(len(X)):
+        o = labels[i]
+        if cnt[o] < 2:
+            continue
+        a_exact = dist[i, labels == o].sum() / (cnt[o] - 1)
+        b_exact = min(dist[i, labels == k].mean() for k in range(K) if k != o and cnt[k] > 0)
+        assert a[i] >= a_exact - 1e-12 and b[i] >= b_exact - 1e-12
+    s2, a2, b2 = oracle.brute_scores_at(X, labels, K, np.arange(len(X)), "euclid_approx")
+    np.testing.assert_allclose(s2, sb, rtol=0, atol=1e-13)
+    with pytest.raises(oracle.OracleError):
+        oracle.gradient(X, labels, K, "euclid_approx")
+
+
 def test_expanded_form_vs_centred_form_at_offset():
     # Eq.11 expanded versus the centred form ||x - mu_k||^2 + sigma_k^2 (exact algebra),
     # evaluated in binary64 on data far from the origin
