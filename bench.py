@@ -50,6 +50,14 @@ def measured_traffic(kernel, workload):
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
+def stats_kernel(args, spec):
+    """Name of the statistics pass's reduction kernel for this run: whole-wave rows for squared
+    Euclidean fp32 / bf16 rows of 256, 512 or 1024 bytes, 16-byte chunks otherwise."""
+    rb = spec.d * {"f32": 4, "bf16": 2, "fp8": 1}[args.form]
+    row = args.metric == "sqeuclid" and args.form != "fp8" and rb in (256, 512, 1024)
+    return "k_segreduce_row" if row else "k_segreduce_vec"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +68,8 @@ def parse():
     ap.add_argument("--metric", default="sqeuclid", choices=["sqeuclid", "cosine"])
     ap.add_argument("--form", default="bf16", choices=["bf16", "fp8", "f32"])
     ap.add_argument("--products", type=int, default=3)
+    ap.add_argument("--euclid-approx", action="store_true",
+                    help="the approximate Euclidean form (square roots of the mean squared distances)")
     ap.add_argument("--fp32-steps", type=int, default=4)
     ap.add_argument("--no-fp32", action="store_true", help="skip the fp32-form comparison")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check on sampled points")
@@ -240,12 +250,16 @@ def main():
     from paper_2303_14102_amd import _lib
     lib = _lib.load()
     fn_c = lib.silhouette_sqeuclid if args.metric == "sqeuclid" else lib.silhouette_cosine
+    if args.euclid_approx and args.metric != "sqeuclid":
+        sys.exit("--euclid-approx applies to the squared Euclidean entry point")
+    flags = _lib.SIL_FLAG_EUCLID_APPROX if args.euclid_approx else 0
+    ref_metric = "euclid_approx" if args.euclid_approx else args.metric
     dcode = sil._dtype_code(X)
     stream = sil._stream(dev)
     cs_ptr = sil._ptr(col_scale)
 
     def step():
-        rc = fn_c(sil._ptr(X), dcode, cs_ptr, sil._ptr(labels), spec.n, spec.d, spec.k, args.products, 0,
+        rc = fn_c(sil._ptr(X), dcode, cs_ptr, sil._ptr(labels), spec.n, spec.d, spec.k, args.products, flags,
                   sil._ptr(s), sil._ptr(S), sil._ptr(ws), ws.numel(), stream)
         if rc:
             raise _lib.SilhouetteError(rc, "step")
@@ -258,7 +272,8 @@ def main():
     log(f"{args.form}: {ms:.3f} ms/step (wall {wall:.3f}), phases {['%.3f' % p for p in phases]}, S={S_form:.10f}")
 
     out = {
-        "metric": "Silhouette points/s at D=128,K=1000; bf16-MFMA vs fp32 form at |dS|<1e-4",
+        "metric": ("Approximate-Euclidean " if args.euclid_approx else "")
+        + "Silhouette points/s at D=128,K=1000; bf16-MFMA vs fp32 form at |dS|<1e-4",
         "value": spec.n / (ms * 1e-3),
         "unit": "points/s",
         "n_gpus": 1,
@@ -273,7 +288,8 @@ def main():
         "config": {"workload": spec.name, "n": spec.n, "d": spec.d, "k": spec.k,
                    "metric": args.metric, "storage": args.form,
                    "products": args.products if args.form != "f32" else None,
-                   "centred": args.metric == "sqeuclid"},
+                   "centred": args.metric == "sqeuclid",
+                   **({"euclid_approx": True} if args.euclid_approx else {})},
         "phases_ms": {"stats": phases[0], "finalize": phases[1], "gemm_epilogue": phases[2],
                       "reduce": phases[3]},
         "S": S_form,
@@ -296,7 +312,7 @@ def main():
     out["stats_pass"] = {"bound": "hbm", "algorithmic_bytes": stats_bytes,
                          "achieved_GBps": stats_bytes / (phases[0] * 1e-3) / 1e9,
                          "frac": stats_bytes / (phases[0] * 1e-3) / PEAK["hbm"],
-                         "traffic": measured_traffic("k_segreduce_vec", spec.name)}
+                         "traffic": measured_traffic(stats_kernel(args, spec), spec.name)}
 
     if args.calibrate:
         # a plain device copy of known size: the reference for the FETCH_SIZE / WRITE_SIZE counters
@@ -311,7 +327,7 @@ def main():
         S32 = torch.empty((), dtype=torch.float64, device=dev)
 
         def step32():
-            rc = fn_c(sil._ptr(X32), 0, None, sil._ptr(labels), spec.n, spec.d, spec.k, 0, 0,
+            rc = fn_c(sil._ptr(X32), 0, None, sil._ptr(labels), spec.n, spec.d, spec.k, 0, flags,
                       None, sil._ptr(S32), sil._ptr(ws32), ws32.numel(), stream)
             if rc:
                 raise _lib.SilhouetteError(rc, "step32")
@@ -337,10 +353,10 @@ def main():
         import oracle
         log("oracle check on sampled points (FP64 statistics over the full data)")
         t0 = time.perf_counter()
-        stats = oracle.cluster_stats(host_codes, labels_host, spec.k, args.metric, col_scale=cs_host)
+        stats = oracle.cluster_stats(host_codes, labels_host, spec.k, ref_metric, col_scale=cs_host)
         idx = np.random.default_rng(7).choice(spec.n, size=256, replace=False)
         s_ref, a_ref, b_ref, _ = oracle.scores_at(host_codes, labels_host, spec.k, idx, stats,
-                                                  args.metric, col_scale=cs_host)
+                                                  ref_metric, col_scale=cs_host)
         s_gpu = s.cpu().numpy()[idx].astype(np.float64)
         s_all = s.cpu().numpy().astype(np.float64)
         out["check"] = {"sampled_points": int(len(idx)),
@@ -351,7 +367,7 @@ def main():
 
     if not args.no_cpu:
         log(f"cpu baseline: oracle on {args.cpu_sample} rows")
-        out["cpu_baseline"] = cpu_baseline(spec, host_codes, labels_host, args.metric, cs_host, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(spec, host_codes, labels_host, ref_metric, cs_host, args.cpu_sample)
         log(f"cpu baseline: {out['cpu_baseline']}")
 
     print(json.dumps(out), flush=True)

@@ -80,7 +80,7 @@ __device__ __forceinline__ void batch_body(const MainArgs& a, int DPX, int nb, i
                                            const RowPre<kBatchNBMax>& pre, uint8_t* r0,
                                            uint8_t* r1, float* lmin, int32_t* larg, int32_t* llab,
                                            double* lbsum, int tid) {
-  const int wave = tid >> 6, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
 #define SIL_BODY(DP, NB)                                                                      \
   do {                                                                                        \
     issue_first<f32_ring<DP, 2>>(static_cast<const char*>(a.btab), a.piece * 4, a.ntiles, r0,  \
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256, 2) void k_main_f32_batched(BatchDev b, int32_t
     int32_t nxt = 0;
     if (threadIdx.x == 0) nxt = atomicAdd(b.queue, grab);
     const int32_t end = base + grab < total ? base + grab : total;
-    const int wave0 = threadIdx.x >> 6, lane0 = threadIdx.x & 63;
+    const int wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane0 = threadIdx.x & 63;
     int jc = uniform(batch_locate(pre_items, n, base));
     RowPre<kBatchNBMax> rows = batch_rows(b.prob[b.order[jc]], base - pre_items[jc], wave0, lane0);
     for (int32_t it = base; it < end; ++it) {

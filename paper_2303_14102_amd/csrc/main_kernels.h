@@ -594,7 +594,8 @@ __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
   using R = Ring<NPC, RS * 2, 3, TC>;
   constexpr int ARGW = SAVE ? NB * 32 : 1;
 
-  const int wave = tid >> 6, lane = tid & 63;
+  // wave-uniform, so that per-wave addresses (LDS DMA destinations) live in SGPRs
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int col = lane & 31, h = lane >> 5;
   const int64_t wg0 = wb * (kMainWaves * NB * 32);
   int32_t* lab_w = lds_lab + wave * NB * 32;
@@ -733,7 +734,7 @@ __global__ __launch_bounds__(256, DPX > 144 ? 1 : (TC == 32 ? 3 : 2)) void k_mai
 
   constexpr int64_t ROWS = kMainWaves * NB * 32;
   const int64_t wb = blockIdx.x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   // the first tiles' latency overlaps the prologue
   issue_first<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, wave, lane);
   const RowPre<NB> pre = fetch_rows<NB>(a, wb * ROWS + wave * NB * 32, lane);
@@ -767,7 +768,8 @@ __device__ __forceinline__ void main_f32_body(const MainArgs& a, int64_t wb, con
   using R = f32_ring<DPX, NS_MAX>;
   constexpr int ARGW = SAVE ? NB * 32 : 1;
 
-  const int wave = tid >> 6, lane = tid & 63;
+  // wave-uniform, so that per-wave addresses (LDS DMA destinations) live in SGPRs
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int col = lane & 31, h = lane >> 5;
   const int64_t wg0 = wb * (kMainWaves * NB * 32);
 
@@ -849,7 +851,7 @@ __global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_f32(MainArgs a)
   __shared__ double lds_bsum[kMainWaves];
   constexpr int64_t ROWS = kMainWaves * NB * 32;
   const int64_t wb = blockIdx.x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   // the first tiles' latency overlaps the prologue
   issue_first<R>(static_cast<const char*>(a.btab), a.piece * 4, a.ntiles, ring0, ring1, wave, lane);
   const RowPre<NB> pre = fetch_rows<NB>(a, wb * ROWS + wave * NB * 32, lane);
