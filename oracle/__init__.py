@@ -62,8 +62,9 @@ def _load():
     lib.orc_brute_silhouette.argtypes = common + [P, P]
     lib.orc_brute_scores_at.argtypes = common + [P, I64, P, P, P]
     lib.orc_gradient.argtypes = common + [P]
+    lib.orc_kmeans_step.argtypes = [P, I, P, P, I64, I32, I32, P, P, P, P]
     for f in ("orc_cluster_stats", "orc_scores_at", "orc_silhouette", "orc_brute_silhouette",
-              "orc_brute_scores_at", "orc_gradient", "orc_num_threads"):
+              "orc_brute_scores_at", "orc_gradient", "orc_kmeans_step", "orc_num_threads"):
         getattr(lib, f).restype = ctypes.c_int
     lib.orc_decode_bf16.argtypes = [ctypes.c_uint16]
     lib.orc_decode_bf16.restype = ctypes.c_double
@@ -171,6 +172,19 @@ def gradient(X, labels, K, metric="sqeuclid", col_scale=None):
     dX = np.zeros((N, D))
     _check(_load().orc_gradient(_ptr(X), dt, _ptr(cs), _ptr(labels), N, D, K, m, _ptr(dX)))
     return dX
+
+
+def kmeans_step(X, labels, K, col_scale=None):
+    """One Lloyd step (means from `labels`, then nearest non-empty mean, lowest id on ties),
+    binary64: (new labels int32[N], inertia, d1 f64[N] distance to the chosen mean, d2 f64[N]
+    next smallest distance, +inf when there is none)."""
+    X, dt, cs, labels, N, D, K, _ = _prep(X, labels, K, "sqeuclid", col_scale)
+    out = np.zeros(N, np.int32)
+    inertia = np.zeros(1)
+    d1, d2 = np.zeros(N), np.zeros(N)
+    _check(_load().orc_kmeans_step(_ptr(X), dt, _ptr(cs), _ptr(labels), N, D, K, _ptr(out),
+                                   _ptr(inertia), _ptr(d1), _ptr(d2)))
+    return out, float(inertia[0]), d1, d2
 
 
 def decode_bf16(bits: int) -> float:

@@ -612,6 +612,80 @@ done:
   return rc;
 }
 
+/* ---------------------------------------------------------------------------------------- */
+/* K-means (Lloyd) step                                                                      */
+
+/*
+ * The Introduction names K-Means among the clustering methods whose output the Silhouette
+ * evaluates.  One Lloyd step on given labels, written out from its textbook definition:
+ *   update:  mu_k = Y_k / N_k for every non-empty cluster, Y_k and N_k as in Eq.8;
+ *   assign:  each point goes to the non-empty cluster with the smallest squared Euclidean
+ *            distance sum_l (x_l - mu_kl)^2, the lowest id on ties; empty clusters stay empty.
+ * d1[i] is the distance to the chosen mean, d2[i] the next smallest one over the other
+ * non-empty clusters (+inf when there is none); *inertia = sum_i d1[i] in increasing i.
+ * d1 and d2 may be NULL.  At least one cluster must be non-empty (always true for N >= 1).
+ */
+int orc_kmeans_step(const void* X, int dtype, const float* col_scale, const int32_t* labels,
+                    int64_t N, int32_t D, int32_t K, int32_t* labels_out, double* inertia,
+                    double* d1, double* d2) {
+  int rc = orc_check_args(X, dtype, col_scale, labels, N, D, K, ORC_SQEUCLID);
+  if (rc) return rc;
+  if (!labels_out || !inertia) return ORC_E_ARG;
+  int64_t* count = (int64_t*)malloc(sizeof(int64_t) * (size_t)K);
+  double* V = (double*)malloc(sizeof(double) * (size_t)K * (size_t)D);
+  double* psi = (double*)malloc(sizeof(double) * (size_t)K);
+  double* dist = (double*)malloc(sizeof(double) * (size_t)N);
+  if (!count || !V || !psi || !dist) { rc = ORC_E_NOMEM; goto done; }
+  rc = orc_cluster_stats(X, dtype, col_scale, labels, N, D, K, ORC_SQEUCLID, count, V, psi);
+  if (rc) goto done;
+  for (int32_t k = 0; k < K; ++k)  /* the means replace the sums in place */
+    if (count[k] > 0)
+      for (int32_t l = 0; l < D; ++l) V[(int64_t)k * D + l] /= (double)count[k];
+  int bad = 0;
+#pragma omp parallel
+  {
+    double* x = (double*)malloc(sizeof(double) * (size_t)D);
+    if (!x) {
+#pragma omp atomic write
+      bad = 1;
+    } else {
+#pragma omp for schedule(static)
+      for (int64_t i = 0; i < N; ++i) {
+        orc_row(X, dtype, col_scale, i, D, x);
+        double best = INFINITY, second = INFINITY;
+        int32_t arg = -1;
+        for (int32_t k = 0; k < K; ++k) {
+          if (count[k] == 0) continue;
+          double d = 0.0;
+          for (int32_t l = 0; l < D; ++l) {
+            const double t = x[l] - V[(int64_t)k * D + l];
+            d += t * t;
+          }
+          if (d < best) {
+            second = best;
+            best = d;
+            arg = k;
+          } else if (d < second) {
+            second = d;
+          }
+        }
+        labels_out[i] = arg;
+        dist[i] = best;
+        if (d1) d1[i] = best;
+        if (d2) d2[i] = second;
+      }
+      free(x);
+    }
+  }
+  if (bad) { rc = ORC_E_NOMEM; goto done; }
+  double tot = 0.0;
+  for (int64_t i = 0; i < N; ++i) tot += dist[i];
+  *inertia = tot;
+done:
+  free(count); free(V); free(psi); free(dist);
+  return rc;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();
