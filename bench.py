@@ -50,6 +50,97 @@ def measured_traffic(kernel, workload):
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
+def bench_kmeans(args, spec, X, col_scale, labels, dev):
+    """One K-means (Lloyd) step per timed step: the means of the workload's labels, then every
+    point's nearest mean, into a separate output so that every step does the same work."""
+    import numpy as np
+    import torch
+
+    from paper_2303_14102_amd import _lib
+    from paper_2303_14102_amd import binding as sil
+    from paper_2303_14102_amd import workloads as wl
+    lib = _lib.load()
+    ws = sil.new_workspace(spec.n, spec.d, spec.k, "sqeuclid", X.dtype, 0, dev)
+    out = torch.empty(spec.n, dtype=torch.int32, device=dev)
+    inertia = torch.empty((), dtype=torch.float64, device=dev)
+    dcode, stream, cs_ptr = sil._dtype_code(X), sil._stream(dev), sil._ptr(col_scale)
+
+    def step():
+        rc = lib.silhouette_kmeans_step(sil._ptr(X), dcode, cs_ptr, sil._ptr(labels), spec.n, spec.d,
+                                        spec.k, 0, 0, sil._ptr(out), sil._ptr(inertia), sil._ptr(ws),
+                                        ws.numel(), stream)
+        if rc:
+            raise _lib.SilhouetteError(rc, "kmeans step")
+
+    log(f"timing the K-means step ({args.form}): warmup {args.warmup}, steps {args.steps}")
+    ms, phases, wall = timed_steps(step, args.steps, args.warmup, torch)
+    _lib.check(sil.status(ws), "device status")
+    moved = int((out != labels).sum().item())
+    log(f"kmeans: {ms:.3f} ms/step, phases {['%.3f' % p for p in phases]}, inertia {inertia.item():.6e}, "
+        f"moved {moved}")
+    useful = 2.0 * spec.n * spec.d * spec.k
+    t_main = phases[2] * 1e-3
+    prods = 1 if args.form == "f32" else 3
+    peak = PEAK["fp32"] if args.form == "f32" else PEAK["bf16"]
+    kname = "k_main_f32" if args.form == "f32" else "k_main_bf16"
+    res = {
+        "metric": "K-means (Lloyd) step points/s at D=128,K=1000; bf16-MFMA",
+        "value": spec.n / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"bf16": "bf16", "fp8": "fp8e4m3", "f32": "f32"}[args.form],
+        "data": "synthetic",
+        "config": {"workload": spec.name, "n": spec.n, "d": spec.d, "k": spec.k, "storage": args.form,
+                   "products": prods if args.form != "f32" else None, "centred": True, "kmeans_step": True},
+        "phases_ms": {"stats": phases[0], "finalize": phases[1], "gemm_argmin": phases[2], "reduce": phases[3]},
+        "inertia": inertia.item(), "moved_points": moved,
+        "roofline": {"bound": "mfma", "achieved": useful / t_main / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": useful / t_main / peak, "traffic": None, "kernel": kname,
+                     "issued_frac": useful * prods / t_main / peak,
+                     "note": "achieved = 2*N*D*K useful flops / mean duration of the fused argmin kernel"},
+    }
+    if not args.no_check or not args.no_cpu:
+        import oracle
+        host_codes = wl.host_codes(X)
+        labels_host = labels.cpu().numpy()
+        cs_host = None if col_scale is None else col_scale.cpu().numpy()
+    if not args.no_check:
+        # FP64 means of all rows, then the nearest mean of sampled points in binary64
+        t0 = time.perf_counter()
+        count, V, _ = oracle.cluster_stats(host_codes, labels_host, spec.k, "sqeuclid", col_scale=cs_host)
+        ne = count > 0
+        mu = V[ne] / count[ne, None]
+        ids = np.nonzero(ne)[0]
+        idx = np.sort(np.random.default_rng(7).choice(spec.n, size=256, replace=False))
+        codes = np.ascontiguousarray(host_codes[idx])
+        if codes.dtype == np.uint16:    # bf16 bit patterns
+            xs = (codes.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        elif codes.dtype == np.uint8:   # fp8 e4m3fn codes times the column scale (exact)
+            xs = torch.from_numpy(codes).view(torch.float8_e4m3fn).double().numpy() * cs_host.astype(np.float64)
+        else:
+            xs = codes.astype(np.float64)
+        d = ((xs[:, None, :] - mu[None, :, :]) ** 2).sum(axis=2)
+        best = d.min(axis=1)
+        got = out.cpu().numpy()[idx]
+        pos = np.searchsorted(ids, got)
+        ok = (pos < len(ids)) & (ids[np.minimum(pos, len(ids) - 1)] == got)
+        d_got = np.where(ok, d[np.arange(len(idx)), np.minimum(pos, len(ids) - 1)], np.inf)
+        res["check"] = {"sampled_points": int(len(idx)),
+                        "label_equals_fp64_argmin": float((ids[d.argmin(axis=1)] == got).mean()),
+                        "max_rel_excess_distance": float(((d_got - best) / np.maximum(best, 1e-30)).max()),
+                        "oracle_stats_s": time.perf_counter() - t0}
+        log(f"check: {res['check']}")
+    if not args.no_cpu:
+        n = min(args.cpu_sample, spec.n)
+        t0 = time.perf_counter()
+        oracle.kmeans_step(np.ascontiguousarray(host_codes[:n]), np.ascontiguousarray(labels_host[:n]), spec.k,
+                           col_scale=cs_host)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": n / dt, "unit": "points/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"first {n} rows of {spec.name} "
+                               f"({host_codes.dtype} storage), FP64 oracle K-means step, {dt:.1f} s"}
+    print(json.dumps(res), flush=True)
+
+
 def stats_kernel(args, spec):
     """Name of the statistics pass's reduction kernel for this run: whole-wave rows for squared
     Euclidean fp32 / bf16 rows of 256, 512 or 1024 bytes, 16-byte chunks otherwise."""
@@ -68,6 +159,8 @@ def parse():
     ap.add_argument("--metric", default="sqeuclid", choices=["sqeuclid", "cosine"])
     ap.add_argument("--form", default="bf16", choices=["bf16", "fp8", "f32"])
     ap.add_argument("--products", type=int, default=3)
+    ap.add_argument("--kmeans", action="store_true",
+                    help="time one K-means (Lloyd) step on the workload instead of the Silhouette")
     ap.add_argument("--euclid-approx", action="store_true",
                     help="the approximate Euclidean form (square roots of the mean squared distances)")
     ap.add_argument("--fp32-steps", type=int, default=4)
@@ -242,6 +335,9 @@ def main():
         X = X32
     torch.cuda.synchronize()
     log(f"generated in {time.perf_counter() - t0:.1f} s")
+
+    if args.kmeans:
+        return bench_kmeans(args, spec, X, col_scale, labels, dev)
 
     ws = sil.new_workspace(spec.n, spec.d, spec.k, args.metric, X.dtype, 0, dev)
     s = torch.empty(spec.n, dtype=torch.float32, device=dev)

@@ -132,6 +132,30 @@ int silhouette_cosine_backward(const void* X, int32_t dtype, const float* col_sc
                                size_t ws_bytes, void* stream);
 
 /*
+ * One K-means (Lloyd) step, the producer of the labels that the Silhouette evaluates (the paper's
+ * Introduction names K-Means among the clustering methods whose output it scores).  It runs on the
+ * same passes as silhouette_sqeuclid:
+ *   update   the mean of every non-empty cluster of `labels`, mu_k = Y_k / N_k (Eq.8 sums);
+ *   assign   labels_out[i] = the non-empty cluster whose mean is nearest to x_i in squared
+ *            Euclidean distance, the lowest id on ties (empty clusters stay empty);
+ *   inertia  *inertia = sum_i ||x_i - mu_{labels_out[i]}||^2, reduced in FP64 in a fixed order.
+ *   labels_out  device, int32 [N]; may be the same buffer as `labels` (the labels are read only
+ *               by the statistics pass, before any label is written)
+ *   inertia     device, float64 [1]
+ *   products    0 or 3 (bf16 / fp8 storage run the BF16x3 form; ignored for fp32)
+ *   flags       0 or SIL_FLAG_NO_CENTRE
+ * The distances are formed like the forward call's (centred, split products, fp32 accumulation),
+ * so a point whose two nearest means lie within that rounding of each other may take either.
+ * Workspace: silhouette_workspace_bytes(N, D, K, SIL_SQEUCLID, dtype, flags).  Errors: as
+ * silhouette_sqeuclid, except that one non-empty cluster suffices; on a device-detected error
+ * every labels_out[i] becomes -1 and the inertia NaN.
+ */
+int silhouette_kmeans_step(const void* X, int32_t dtype, const float* col_scale,
+                           const int32_t* labels, int64_t N, int32_t D, int32_t K,
+                           int32_t products, int32_t flags, int32_t* labels_out, double* inertia,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Only the per-cluster statistics pass (one pass over X; Eq.5, Eq.6, Eq.8 for the squared
  * Euclidean distance, Eq.15-16 for cosine), copied out of the workspace:
  *   count  device, int32 [K]        N_k

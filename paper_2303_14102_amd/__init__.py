@@ -4,5 +4,5 @@ The computation lives in the HIP library libsilhouette.so behind the C ABI of
 include/silhouette.h; ``silhouette`` and ``cluster_stats`` are thin torch-facing bindings.
 """
 
-from .binding import (BatchedSilhouette, SilhouetteFn, cluster_stats, silhouette,  # noqa: F401
-                      silhouette_backward, status, workspace_bytes)
+from .binding import (BatchedSilhouette, SilhouetteFn, cluster_stats, kmeans_step,  # noqa: F401
+                      silhouette, silhouette_backward, status, workspace_bytes)

@@ -106,6 +106,29 @@ def cluster_stats(X: torch.Tensor, labels: torch.Tensor, K: int, metric: str = "
     return count, V, psi
 
 
+def kmeans_step(X: torch.Tensor, labels: torch.Tensor, K: int, *, products: int = 0,
+                centre: bool = True, col_scale: Optional[torch.Tensor] = None,
+                labels_out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                check_status: bool = False):
+    """One K-means (Lloyd) step: (new labels int32 [N], inertia float64 0-d tensor), both on the
+    device.  labels_out may be `labels` itself (an in-place step)."""
+    _check_inputs(X, labels, col_scale)
+    N, D = X.shape
+    flags = 0 if centre else L.SIL_FLAG_NO_CENTRE
+    if workspace is None:
+        workspace = new_workspace(N, D, K, "sqeuclid", X.dtype, flags, X.device)
+    if labels_out is None:
+        labels_out = torch.empty(N, dtype=torch.int32, device=X.device)
+    inertia = torch.empty((), dtype=torch.float64, device=X.device)
+    rc = L.load().silhouette_kmeans_step(_ptr(X), _dtype_code(X), _ptr(col_scale), _ptr(labels), N, D,
+                                         int(K), int(products), flags, _ptr(labels_out), _ptr(inertia),
+                                         _ptr(workspace), workspace.numel(), _stream(X.device))
+    L.check(rc, "silhouette_kmeans_step")
+    if check_status:
+        L.check(status(workspace), "silhouette_kmeans_step (device)")
+    return labels_out, inertia
+
+
 def status(workspace: torch.Tensor) -> int:
     """First device-detected error of the last call on this workspace (waits for the stream)."""
     return L.load().silhouette_status(_ptr(workspace), _stream(workspace.device))

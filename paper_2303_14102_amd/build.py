@@ -12,8 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsilhouette.so")
-SOURCES = ["main_batched.hip", "main_f32.hip", "main_bf16.hip", "main_fp8.hip", "api.hip", "stats.hip",
-           "finalize.hip", "main.hip", "backward.hip", "batched.hip"]
+SOURCES = ["main_batched.hip", "main_f32.hip", "main_bf16.hip", "main_fp8.hip", "main_assign.hip",
+           "api.hip", "stats.hip", "finalize.hip", "main.hip", "backward.hip", "batched.hip"]
 ARCH = os.environ.get("SIL_OFFLOAD_ARCH", "gfx950")
 
 

@@ -144,6 +144,39 @@ static int forward(int32_t metric, const void* X, int32_t dtype, const float* co
   return SIL_OK;
 }
 
+// One K-means (Lloyd) step on the same passes: the statistics and tables of the given labels
+// (the means), then the fused kernel with the argmin over every cluster.  Phases are recorded
+// like a forward call's.
+static int kmeans(const void* X, int32_t dtype, const float* col_scale, const int32_t* labels,
+                  int64_t N, int32_t D, int32_t K, int32_t products, int32_t flags,
+                  int32_t* labels_out, double* inertia, void* ws, size_t ws_bytes, void* stream) {
+  if (flags & ~SIL_FLAG_NO_CENTRE) return SIL_E_ARG;
+  WsLayout L;
+  int rc = check_common(X, dtype, col_scale, labels, N, D, K, SIL_SQEUCLID, ws, ws_bytes, flags,
+                        &L);
+  if (rc) return rc;
+  if (!labels_out || !inertia) return SIL_E_ARG;
+  if (products != 0 && products != 3) return SIL_E_ARG;
+  const WsPtrs w = carve(L, ws);
+  const int64_t nblocks = ceil_div(N, main_rows_per_block(dtype, L.DPX, 3));
+  Problem p{X, col_scale, labels, N, D, L.DPX, K, L.Kpad, dtype, SIL_SQEUCLID, 3, flags, nullptr,
+            inertia, nblocks};
+  p.labels_out = labels_out;
+  p.assign = 1;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int call = g_prof.on && g_prof.used < g_prof.cap ? g_prof.used++ : -1;
+  prof_record(call, 0, st);
+  if (launch_stats(p, L, w, st) != hipSuccess) return SIL_E_HIP;
+  prof_record(call, 1, st);
+  if (launch_finalize(p, L, w, st) != hipSuccess) return SIL_E_HIP;
+  prof_record(call, 2, st);
+  if (launch_main(p, L, w, st) != hipSuccess) return SIL_E_HIP;
+  prof_record(call, 3, st);
+  if (launch_reduce(p, L, w, st) != hipSuccess) return SIL_E_HIP;
+  prof_record(call, 4, st);
+  return SIL_OK;
+}
+
 static int backward(int32_t metric, const void* X, int32_t dtype, const float* col_scale,
                     const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t flags,
                     const double* gS, float* dX, void* ws, size_t ws_bytes, void* stream) {
@@ -227,6 +260,14 @@ int silhouette_cosine_backward(const void* X, int32_t dtype, const float* col_sc
                                size_t ws_bytes, void* stream) {
   return backward(SIL_COSINE, X, dtype, col_scale, labels, N, D, K, flags & ~SIL_FLAG_NO_CENTRE,
                   gS, dX, ws, ws_bytes, stream);
+}
+
+int silhouette_kmeans_step(const void* X, int32_t dtype, const float* col_scale,
+                           const int32_t* labels, int64_t N, int32_t D, int32_t K,
+                           int32_t products, int32_t flags, int32_t* labels_out, double* inertia,
+                           void* ws, size_t ws_bytes, void* stream) {
+  return kmeans(X, dtype, col_scale, labels, N, D, K, products, flags, labels_out, inertia, ws,
+                ws_bytes, stream);
 }
 
 int silhouette_cluster_stats(const void* X, int32_t dtype, const float* col_scale,

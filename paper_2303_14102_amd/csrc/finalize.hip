@@ -78,7 +78,7 @@ __device__ __forceinline__ void finalize_body(
     const int32_t* __restrict__ count, const double* __restrict__ V,
     const double* __restrict__ psi, const double* __restrict__ gmean, int32_t K, int32_t Kpad,
     int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ atab,
-    float* __restrict__ avec, float* __restrict__ ascale, int64_t bid) {
+    float* __restrict__ avec, float* __restrict__ ascale, int with_var, int64_t bid) {
   constexpr double ALPHA = METRIC == SIL_SQEUCLID ? -2.0 : -1.0;
   const int lane = threadIdx.x & 63;
   const int32_t k = static_cast<int32_t>(bid) * 4 + (threadIdx.x >> 6);
@@ -119,7 +119,9 @@ __device__ __forceinline__ void finalize_body(
     if (n > 0) {
       if (METRIC == SIL_SQEUCLID) {
         const double sigma2 = fmax(0.0, psi[k] / dn - mu2);
-        c = muc2 + sigma2;  // equals Psi_k/N_k when the centring vector is zero
+        // equals Psi_k/N_k when the centring vector is zero; without the variance term the GEMM
+        // form gives ||x' - mu'_k||^2, the K-means assignment's distance
+        c = with_var ? muc2 + sigma2 : muc2;
         av = sigma2;
       } else {
         c = 1.0;
@@ -149,9 +151,9 @@ __global__ __launch_bounds__(256) void k_finalize(
     const int32_t* __restrict__ count, const double* __restrict__ V,
     const double* __restrict__ psi, const double* __restrict__ gmean, int32_t K, int32_t Kpad,
     int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ atab,
-    float* __restrict__ avec, float* __restrict__ ascale) {
+    float* __restrict__ avec, float* __restrict__ ascale, int with_var) {
   finalize_body<METRIC, BF16TAB>(count, V, psi, gmean, K, Kpad, D, DPX, RS, btab, atab, avec,
-                                 ascale, blockIdx.x);
+                                 ascale, with_var, blockIdx.x);
 }
 
 hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
@@ -163,7 +165,7 @@ hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w,
 #define SIL_FIN(MT, BF)                                                                        \
   k_finalize<MT, BF><<<nb, 256, 0, st>>>(w.count, w.V, w.psi, w.gmean, p.K, p.Kpad, p.D, p.DPX, \
                                          table_stride(p.DPX, p.dtype), w.btab, w.atab, w.avec,  \
-                                         w.ascale)
+                                         w.ascale, p.assign ? 0 : 1)
   if (p.metric == SIL_SQEUCLID) {
     if (bf) SIL_FIN(SIL_SQEUCLID, true);
     else SIL_FIN(SIL_SQEUCLID, false);
@@ -202,10 +204,10 @@ __global__ __launch_bounds__(256) void kb_fin(BatchDev b) {
   const int32_t RS = table_stride(q.DPX, SIL_F32);
   if (q.metric == SIL_SQEUCLID)
     finalize_body<SIL_SQEUCLID, false>(q.count, q.V, q.psi, q.gmean, q.K, q.Kpad, q.D, q.DPX, RS,
-                                       q.btab, q.atab, q.avec, q.ascale, it);
+                                       q.btab, q.atab, q.avec, q.ascale, 1, it);
   else
     finalize_body<SIL_COSINE, false>(q.count, q.V, q.psi, q.gmean, q.K, q.Kpad, q.D, q.DPX, RS,
-                                     q.btab, q.atab, q.avec, q.ascale, it);
+                                     q.btab, q.atab, q.avec, q.ascale, 1, it);
 }
 
 hipError_t launch_finalize_batched(const BatchLaunch& b, hipStream_t st) {

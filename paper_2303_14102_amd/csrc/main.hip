@@ -33,19 +33,21 @@ __global__ __launch_bounds__(1024) void k_reduce1(const double* __restrict__ bpa
   reduce1_body(bpart, nb, chunk, out, blockIdx.x);
 }
 
+// mean: S = sum / N (the Silhouette); otherwise the sum itself (the K-means inertia)
 __device__ __forceinline__ void reduce2_body(const double* __restrict__ part, int n, int64_t N,
                                              const int32_t* __restrict__ hdr,
-                                             double* __restrict__ S) {
+                                             double* __restrict__ S, int mean) {
   __shared__ double sh[1024];
   const double v = static_cast<int>(threadIdx.x) < n ? part[threadIdx.x] : 0.0;
   const double tot = block_sum_1024(v, sh);
-  if (threadIdx.x == 0) *S = hdr[0] != 0 ? __builtin_nan("") : tot / static_cast<double>(N);
+  if (threadIdx.x == 0)
+    *S = hdr[0] != 0 ? __builtin_nan("") : (mean ? tot / static_cast<double>(N) : tot);
 }
 
 __global__ __launch_bounds__(1024) void k_reduce2(const double* __restrict__ part, int n,
                                                   int64_t N, const int32_t* __restrict__ hdr,
-                                                  double* __restrict__ S) {
-  reduce2_body(part, n, N, hdr, S);
+                                                  double* __restrict__ S, int mean) {
+  reduce2_body(part, n, N, hdr, S, mean);
 }
 
 __device__ __forceinline__ void poison_body(const int32_t* __restrict__ hdr, float* __restrict__ s,
@@ -57,6 +59,15 @@ __device__ __forceinline__ void poison_body(const int32_t* __restrict__ hdr, flo
 
 __global__ void k_poison(const int32_t* __restrict__ hdr, float* __restrict__ s, int64_t N) {
   poison_body(hdr, s, N, blockIdx.x, gridDim.x);
+}
+
+// K-means step: every label becomes -1 when the workspace holds an error
+__global__ void k_poison_labels(const int32_t* __restrict__ hdr, int32_t* __restrict__ lab,
+                                int64_t N) {
+  if (hdr[0] == 0) return;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride)
+    lab[i] = -1;
 }
 
 int main_rows_per_block(int dtype, int DPX, int products) {
@@ -89,8 +100,15 @@ hipError_t launch_main(const Problem& p, const WsLayout& L, const WsPtrs& w, hip
   m.save_a = w.save_a;
   m.save_b = w.save_b;
   m.save_n = w.save_n;
+  m.labels_out = p.labels_out;
+  m.assign = p.assign;
   const unsigned grid = static_cast<unsigned>(p.nblocks);
-  if (p.dtype == SIL_F32) {
+  if (p.assign) {
+    if (p.dtype == SIL_F32)
+      launch_main_f32(m, p.DPX, SIL_SQEUCLID, true, grid, st);
+    else
+      launch_main_assign(m, p.DPX, p.dtype, grid, st);
+  } else if (p.dtype == SIL_F32) {
     launch_main_f32(m, p.DPX, p.metric, (p.flags & SIL_FLAG_SAVE_FOR_GRAD) != 0, grid, st);
   } else if (p.dtype == SIL_BF16) {
     launch_main_bf16(m, p.DPX, p.metric, p.products, grid, st);
@@ -111,8 +129,9 @@ hipError_t launch_reduce(const Problem& p, const WsLayout& L, const WsPtrs& w, h
   int32_t n1;
   reduce_split(p.nblocks, &chunk, &n1);
   k_reduce1<<<static_cast<unsigned>(n1), 1024, 0, st>>>(w.bpart, p.nblocks, chunk, w.bpart2);
-  k_reduce2<<<1, 1024, 0, st>>>(w.bpart2, n1, p.N, w.hdr, p.S);
+  k_reduce2<<<1, 1024, 0, st>>>(w.bpart2, n1, p.N, w.hdr, p.S, p.assign ? 0 : 1);
   if (p.s) k_poison<<<1024, 256, 0, st>>>(w.hdr, p.s, p.N);
+  if (p.labels_out) k_poison_labels<<<1024, 256, 0, st>>>(w.hdr, p.labels_out, p.N);
   return hipGetLastError();
 }
 
@@ -138,7 +157,7 @@ __global__ __launch_bounds__(1024) void kb_red1(BatchDev b) {
 __global__ __launch_bounds__(1024) void kb_red2(BatchDev b) {
   int64_t it;
   const BatchProblem& q = batch_item_red(b, BP_RED2, &it);
-  reduce2_body(q.bpart2, q.red_n1, q.N, q.hdr, q.S);
+  reduce2_body(q.bpart2, q.red_n1, q.N, q.hdr, q.S, 1);
 }
 
 __global__ __launch_bounds__(256) void kb_poison(BatchDev b) {

@@ -64,6 +64,10 @@ struct MainArgs {
   float* save_a;
   float* save_b;
   int32_t* save_n;
+  // K-means assignment (kernels with the argmin, SAVE): no own-cluster exclusion, the nearest
+  // mean's id goes to labels_out[row] and the squared distance to it into the block sum
+  int32_t* labels_out = nullptr;
+  int32_t assign = 0;
 };
 
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
@@ -202,6 +206,10 @@ __device__ __forceinline__ void make_blocks(const MainArgs& a, const RowPre<NB>&
     B.mixed[nb] = !__all(o == o0 || o < 0);
     B.town[nb] = o0 >> 5;
     B.cown[nb] = o0 & 31;
+    if (a.assign) {  // the minimum runs over every cluster, the own one included
+      B.mixed[nb] = false;
+      B.town[nb] = -1;
+    }
     if (lane < 32) lds_lab[nb * 32 + r] = o;  // labels of the block for the mixed-block path
   }
 }
@@ -452,6 +460,13 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Bloc
     float b = lds_min[nb * 32 + r];
     if constexpr (METRIC == SIL_SQEUCLID) b += nrow[nb];
     b = fmaxf(b, 0.0f);
+    if constexpr (SAVE) {
+      if (a.assign) {  // K-means assignment: nearest mean and the squared distance to it
+        a.labels_out[row] = lds_arg[nb * 32 + r];
+        bsum += static_cast<double>(b);
+        continue;
+      }
+    }
     float av = fmaxf(arow[nb], 0.0f);
     if (METRIC == SIL_SQEUCLID && a.root) {  // the mean distances' square roots
       b = sqrtf(b);
@@ -868,6 +883,8 @@ void launch_main_f32(const MainArgs& m, int DPX, int metric, bool save, unsigned
                      hipStream_t st);
 void launch_main_bf16(const MainArgs& m, int DPX, int metric, int products, unsigned grid,
                       hipStream_t st);
+// K-means assignment with bf16 MFMA (X stored bf16 or fp8), three products, squared Euclidean
+void launch_main_assign(const MainArgs& m, int DPX, int dtype, unsigned grid, hipStream_t st);
 void launch_main_fp8(const MainArgs& m, int DPX, int metric, int products, unsigned grid,
                      hipStream_t st);
 

@@ -126,6 +126,10 @@ struct Problem {
   float* s;
   double* S;
   int64_t nblocks;  // workgroups of the fused kernel for this call
+  // K-means step: the nearest mean of every row over all non-empty clusters goes to labels_out,
+  // and S receives the sum of the squared distances to it
+  int32_t* labels_out = nullptr;
+  int assign = 0;
 };
 
 // zero the small workspace regions; histogram, scan, scatter, segmented reduction, combine

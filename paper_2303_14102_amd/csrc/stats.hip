@@ -108,10 +108,10 @@ __global__ __launch_bounds__(256) void k_hist(const int32_t* __restrict__ labels
 }
 
 // Exclusive prefix of the cluster sizes, scatter cursors, number of valid points and of
-// non-empty clusters.  One workgroup of 1024 threads.
+// non-empty clusters (fewer than min_nonempty is an error).  One workgroup of 1024 threads.
 __device__ __forceinline__ void scan_body(const int32_t* __restrict__ count, int32_t K,
                                           int32_t* __restrict__ offset, int32_t* __restrict__ cursor,
-                                          int32_t* __restrict__ hdr) {
+                                          int32_t* __restrict__ hdr, int min_nonempty) {
   __shared__ int32_t part[1024];
   __shared__ int32_t nz[1024];
   const int t = threadIdx.x;
@@ -144,15 +144,15 @@ __device__ __forceinline__ void scan_body(const int32_t* __restrict__ count, int
     offset[K] = part[1023];
     hdr[1] = part[1023];
     hdr[2] = nz[1023];
-    if (nz[1023] < 2) set_status(hdr, SIL_E_FEW_CLUSTERS);
+    if (nz[1023] < min_nonempty) set_status(hdr, SIL_E_FEW_CLUSTERS);
   }
 }
 
 __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count, int32_t K,
                                                int32_t* __restrict__ offset,
                                                int32_t* __restrict__ cursor,
-                                               int32_t* __restrict__ hdr) {
-  scan_body(count, K, offset, cursor, hdr);
+                                               int32_t* __restrict__ hdr, int min_nonempty) {
+  scan_body(count, K, offset, cursor, hdr, min_nonempty);
 }
 
 // Scatter row ids into their cluster's range of the sorted order.
@@ -686,7 +686,8 @@ hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hi
   const unsigned nchunk = static_cast<unsigned>(ceil_div(p.N, kChunk));
   const size_t lds = p.K <= kLdsHistMaxK ? static_cast<size_t>(p.K) * 4 : 0;
   k_hist<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.count, w.hdr);
-  k_scan<<<1, 1024, 0, st>>>(w.count, p.K, w.offset, w.cursor, w.hdr);
+  // the Silhouette needs a neighbouring cluster; a K-means step needs one non-empty cluster
+  k_scan<<<1, 1024, 0, st>>>(w.count, p.K, w.offset, w.cursor, w.hdr, p.assign ? 1 : 2);
   k_scatter<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.cursor, w.perm, w.lsorted);
   const unsigned nblk = static_cast<unsigned>(ceil_div(L.nseg, 4));
   // 16-byte chunks when a row splits into a power-of-two number of them
@@ -755,7 +756,7 @@ __global__ __launch_bounds__(256) void kb_hist(BatchDev b) {
 __global__ __launch_bounds__(1024) void kb_scan(BatchDev b) {
   int64_t it;
   const BatchProblem& q = batch_item(b, BP_SCAN, &it);
-  scan_body(q.count, q.K, q.offset, q.cursor, q.hdr);
+  scan_body(q.count, q.K, q.offset, q.cursor, q.hdr, 2);
 }
 
 __global__ __launch_bounds__(256) void kb_scatter(BatchDev b) {

@@ -103,3 +103,19 @@ def storage(X32: torch.Tensor, form: str):
         return q, None, wl.host_codes(q)
     q, sc = wl.to_fp8_e4m3(X32)
     return q, sc, wl.host_codes(q)
+
+
+def kmeans_dist_bound(form, centre, X, labels, K):
+    """Per-point bound on |d~(x_i, mu_k) - d(x_i, mu_k)| for the K-means assignment's squared
+    distance ||x'||^2 + ||mu'_k||^2 - 2 x'.mu'_k, formed like the Silhouette's b-path (cross term
+    to relative accuracy eps, fp32 rounding of the sum), with the means of the given labels."""
+    X = np.asarray(X, np.float64)
+    D = X.shape[1]
+    ids = np.unique(labels)
+    mu = np.stack([X[labels == k].mean(axis=0) for k in ids])
+    m = X.mean(axis=0) if centre else np.zeros(D)
+    xp, mup = X - m, mu - m
+    nx = np.linalg.norm(xp, axis=1)
+    nmu = np.linalg.norm(mup, axis=1)
+    eps = cross_term_eps(form, 3, "sqeuclid", centre, D)
+    return 2 * eps * nx * nmu.max() + 4 * U32 * (nx ** 2 + (nmu ** 2).max())

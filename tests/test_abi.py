@@ -85,6 +85,22 @@ def test_host_argument_errors_launch_nothing(lib):
         assert bw(fake, 0, None, fake, 10, 4, 2, _lib.SIL_FLAG_EUCLID_APPROX, fake, fake, ws, 1 << 30, None) == -1
 
 
+def test_kmeans_host_checks(lib):
+    from paper_2303_14102_amd import _lib
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x100000)
+    f = lib.silhouette_kmeans_step
+    # (X, dtype, col_scale, labels, N, D, K, products, flags, labels_out, inertia, ws, bytes, stream)
+    assert f(fake, 0, None, fake, 10, 4, 2, 0, _lib.SIL_FLAG_SAVE_FOR_GRAD, fake, fake, ws, 1 << 30, None) == -1
+    assert f(fake, 0, None, fake, 10, 4, 2, 0, _lib.SIL_FLAG_EUCLID_APPROX, fake, fake, ws, 1 << 30, None) == -1
+    assert f(fake, 1, None, fake, 10, 4, 2, 2, 0, fake, fake, ws, 1 << 30, None) == -1   # products
+    assert f(fake, 0, None, fake, 10, 4, 2, 0, 0, None, fake, ws, 1 << 30, None) == -1   # labels_out
+    assert f(fake, 0, None, fake, 10, 4, 2, 0, 0, fake, None, ws, 1 << 30, None) == -1   # inertia
+    assert f(fake, 0, None, fake, 10, 4, 1, 0, 0, fake, fake, ws, 1 << 30, None) == -1   # K
+    assert f(fake, 2, None, fake, 10, 4, 2, 0, 0, fake, fake, ws, 1 << 30, None) == -2   # fp8 w/o scale
+    assert f(fake, 0, None, fake, 10, 4, 2, 0, 0, fake, fake, ws, 16, None) == -7        # workspace
+
+
 def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, 99):
         assert isinstance(lib.silhouette_strerror(code), bytes)
