@@ -141,6 +141,71 @@ def bench_kmeans(args, spec, X, col_scale, labels, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_stream(args, spec, X, col_scale, labels, dev):
+    """Out-of-core form: X and labels moved to pinned host memory (the device copy is freed), then
+    every step streams them through the device twice in chunks.  The rate includes the PCIe
+    transfers; it is not the device-resident rate of the default line."""
+    import torch
+
+    from paper_2303_14102_amd import _lib
+    from paper_2303_14102_amd import binding as sil
+    lib = _lib.load()
+    metric = sil.METRIC[args.metric]
+    ws_mem = sil.new_workspace(spec.n, spec.d, spec.k, args.metric, X.dtype, 0, dev)
+    S_mem = torch.empty((), dtype=torch.float64, device=dev)
+    fn_c = lib.silhouette_sqeuclid if args.metric == "sqeuclid" else lib.silhouette_cosine
+    _lib.check(fn_c(sil._ptr(X), sil._dtype_code(X), sil._ptr(col_scale), sil._ptr(labels), spec.n, spec.d,
+                    spec.k, args.products, 0, None, sil._ptr(S_mem), sil._ptr(ws_mem), ws_mem.numel(),
+                    sil._stream(dev)), "in-memory reference")
+    S_ref = S_mem.item()
+    del ws_mem
+    log("moving X and labels to pinned host memory")
+    Xh = torch.empty(X.shape, dtype=X.dtype, pin_memory=True)
+    Xh.copy_(X)
+    lh = torch.empty(spec.n, dtype=torch.int32, pin_memory=True)
+    lh.copy_(labels)
+    dcode = sil._dtype_code(X)
+    del X, labels
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    chunk = min(args.chunk_rows, spec.n)
+    ws = torch.empty(sil.stream_workspace_bytes(spec.n, chunk, spec.d, spec.k, args.metric, Xh.dtype),
+                     dtype=torch.uint8, device=dev)
+    sh = torch.empty(spec.n, dtype=torch.float32, pin_memory=True)
+    S = torch.empty((), dtype=torch.float64, device=dev)
+    stream, cs_ptr = sil._stream(dev), sil._ptr(col_scale)
+
+    def step():
+        rc = lib.silhouette_stream(metric, ctypes.c_void_p(Xh.data_ptr()), dcode, cs_ptr,
+                                   ctypes.c_void_p(lh.data_ptr()), spec.n, spec.d, spec.k, args.products, 0,
+                                   ctypes.c_void_p(sh.data_ptr()), sil._ptr(S), chunk, sil._ptr(ws), ws.numel(),
+                                   stream)
+        if rc:
+            raise _lib.SilhouetteError(rc, "stream step")
+
+    log(f"timing the out-of-core form: chunk {chunk} rows, warmup {args.warmup}, steps {args.steps}")
+    ms, _, wall = timed_steps(step, args.steps, args.warmup, torch)
+    _lib.check(sil.status(ws), "device status")
+    esz = Xh.element_size()
+    h2d = 2 * (spec.n * spec.d * esz + 4 * spec.n)
+    d2h = 4 * spec.n
+    res = {
+        "metric": "Out-of-core Silhouette points/s at D=128,K=1000 (X in pinned host memory, PCIe-inclusive)",
+        "value": spec.n / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"bf16": "bf16", "fp8": "fp8e4m3", "f32": "f32"}[args.form],
+        "data": "synthetic",
+        "config": {"workload": spec.name, "n": spec.n, "d": spec.d, "k": spec.k, "metric": args.metric,
+                   "storage": args.form, "products": args.products if args.form != "f32" else None,
+                   "chunk_rows": chunk, "device_workspace_gb": ws.numel() / 1e9,
+                   "host_bytes_gb": (Xh.numel() * esz + 4 * spec.n) / 1e9},
+        "S": S.item(), "dS_vs_in_memory": abs(S.item() - S_ref),
+        "transfer": {"h2d_bytes": h2d, "d2h_bytes": d2h, "h2d_GBps": h2d / (ms * 1e-3) / 1e9,
+                     "note": "X and labels cross PCIe twice (statistics pass, then scoring pass)"},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def stats_kernel(args, spec):
     """Name of the statistics pass's reduction kernel for this run: whole-wave rows for squared
     Euclidean fp32 / bf16 rows of 256, 512 or 1024 bytes, 16-byte chunks otherwise."""
@@ -159,6 +224,9 @@ def parse():
     ap.add_argument("--metric", default="sqeuclid", choices=["sqeuclid", "cosine"])
     ap.add_argument("--form", default="bf16", choices=["bf16", "fp8", "f32"])
     ap.add_argument("--products", type=int, default=3)
+    ap.add_argument("--stream", action="store_true",
+                    help="out-of-core: X and labels in pinned host memory, streamed in chunks")
+    ap.add_argument("--chunk-rows", type=int, default=4_000_000)
     ap.add_argument("--kmeans", action="store_true",
                     help="time one K-means (Lloyd) step on the workload instead of the Silhouette")
     ap.add_argument("--euclid-approx", action="store_true",
@@ -338,6 +406,9 @@ def main():
 
     if args.kmeans:
         return bench_kmeans(args, spec, X, col_scale, labels, dev)
+    if args.stream:
+        del X32, blobs
+        return bench_stream(args, spec, X, col_scale, labels, dev)
 
     ws = sil.new_workspace(spec.n, spec.d, spec.k, args.metric, X.dtype, 0, dev)
     s = torch.empty(spec.n, dtype=torch.float32, device=dev)

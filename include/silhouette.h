@@ -156,6 +156,39 @@ int silhouette_kmeans_step(const void* X, int32_t dtype, const float* col_scale,
                            void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Out-of-core evaluation for data sets larger than device memory.  Section II notes that the
+ * quadratic method needs the whole data set on every machine; Section III-A computes the cluster
+ * statistics first and then scores every point independently, so a device need only hold a share
+ * of the points plus the statistics.  X and labels stay in host memory and are streamed through
+ * two device chunk buffers of `chunk_rows` rows, twice: pass 1 accumulates every chunk's
+ * statistics into FP64 global sums (in chunk order), pass 2 scores every chunk against the
+ * tables of the whole data set.  The result equals silhouette_sqeuclid / silhouette_cosine on
+ * the same data up to the order of the FP64 cluster sums.
+ *   metric       SIL_SQEUCLID or SIL_COSINE
+ *   X_host       host, [N, D] in `dtype`; pinned (hipHostMalloc) for the uploads to overlap the
+ *                kernels, pageable memory works but serialises them
+ *   col_scale    device, float32 [D] (fp8 only)
+ *   labels_host  host, int32 [N]
+ *   s_host       host, float32 [N], or NULL
+ *   S            device, float64 [1]
+ *   chunk_rows   rows per chunk (>= 1; clamped to N)
+ *   flags        SIL_FLAG_NO_CENTRE, SIL_FLAG_EUCLID_APPROX (squared Euclidean only)
+ *   ws           device, silhouette_stream_workspace_bytes(...) bytes, 256-byte aligned: one
+ *                chunk's workspace, the two chunk buffers and the global sums
+ * The call enqueues the work and returns: the host buffers must stay valid and unchanged (and
+ * s_host unread) until `stream` has completed.  Uploads run on a copy stream the library creates
+ * once per device (default priority, kept until the process ends); events order it against
+ * `stream`.  Concurrent calls on one device are serialised while they enqueue.  Errors: as
+ * silhouette_sqeuclid (silhouette_status reads the whole data set's status from `ws`).
+ */
+size_t silhouette_stream_workspace_bytes(int64_t N, int64_t chunk_rows, int32_t D, int32_t K,
+                                         int32_t metric, int32_t dtype, int32_t flags);
+int silhouette_stream(int32_t metric, const void* X_host, int32_t dtype, const float* col_scale,
+                      const int32_t* labels_host, int64_t N, int32_t D, int32_t K,
+                      int32_t products, int32_t flags, float* s_host, double* S,
+                      int64_t chunk_rows, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Only the per-cluster statistics pass (one pass over X; Eq.5, Eq.6, Eq.8 for the squared
  * Euclidean distance, Eq.15-16 for cosine), copied out of the workspace:
  *   count  device, int32 [K]        N_k

@@ -5,4 +5,5 @@ include/silhouette.h; ``silhouette`` and ``cluster_stats`` are thin torch-facing
 """
 
 from .binding import (BatchedSilhouette, SilhouetteFn, cluster_stats, kmeans_step,  # noqa: F401
-                      silhouette, silhouette_backward, status, workspace_bytes)
+                      silhouette, silhouette_backward, silhouette_stream, status,
+                      stream_workspace_bytes, workspace_bytes)

@@ -129,6 +129,54 @@ def kmeans_step(X: torch.Tensor, labels: torch.Tensor, K: int, *, products: int 
     return labels_out, inertia
 
 
+def stream_workspace_bytes(N: int, chunk_rows: int, D: int, K: int, metric: str = "sqeuclid",
+                           dtype=torch.float32, flags: int = 0) -> int:
+    code = {torch.float32: L.SIL_F32, torch.bfloat16: L.SIL_BF16,
+            torch.float8_e4m3fn: L.SIL_FP8_E4M3}[dtype]
+    n = L.load().silhouette_stream_workspace_bytes(N, chunk_rows, D, K, METRIC[metric], code, flags)
+    if n == 0:
+        raise ValueError(f"shape out of range: N={N} chunk_rows={chunk_rows} D={D} K={K}")
+    return n
+
+
+def silhouette_stream(X_host: torch.Tensor, labels_host: torch.Tensor, K: int, metric: str = "sqeuclid", *,
+                      chunk_rows: int, products: int = 0, centre: bool = True,
+                      col_scale: Optional[torch.Tensor] = None, want_s: bool = True,
+                      euclid_approx: bool = False, workspace: Optional[torch.Tensor] = None,
+                      device: Optional[torch.device] = None, sync: bool = True, check_status: bool = False):
+    """Out-of-core evaluation: X_host [N, D] and labels_host int32 [N] stay in host memory (pinned for
+    the uploads to overlap the kernels) and are streamed in chunks of `chunk_rows` rows.  Returns
+    (s float32 [N] in pinned host memory or None, S float64 0-d tensor on the device).  With
+    sync=False the call returns after enqueueing: the host tensors must then be kept alive and
+    unchanged until the current stream completes."""
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    if X_host.device.type != "cpu" or labels_host.device.type != "cpu":
+        raise ValueError("X_host and labels_host must be host tensors")
+    if X_host.dim() != 2 or not X_host.is_contiguous():
+        raise ValueError("X_host must be a contiguous [N, D] tensor")
+    if labels_host.dtype != torch.int32 or labels_host.shape != (X_host.shape[0],) or not labels_host.is_contiguous():
+        raise ValueError("labels_host must be a contiguous int32 [N] tensor")
+    if X_host.dtype == torch.float8_e4m3fn and (col_scale is None or col_scale.device != device):
+        raise ValueError("fp8 X needs a float32 [D] col_scale on the device")
+    N, D = X_host.shape
+    flags = ((0 if centre else L.SIL_FLAG_NO_CENTRE) | (L.SIL_FLAG_EUCLID_APPROX if euclid_approx else 0))
+    if workspace is None:
+        nbytes = stream_workspace_bytes(N, chunk_rows, D, K, metric, X_host.dtype, flags)
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    s = torch.empty(N, dtype=torch.float32, pin_memory=True) if want_s else None
+    S = torch.empty((), dtype=torch.float64, device=device)
+    rc = L.load().silhouette_stream(METRIC[metric], ctypes.c_void_p(X_host.data_ptr()), _dtype_code(X_host),
+                                    _ptr(col_scale), ctypes.c_void_p(labels_host.data_ptr()), N, D, int(K),
+                                    int(products), flags, _ptr(s), _ptr(S), int(chunk_rows), _ptr(workspace),
+                                    workspace.numel(), _stream(device))
+    L.check(rc, "silhouette_stream")
+    if sync:
+        torch.cuda.current_stream(device).synchronize()
+    if check_status:
+        L.check(status(workspace), "silhouette_stream (device)")
+    return s, S
+
+
 def status(workspace: torch.Tensor) -> int:
     """First device-detected error of the last call on this workspace (waits for the stream)."""
     return L.load().silhouette_status(_ptr(workspace), _stream(workspace.device))

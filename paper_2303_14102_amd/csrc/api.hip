@@ -82,7 +82,7 @@ WsPtrs carve(const WsLayout& L, void* ws) {
   return w;
 }
 
-static bool shape_ok(int64_t N, int32_t D, int32_t K) {
+bool shape_ok(int64_t N, int32_t D, int32_t K) {
   return N >= 1 && N <= INT32_MAX && D >= 1 && D <= kMaxD && K >= 2 && K <= kMaxK;
 }
 
@@ -163,6 +163,7 @@ static int kmeans(const void* X, int32_t dtype, const float* col_scale, const in
             inertia, nblocks};
   p.labels_out = labels_out;
   p.assign = 1;
+  p.min_nonempty = 1;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int call = g_prof.on && g_prof.used < g_prof.cap ? g_prof.used++ : -1;
   prof_record(call, 0, st);

@@ -129,7 +129,7 @@ hipError_t launch_reduce(const Problem& p, const WsLayout& L, const WsPtrs& w, h
   int32_t n1;
   reduce_split(p.nblocks, &chunk, &n1);
   k_reduce1<<<static_cast<unsigned>(n1), 1024, 0, st>>>(w.bpart, p.nblocks, chunk, w.bpart2);
-  k_reduce2<<<1, 1024, 0, st>>>(w.bpart2, n1, p.N, w.hdr, p.S, p.assign ? 0 : 1);
+  k_reduce2<<<1, 1024, 0, st>>>(w.bpart2, n1, p.N, w.hdr, p.S, (p.assign || p.reduce_sum) ? 0 : 1);
   if (p.s) k_poison<<<1024, 256, 0, st>>>(w.hdr, p.s, p.N);
   if (p.labels_out) k_poison_labels<<<1024, 256, 0, st>>>(w.hdr, p.labels_out, p.N);
   return hipGetLastError();

@@ -109,6 +109,7 @@ struct WsPtrs {
 };
 
 WsPtrs carve(const WsLayout& L, void* ws);
+bool shape_ok(int64_t N, int32_t D, int32_t K);
 
 // Status codes written into hdr[0] by kernels (first error wins).
 __device__ inline void set_status(int32_t* hdr, int32_t code) { atomicCAS(hdr, 0, code); }
@@ -130,10 +131,16 @@ struct Problem {
   // and S receives the sum of the squared distances to it
   int32_t* labels_out = nullptr;
   int assign = 0;
+  // fewer non-empty clusters than this is an error of the statistics pass (0: never)
+  int min_nonempty = 2;
+  // the reduction returns the sum of the block partials rather than their mean
+  int reduce_sum = 0;
 };
 
 // zero the small workspace regions; histogram, scan, scatter, segmented reduction, combine
 hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st);
+// the counting sort alone (zero, histogram, scan, scatter): perm and sorted labels, no sums
+hipError_t launch_sort(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st);
 // global mean, per-cluster tables
 hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st);
 // fused GEMM + epilogue, then the fixed-order reduction of S

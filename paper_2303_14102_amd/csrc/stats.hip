@@ -677,6 +677,19 @@ static void launch_seg_row(const Problem& p, const WsLayout& L, const WsPtrs& w,
   }
 }
 
+hipError_t launch_sort(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
+  const int64_t words = static_cast<int64_t>((L.perm - L.hdr) / 4);
+  const int64_t zblocks = ceil_div(words, 256) < 2048 ? ceil_div(words, 256) : 2048;
+  k_fill_zero<<<static_cast<unsigned>(zblocks), 256, 0, st>>>(
+      reinterpret_cast<uint32_t*>(w.hdr), words);
+  const unsigned nchunk = static_cast<unsigned>(ceil_div(p.N, kChunk));
+  const size_t lds = p.K <= kLdsHistMaxK ? static_cast<size_t>(p.K) * 4 : 0;
+  k_hist<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.count, w.hdr);
+  k_scan<<<1, 1024, 0, st>>>(w.count, p.K, w.offset, w.cursor, w.hdr, p.min_nonempty);
+  k_scatter<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.cursor, w.perm, w.lsorted);
+  return hipGetLastError();
+}
+
 hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
   // zero: header .. segpart are contiguous in the layout; zero [hdr, perm)
   const int64_t words = static_cast<int64_t>((L.perm - L.hdr) / 4);
@@ -687,7 +700,7 @@ hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hi
   const size_t lds = p.K <= kLdsHistMaxK ? static_cast<size_t>(p.K) * 4 : 0;
   k_hist<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.count, w.hdr);
   // the Silhouette needs a neighbouring cluster; a K-means step needs one non-empty cluster
-  k_scan<<<1, 1024, 0, st>>>(w.count, p.K, w.offset, w.cursor, w.hdr, p.assign ? 1 : 2);
+  k_scan<<<1, 1024, 0, st>>>(w.count, p.K, w.offset, w.cursor, w.hdr, p.min_nonempty);
   k_scatter<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.cursor, w.perm, w.lsorted);
   const unsigned nblk = static_cast<unsigned>(ceil_div(L.nseg, 4));
   // 16-byte chunks when a row splits into a power-of-two number of them

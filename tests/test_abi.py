@@ -101,6 +101,29 @@ def test_kmeans_host_checks(lib):
     assert f(fake, 0, None, fake, 10, 4, 2, 0, 0, fake, fake, ws, 16, None) == -7        # workspace
 
 
+def test_stream_host_checks(lib):
+    from paper_2303_14102_amd import _lib
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x100000)
+    f = lib.silhouette_stream
+    # (metric, X, dtype, col_scale, labels, N, D, K, products, flags, s, S, chunk, ws, bytes, stream)
+    assert f(0, fake, 0, None, fake, 100, 4, 2, 0, 0, None, fake, 0, ws, 1 << 30, None) == -1     # chunk
+    assert f(0, None, 0, None, fake, 100, 4, 2, 0, 0, None, fake, 10, ws, 1 << 30, None) == -1    # X
+    assert f(0, fake, 0, None, fake, 100, 4, 2, 0, 0, None, None, 10, ws, 1 << 30, None) == -1    # S
+    assert f(2, fake, 0, None, fake, 100, 4, 2, 0, 0, None, fake, 10, ws, 1 << 30, None) == -1    # metric
+    assert f(1, fake, 0, None, fake, 100, 4, 2, 0, _lib.SIL_FLAG_EUCLID_APPROX, None, fake, 10, ws, 1 << 30,
+             None) == -1
+    assert f(0, fake, 0, None, fake, 100, 4, 2, 0, _lib.SIL_FLAG_SAVE_FOR_GRAD, None, fake, 10, ws, 1 << 30,
+             None) == -1
+    assert f(0, fake, 2, None, fake, 100, 4, 2, 0, 0, None, fake, 10, ws, 1 << 30, None) == -2    # fp8 scale
+    assert f(0, fake, 0, None, fake, 100, 4, 2, 0, 0, None, fake, 10, ws, 16, None) == -7         # workspace
+    sz = lib.silhouette_stream_workspace_bytes
+    assert sz(100, 0, 4, 2, 0, 0, 0) == 0
+    a, b = sz(10_000, 1_000, 8, 4, 0, 0, 0), sz(10_000, 2_000, 8, 4, 0, 0, 0)
+    assert 0 < a < b  # two chunk buffers grow with the chunk
+    assert sz(10_000, 20_000, 8, 4, 0, 0, 0) == sz(10_000, 10_000, 8, 4, 0, 0, 0)  # clamped to N
+
+
 def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, 99):
         assert isinstance(lib.silhouette_strerror(code), bytes)
