@@ -63,8 +63,11 @@ def _load():
     lib.orc_brute_scores_at.argtypes = common + [P, I64, P, P, P]
     lib.orc_gradient.argtypes = common + [P]
     lib.orc_kmeans_step.argtypes = [P, I, P, P, I64, I32, I32, P, P, P, P]
+    lib.orc_silhouette_mahalanobis.argtypes = [P, I, P, P, P, I64, I32, I32, P, P, P, P]
+    lib.orc_brute_silhouette_mahalanobis.argtypes = [P, I, P, P, P, I64, I32, I32, P, P]
     for f in ("orc_cluster_stats", "orc_scores_at", "orc_silhouette", "orc_brute_silhouette",
-              "orc_brute_scores_at", "orc_gradient", "orc_kmeans_step", "orc_num_threads"):
+              "orc_brute_scores_at", "orc_gradient", "orc_kmeans_step", "orc_silhouette_mahalanobis",
+              "orc_brute_silhouette_mahalanobis", "orc_num_threads"):
         getattr(lib, f).restype = ctypes.c_int
     lib.orc_decode_bf16.argtypes = [ctypes.c_uint16]
     lib.orc_decode_bf16.restype = ctypes.c_double
@@ -172,6 +175,35 @@ def gradient(X, labels, K, metric="sqeuclid", col_scale=None):
     dX = np.zeros((N, D))
     _check(_load().orc_gradient(_ptr(X), dt, _ptr(cs), _ptr(labels), N, D, K, m, _ptr(dX)))
     return dX
+
+
+def _metric_matrix(M, D):
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    if M.shape != (D, D):
+        raise ValueError("M must be [D, D]")
+    return M
+
+
+def silhouette_mahalanobis(X, labels, K, M, col_scale=None, details=False):
+    """The linear method under d(x, y) = (x - y)^T M (x - y), binary64: (s f64[N], S) or, with
+    details, also a, b."""
+    X, dt, cs, labels, N, D, K, _ = _prep(X, labels, K, "sqeuclid", col_scale)
+    M = _metric_matrix(M, D)
+    s, S = np.zeros(N), np.zeros(1)
+    a, b = np.zeros(N), np.zeros(N)
+    _check(_load().orc_silhouette_mahalanobis(_ptr(X), dt, _ptr(cs), _ptr(M), _ptr(labels), N, D, K,
+                                              _ptr(s), _ptr(S), _ptr(a), _ptr(b)))
+    return (s, float(S[0]), a, b) if details else (s, float(S[0]))
+
+
+def brute_silhouette_mahalanobis(X, labels, K, M, col_scale=None):
+    """The quadratic definition under the same distance, binary64: (s f64[N], S)."""
+    X, dt, cs, labels, N, D, K, _ = _prep(X, labels, K, "sqeuclid", col_scale)
+    M = _metric_matrix(M, D)
+    s, S = np.zeros(N), np.zeros(1)
+    _check(_load().orc_brute_silhouette_mahalanobis(_ptr(X), dt, _ptr(cs), _ptr(M), _ptr(labels), N, D, K,
+                                                    _ptr(s), _ptr(S)))
+    return s, float(S[0])
 
 
 def kmeans_step(X, labels, K, col_scale=None):

@@ -613,6 +613,144 @@ done:
 }
 
 /* ---------------------------------------------------------------------------------------- */
+/* fixed-matrix Mahalanobis distance                                                         */
+
+/*
+ * Section V notes that a similar approach may serve other metrics.  For
+ *   d(x, y) = (x - y)^T M (x - y),   M [D, D] fixed, symmetric positive semi-definite,
+ * expanding the quadratic form as Eq.9-11 expand the squared Euclidean distance gives the mean
+ * distance from x to cluster k (self included, Eq.3) from per-cluster statistics alone:
+ *   m(x, k) = x^T M x + PsiM_k / N_k - 2 x^T M Y_k / N_k,   PsiM_k = sum_{y in k} y^T M y,
+ * with Y_k the plain vector sums of Eq.8.  a_i, b_i and s_i then follow orc_point_score with the
+ * readings of the squared Euclidean distance (M = I gives exactly that distance).
+ */
+static double orc_quad(const double* M, const double* x, int32_t D) {
+  double q = 0.0;
+  for (int32_t r = 0; r < D; ++r) {
+    double t = 0.0;
+    for (int32_t c = 0; c < D; ++c) t += M[(int64_t)r * D + c] * x[c];
+    q += x[r] * t;
+  }
+  return q;
+}
+
+int orc_silhouette_mahalanobis(const void* X, int dtype, const float* col_scale, const double* M,
+                               const int32_t* labels, int64_t N, int32_t D, int32_t K, double* s,
+                               double* S, double* a, double* b) {
+  int rc = orc_check_args(X, dtype, col_scale, labels, N, D, K, ORC_SQEUCLID);
+  if (rc) return rc;
+  if (!M || !s || !S) return ORC_E_ARG;
+  int64_t* count = (int64_t*)calloc((size_t)K, sizeof(int64_t));
+  double* Y = (double*)calloc((size_t)K * (size_t)D, sizeof(double));
+  double* psi = (double*)calloc((size_t)K, sizeof(double));
+  double* x = (double*)malloc(sizeof(double) * (size_t)D);
+  if (!count || !Y || !psi || !x) { rc = ORC_E_NOMEM; goto done; }
+  /* statistics: N_k, Y_k (Eq.8) and PsiM_k, one pass in increasing row order */
+  for (int64_t i = 0; i < N; ++i) {
+    int32_t k = labels[i];
+    if (k < 0 || k >= K) { rc = ORC_E_LABEL; goto done; }
+    orc_row(X, dtype, col_scale, i, D, x);
+    for (int32_t l = 0; l < D; ++l)
+      if (!isfinite(x[l])) { rc = ORC_E_NONFINITE; goto done; }
+    count[k] += 1;
+    for (int32_t l = 0; l < D; ++l) Y[(int64_t)k * D + l] += x[l];
+    psi[k] += orc_quad(M, x, D);
+  }
+  if (orc_nonempty(count, K) < 2) { rc = ORC_E_FEW_CLUSTERS; goto done; }
+  int bad = 0;
+#pragma omp parallel
+  {
+    double* xl = (double*)malloc(sizeof(double) * (size_t)D);
+    double* Mx = (double*)malloc(sizeof(double) * (size_t)D);
+    double* m = (double*)malloc(sizeof(double) * (size_t)K);
+    if (!xl || !Mx || !m) {
+#pragma omp atomic write
+      bad = 1;
+    } else {
+#pragma omp for schedule(static)
+      for (int64_t i = 0; i < N; ++i) {
+        orc_row(X, dtype, col_scale, i, D, xl);
+        double xmx = 0.0;
+        for (int32_t r = 0; r < D; ++r) {
+          double t = 0.0;
+          for (int32_t c = 0; c < D; ++c) t += M[(int64_t)r * D + c] * xl[c];
+          Mx[r] = t;
+          xmx += xl[r] * t;
+        }
+        for (int32_t k = 0; k < K; ++k) {
+          if (count[k] == 0) { m[k] = NAN; continue; }
+          double dot = 0.0;
+          for (int32_t l = 0; l < D; ++l) dot += Mx[l] * Y[(int64_t)k * D + l];
+          const double nk = (double)count[k];
+          m[k] = xmx + psi[k] / nk - 2.0 * dot / nk;
+        }
+        s[i] = orc_point_score(m, K, labels[i], count, 0, a ? &a[i] : NULL, b ? &b[i] : NULL, NULL);
+      }
+    }
+    free(xl); free(Mx); free(m);
+  }
+  if (bad) { rc = ORC_E_NOMEM; goto done; }
+  {
+    double tot = 0.0;
+    for (int64_t i = 0; i < N; ++i) tot += s[i];
+    *S = tot / (double)N;
+  }
+done:
+  free(count); free(Y); free(psi); free(x);
+  return rc;
+}
+
+/* The quadratic definition under the same distance: every pair's (x_i - x_j)^T M (x_i - x_j). */
+int orc_brute_silhouette_mahalanobis(const void* X, int dtype, const float* col_scale,
+                                     const double* M, const int32_t* labels, int64_t N, int32_t D,
+                                     int32_t K, double* s, double* S) {
+  int rc = orc_check_args(X, dtype, col_scale, labels, N, D, K, ORC_SQEUCLID);
+  if (rc) return rc;
+  if (!M || !s || !S) return ORC_E_ARG;
+  double* Xd = (double*)malloc(sizeof(double) * (size_t)N * (size_t)D);
+  int64_t* count = (int64_t*)calloc((size_t)K, sizeof(int64_t));
+  if (!Xd || !count) { rc = ORC_E_NOMEM; goto done; }
+  for (int64_t i = 0; i < N; ++i) {
+    if (labels[i] < 0 || labels[i] >= K) { rc = ORC_E_LABEL; goto done; }
+    orc_row(X, dtype, col_scale, i, D, Xd + i * (int64_t)D);
+    count[labels[i]] += 1;
+  }
+  if (orc_nonempty(count, K) < 2) { rc = ORC_E_FEW_CLUSTERS; goto done; }
+  int bad = 0;
+#pragma omp parallel
+  {
+    double* sum = (double*)malloc(sizeof(double) * (size_t)K);
+    double* diff = (double*)malloc(sizeof(double) * (size_t)D);
+    double* m = (double*)malloc(sizeof(double) * (size_t)K);
+    if (!sum || !diff || !m) {
+#pragma omp atomic write
+      bad = 1;
+    } else {
+#pragma omp for schedule(static)
+      for (int64_t i = 0; i < N; ++i) {
+        for (int32_t k = 0; k < K; ++k) sum[k] = 0.0;
+        for (int64_t j = 0; j < N; ++j) {
+          for (int32_t l = 0; l < D; ++l) diff[l] = Xd[i * D + l] - Xd[j * D + l];
+          sum[labels[j]] += orc_quad(M, diff, D);
+        }
+        for (int32_t k = 0; k < K; ++k) m[k] = count[k] ? sum[k] / (double)count[k] : NAN;
+        s[i] = orc_point_score(m, K, labels[i], count, 0, NULL, NULL, NULL);
+      }
+    }
+    free(sum); free(diff); free(m);
+  }
+  if (bad) { rc = ORC_E_NOMEM; goto done; }
+  {
+    double tot = 0.0;
+    for (int64_t i = 0; i < N; ++i) tot += s[i];
+    *S = tot / (double)N;
+  }
+done:
+  free(Xd); free(count);
+  return rc;
+}
+
+/* ---------------------------------------------------------------------------------------- */
 /* K-means (Lloyd) step                                                                      */
 
 /*
