@@ -141,6 +141,56 @@ def bench_kmeans(args, spec, X, col_scale, labels, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_mahalanobis(args, spec, X, col_scale, labels, dev):
+    """Silhouette under d(x, y) = (x - y)^T L^T L (x - y) with a seeded random L = I + G / sqrt(D):
+    the transform Z = X L^T on fp32 MFMA, then the fp32 squared Euclidean form on Z."""
+    import numpy as np
+    import torch
+
+    from paper_2303_14102_amd import _lib
+    from paper_2303_14102_amd import binding as sil
+    lib = _lib.load()
+    rng = np.random.default_rng(11)
+    Lm = torch.from_numpy((np.eye(spec.d) + rng.standard_normal((spec.d, spec.d)) / np.sqrt(spec.d))
+                          .astype(np.float32)).to(dev)
+    nbytes = lib.silhouette_mahalanobis_workspace_bytes(spec.n, spec.d, spec.k, 0)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    s = torch.empty(spec.n, dtype=torch.float32, device=dev)
+    S = torch.empty((), dtype=torch.float64, device=dev)
+    dcode, stream, cs_ptr = sil._dtype_code(X), sil._stream(dev), sil._ptr(col_scale)
+
+    def step():
+        rc = lib.silhouette_mahalanobis(sil._ptr(X), dcode, cs_ptr, sil._ptr(Lm), sil._ptr(labels), spec.n,
+                                        spec.d, spec.k, 0, sil._ptr(s), sil._ptr(S), sil._ptr(ws), ws.numel(),
+                                        stream)
+        if rc:
+            raise _lib.SilhouetteError(rc, "mahalanobis step")
+
+    log(f"timing the Mahalanobis form ({args.form} storage): warmup {args.warmup}, steps {args.steps}")
+    ms, phases, _ = timed_steps(step, args.steps, args.warmup, torch)
+    zb = (spec.n * spec.d * 4 + 255) // 256 * 256
+    _lib.check(sil.status(ws[zb:]), "device status")
+    useful = 2.0 * spec.n * spec.d * spec.k
+    t_main = phases[2] * 1e-3
+    transform_ms = ms - sum(phases)
+    res = {
+        "metric": "Mahalanobis Silhouette points/s at D=128,K=1000 (fixed M = L^T L; fp32 MFMA transform and form)",
+        "value": spec.n / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": spec.name, "n": spec.n, "d": spec.d, "k": spec.k, "storage": args.form,
+                   "metric": "mahalanobis", "L": "I + N(0,1)/sqrt(D), seed 11"},
+        "phases_ms": {"transform": transform_ms, "stats": phases[0], "finalize": phases[1],
+                      "gemm_epilogue": phases[2], "reduce": phases[3]},
+        "S": S.item(),
+        "roofline": {"bound": "mfma", "achieved": useful / t_main / 1e12, "peak": PEAK["fp32"] / 1e12,
+                     "unit": "TFLOP/s", "frac": useful / t_main / PEAK["fp32"], "traffic": None,
+                     "kernel": "k_main_f32",
+                     "transform_TFLOPs": 2.0 * spec.n * spec.d * spec.d / (transform_ms * 1e-3) / 1e12},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def bench_stream(args, spec, X, col_scale, labels, dev):
     """Out-of-core form: X and labels moved to pinned host memory (the device copy is freed), then
     every step streams them through the device twice in chunks.  The rate includes the PCIe
@@ -227,6 +277,8 @@ def parse():
     ap.add_argument("--stream", action="store_true",
                     help="out-of-core: X and labels in pinned host memory, streamed in chunks")
     ap.add_argument("--chunk-rows", type=int, default=4_000_000)
+    ap.add_argument("--mahalanobis", action="store_true",
+                    help="the Silhouette under a fixed Mahalanobis distance (M = L^T L, random L)")
     ap.add_argument("--kmeans", action="store_true",
                     help="time one K-means (Lloyd) step on the workload instead of the Silhouette")
     ap.add_argument("--euclid-approx", action="store_true",
@@ -406,6 +458,8 @@ def main():
 
     if args.kmeans:
         return bench_kmeans(args, spec, X, col_scale, labels, dev)
+    if args.mahalanobis:
+        return bench_mahalanobis(args, spec, X, col_scale, labels, dev)
     if args.stream:
         del X32, blobs
         return bench_stream(args, spec, X, col_scale, labels, dev)

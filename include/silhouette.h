@@ -156,6 +156,25 @@ int silhouette_kmeans_step(const void* X, int32_t dtype, const float* col_scale,
                            void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Silhouette under a fixed-matrix Mahalanobis distance d(x, y) = (x - y)^T M (x - y), M = L^T L
+ * (Section V notes that a similar approach serves other metrics).  The distance is the squared
+ * Euclidean distance between L x and L y, so Eq.11 applies to the transformed points: the call
+ * forms Z = X L^T once in fp32 (MFMA) inside the workspace, then runs the squared Euclidean
+ * Silhouette on Z in fp32.
+ *   L      device, float32 [D, D] row-major (any real matrix; M = L^T L is positive
+ *          semi-definite, rank-deficient allowed)
+ *   flags  0 or SIL_FLAG_NO_CENTRE
+ *   ws     device, silhouette_mahalanobis_workspace_bytes(N, D, K, flags) bytes: Z, then a
+ *          squared Euclidean fp32 workspace
+ * Other arguments, outputs and errors as silhouette_sqeuclid (a non-finite L shows as a
+ * non-finite value of the data).
+ */
+size_t silhouette_mahalanobis_workspace_bytes(int64_t N, int32_t D, int32_t K, int32_t flags);
+int silhouette_mahalanobis(const void* X, int32_t dtype, const float* col_scale, const float* L,
+                           const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t flags,
+                           float* s, double* S, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Out-of-core evaluation for data sets larger than device memory.  Section II notes that the
  * quadratic method needs the whole data set on every machine; Section III-A computes the cluster
  * statistics first and then scores every point independently, so a device need only hold a share

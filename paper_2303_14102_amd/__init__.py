@@ -5,5 +5,5 @@ include/silhouette.h; ``silhouette`` and ``cluster_stats`` are thin torch-facing
 """
 
 from .binding import (BatchedSilhouette, SilhouetteFn, cluster_stats, kmeans_step,  # noqa: F401
-                      silhouette, silhouette_backward, silhouette_stream, status,
+                      silhouette, silhouette_backward, silhouette_mahalanobis, silhouette_stream, status,
                       stream_workspace_bytes, workspace_bytes)

@@ -33,6 +33,8 @@ SIGNATURES = {
     "silhouette_cluster_stats": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
     "silhouette_stream_workspace_bytes": (_SZ, [_I64, _I64, _I32, _I32, _I32, _I32, _I32]),
     "silhouette_stream": (ctypes.c_int, [_I32, _P, _I32, _P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P, _I64, _P, _SZ, _P]),
+    "silhouette_mahalanobis_workspace_bytes": (_SZ, [_I64, _I32, _I32, _I32]),
+    "silhouette_mahalanobis": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I64, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "silhouette_kmeans_step": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "silhouette_status": (ctypes.c_int, [_P, _P]),
     "silhouette_strerror": (ctypes.c_char_p, [ctypes.c_int]),

@@ -129,6 +129,34 @@ def kmeans_step(X: torch.Tensor, labels: torch.Tensor, K: int, *, products: int 
     return labels_out, inertia
 
 
+def silhouette_mahalanobis(X: torch.Tensor, labels: torch.Tensor, K: int, L_mat: torch.Tensor, *,
+                           centre: bool = True, col_scale: Optional[torch.Tensor] = None, want_s: bool = True,
+                           workspace: Optional[torch.Tensor] = None, check_status: bool = False):
+    """Silhouette under d(x, y) = (x - y)^T M (x - y) with M = L_mat^T L_mat (L_mat float32 [D, D] on the
+    device): (s float32 [N] or None, S float64 0-d tensor)."""
+    _check_inputs(X, labels, col_scale)
+    N, D = X.shape
+    if L_mat.dtype != torch.float32 or L_mat.shape != (D, D) or L_mat.device != X.device:
+        raise ValueError("L_mat must be a float32 [D, D] tensor on the device of X")
+    L_mat = L_mat.contiguous()
+    flags = 0 if centre else L.SIL_FLAG_NO_CENTRE
+    if workspace is None:
+        nbytes = L.load().silhouette_mahalanobis_workspace_bytes(N, D, int(K), flags)
+        if nbytes == 0:
+            raise ValueError(f"shape out of range: N={N} D={D} K={K}")
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+    s = torch.empty(N, dtype=torch.float32, device=X.device) if want_s else None
+    S = torch.empty((), dtype=torch.float64, device=X.device)
+    rc = L.load().silhouette_mahalanobis(_ptr(X), _dtype_code(X), _ptr(col_scale), _ptr(L_mat), _ptr(labels),
+                                         N, D, int(K), flags, _ptr(s), _ptr(S), _ptr(workspace),
+                                         workspace.numel(), _stream(X.device))
+    L.check(rc, "silhouette_mahalanobis")
+    if check_status:
+        zb = (N * D * 4 + 255) // 256 * 256
+        L.check(status(workspace[zb:]), "silhouette_mahalanobis (device)")
+    return s, S
+
+
 def stream_workspace_bytes(N: int, chunk_rows: int, D: int, K: int, metric: str = "sqeuclid",
                            dtype=torch.float32, flags: int = 0) -> int:
     code = {torch.float32: L.SIL_F32, torch.bfloat16: L.SIL_BF16,

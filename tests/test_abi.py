@@ -124,6 +124,22 @@ def test_stream_host_checks(lib):
     assert sz(10_000, 20_000, 8, 4, 0, 0, 0) == sz(10_000, 10_000, 8, 4, 0, 0, 0)  # clamped to N
 
 
+def test_mahalanobis_host_checks(lib):
+    from paper_2303_14102_amd import _lib
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x100000)
+    f = lib.silhouette_mahalanobis
+    # (X, dtype, col_scale, L, labels, N, D, K, flags, s, S, ws, bytes, stream)
+    assert f(fake, 0, None, None, fake, 10, 4, 2, 0, None, fake, ws, 1 << 30, None) == -1   # L
+    assert f(fake, 0, None, fake, fake, 10, 4, 2, _lib.SIL_FLAG_EUCLID_APPROX, None, fake, ws, 1 << 30, None) == -1
+    assert f(fake, 0, None, fake, fake, 10, 4, 2, 0, None, None, ws, 1 << 30, None) == -1   # S
+    assert f(fake, 2, None, fake, fake, 10, 4, 2, 0, None, fake, ws, 1 << 30, None) == -2   # fp8 scale
+    assert f(fake, 0, None, fake, fake, 10, 4, 2, 0, None, fake, ws, 64, None) == -7        # workspace
+    sz = lib.silhouette_mahalanobis_workspace_bytes
+    assert sz(1000, 8, 4, 0) >= 1000 * 8 * 4 + lib.silhouette_workspace_bytes(1000, 8, 4, 0, 0, 0)
+    assert sz(0, 8, 4, 0) == 0
+
+
 def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, 99):
         assert isinstance(lib.silhouette_strerror(code), bytes)
