@@ -196,12 +196,107 @@ __device__ __forceinline__ void scatter_body(const int32_t* __restrict__ labels,
   }
 }
 
+// The same scatter with the chunk sorted in LDS first (K <= kStageMaxK): the chunk's rows are
+// counted per cluster, the counts scanned into local offsets, each present cluster's block of
+// positions reserved once, the rows placed in LDS by cluster, and the chunk written out in that
+// order.  A cluster's rows then go to consecutive positions from consecutive lanes, so the
+// stores coalesce into whole-line writes instead of one 4-byte request per row.
+constexpr int kStageChunk = 8192;   // labels per workgroup
+constexpr int kStageThreads = 512;
+constexpr int kStageMaxK = 4096;    // LDS: 8 B per staged row + 12 B per cluster
+
+__global__ __launch_bounds__(kStageThreads) void k_scatter_staged(
+    const int32_t* __restrict__ labels, int64_t N, int32_t K, int32_t* __restrict__ cursor,
+    int32_t* __restrict__ perm, int32_t* __restrict__ lsorted) {
+  constexpr int PER = kStageChunk / kStageThreads;
+  extern __shared__ int32_t sh_dyn[];
+  int32_t* st_row = sh_dyn;                    // [kStageChunk]
+  int32_t* st_lab = st_row + kStageChunk;      // [kStageChunk]
+  int32_t* cnt = st_lab + kStageChunk;         // [K]: counts, then placement cursors
+  int32_t* lbase = cnt + K;                    // [K]: local offsets
+  int32_t* gbase = lbase + K;                  // [K]: reserved global positions
+  __shared__ int32_t part[kStageThreads];
+  const int t = threadIdx.x;
+  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kStageChunk;
+  for (int k = t; k < K; k += kStageThreads) cnt[k] = 0;
+  __syncthreads();
+  int32_t lab[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int64_t i = c0 + u * kStageThreads + t;
+    int32_t k = i < N ? labels[i] : -1;
+    if (k < 0 || k >= K) k = -1;
+    lab[u] = k;
+    if (k >= 0) atomicAdd(&cnt[k], 1);
+  }
+  __syncthreads();
+  // exclusive scan of cnt: contiguous segments per thread, then the segment sums
+  const int seg = (K + kStageThreads - 1) / kStageThreads;
+  const int k0 = min(K, t * seg), k1 = min(K, k0 + seg);
+  int32_t sum = 0;
+  for (int k = k0; k < k1; ++k) sum += cnt[k];
+  part[t] = sum;
+  __syncthreads();
+  for (int d = 1; d < kStageThreads; d <<= 1) {
+    const int32_t v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = part[t] - sum;
+  for (int k = k0; k < k1; ++k) {
+    const int32_t n = cnt[k];
+    lbase[k] = run;
+    if (n) gbase[k] = atomicAdd(&cursor[k], n);
+    cnt[k] = run;  // placement cursor
+    run += n;
+  }
+  const int32_t nvalid = part[kStageThreads - 1];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int32_t k = lab[u];
+    if (k >= 0) {
+      const int32_t slot = atomicAdd(&cnt[k], 1);
+      st_row[slot] = static_cast<int32_t>(c0 + u * kStageThreads + t);
+      st_lab[slot] = k;
+    }
+  }
+  __syncthreads();
+  for (int j = t; j < nvalid; j += kStageThreads) {
+    const int32_t k = st_lab[j];
+    const int32_t pos = gbase[k] + (j - lbase[k]);
+    perm[pos] = st_row[j];
+    lsorted[pos] = k;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ labels, int64_t N,
                                                  int32_t K, int32_t* __restrict__ cursor,
                                                  int32_t* __restrict__ perm,
                                                  int32_t* __restrict__ lsorted) {
   extern __shared__ int32_t sh_dyn[];
   scatter_body(labels, N, K, cursor, perm, lsorted, blockIdx.x, sh_dyn);
+}
+
+static hipError_t launch_scatter(const Problem& p, const WsPtrs& w, unsigned nchunk, size_t lds,
+                                 hipStream_t st) {
+  if (p.K <= kStageMaxK) {
+    static bool lds_set = false;  // above 64 KB of dynamic LDS the kernel must say so once
+    if (!lds_set) {
+      const hipError_t e = hipFuncSetAttribute(
+          reinterpret_cast<const void*>(&k_scatter_staged), hipFuncAttributeMaxDynamicSharedMemorySize,
+          static_cast<int>((2 * kStageChunk + 3 * kStageMaxK) * 4));
+      if (e != hipSuccess) return e;
+      lds_set = true;
+    }
+    const size_t sl = (2 * static_cast<size_t>(kStageChunk) + 3 * static_cast<size_t>(p.K)) * 4;
+    k_scatter_staged<<<static_cast<unsigned>(ceil_div(p.N, kStageChunk)), kStageThreads, sl, st>>>(
+        p.labels, p.N, p.K, w.cursor, w.perm, w.lsorted);
+  } else {
+    k_scatter<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.cursor, w.perm, w.lsorted);
+  }
+  return hipSuccess;
 }
 
 // Cluster whose sorted range contains position q (0 <= q < offset[K]): the largest k with
@@ -686,7 +781,7 @@ hipError_t launch_sort(const Problem& p, const WsLayout& L, const WsPtrs& w, hip
   const size_t lds = p.K <= kLdsHistMaxK ? static_cast<size_t>(p.K) * 4 : 0;
   k_hist<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.count, w.hdr);
   k_scan<<<1, 1024, 0, st>>>(w.count, p.K, w.offset, w.cursor, w.hdr, p.min_nonempty);
-  k_scatter<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.cursor, w.perm, w.lsorted);
+  if (const hipError_t e = launch_scatter(p, w, nchunk, lds, st); e != hipSuccess) return e;
   return hipGetLastError();
 }
 
@@ -701,7 +796,7 @@ hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hi
   k_hist<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.count, w.hdr);
   // the Silhouette needs a neighbouring cluster; a K-means step needs one non-empty cluster
   k_scan<<<1, 1024, 0, st>>>(w.count, p.K, w.offset, w.cursor, w.hdr, p.min_nonempty);
-  k_scatter<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.cursor, w.perm, w.lsorted);
+  if (const hipError_t e = launch_scatter(p, w, nchunk, lds, st); e != hipSuccess) return e;
   const unsigned nblk = static_cast<unsigned>(ceil_div(L.nseg, 4));
   // 16-byte chunks when a row splits into a power-of-two number of them
   int32_t Gv, G, E;

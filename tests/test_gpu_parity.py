@@ -117,6 +117,19 @@ def test_stats_row_reduction_nonfinite(dev):
     assert e.value.code == -6
 
 
+@pytest.mark.parametrize("K", [4096, 4097, 9000])
+def test_stats_scatter_forms(dev, K):
+    # K <= 4096: the chunk is counting-sorted in LDS before the scatter; above: per-row placement
+    from paper_2303_14102_amd import binding as sil
+    b = wl.make_small(3 * K + 1_001, 12, K, seed=K, singletons=3)
+    print(f"[stats-scatter] K={K}", flush=True)
+    count, V, psi = sil.cluster_stats(b.X.to(dev), b.labels.to(dev), K)
+    c_ref, V_ref, p_ref = oracle.cluster_stats(b.X.numpy(), b.labels.numpy(), K)
+    assert np.array_equal(count.cpu().numpy(), c_ref)
+    np.testing.assert_allclose(V.cpu().numpy(), V_ref, rtol=1e-12, atol=1e-12 * np.abs(V_ref).max())
+    np.testing.assert_allclose(psi.cpu().numpy(), p_ref, rtol=1e-12, atol=0)
+
+
 def test_stats_large_clusters_span_segments(dev):
     # a few clusters of ~1e5 points: every cluster crosses many segment borders
     from paper_2303_14102_amd import binding as sil
