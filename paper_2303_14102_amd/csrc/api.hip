@@ -38,6 +38,7 @@ WsLayout make_layout(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dt
   L.mvec = take(static_cast<size_t>(L.DPX) * 4);
   const size_t bt_elem = dtype == SIL_F32 ? 4 : 2 * 2;  // fp32, or bf16 hi + lo
   L.btab = take(static_cast<size_t>(L.Kpad) * table_stride(L.DPX, dtype) * bt_elem);
+  L.ctab = take(static_cast<size_t>(L.Kpad) * 4);
   L.atab = take(static_cast<size_t>(K) * L.DPX * 4);
   L.avec = take(static_cast<size_t>(K) * 4);
   L.ascale = take(static_cast<size_t>(K) * 4);
@@ -69,6 +70,7 @@ WsPtrs carve(const WsLayout& L, void* ws) {
   w.gmean = reinterpret_cast<double*>(b + L.gmean);
   w.mvec = reinterpret_cast<float*>(b + L.mvec);
   w.btab = b + L.btab;
+  w.ctab = reinterpret_cast<float*>(b + L.ctab);
   w.atab = reinterpret_cast<float*>(b + L.atab);
   w.avec = reinterpret_cast<float*>(b + L.avec);
   w.ascale = reinterpret_cast<float*>(b + L.ascale);

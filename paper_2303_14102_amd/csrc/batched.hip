@@ -98,6 +98,7 @@ size_t build_header(sil_plan* P, void* ws) {
     q.gmean = w.gmean;
     q.mvec = w.mvec;
     q.btab = w.btab;
+    q.ctab = w.ctab;
     q.atab = w.atab;
     q.avec = w.avec;
     q.ascale = w.ascale;

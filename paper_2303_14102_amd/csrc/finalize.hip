@@ -65,20 +65,21 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // One wave per (padded) cluster.  GEMM table row k (DPX entries):
-//   fp32:  [alpha mu'_k (D), c_k, 0 ...]
-//   bf16:  hi = [bf16(alpha mu'_k) (D), c_hi, c_mid, c_lo, 0 ...],
-//          lo = [bf16(alpha mu'_k - hi) (D), 0 ...]
+//   fp32:  [alpha mu'_k (D), 0 ...]
+//   bf16:  hi = [bf16(alpha mu'_k) (D), 0 ...], lo = [bf16(alpha mu'_k - hi) (D), 0 ...]
 // alpha = -2 (squared Euclidean) or -1 (cosine) is a power of two, so alpha mu' splits exactly
-// like mu'.  Empty and padding clusters get c_k = kEmptyC (finite, so that 0 * c stays 0 in the
-// split products) and a zero mean.
+// like mu'.  The constant c_k goes to ctab (fp32), which the fused kernels add to the cross term
+// before the minimum.  Empty and padding clusters get c_k = kEmptyC (large and finite) and a
+// zero mean.
 constexpr double kEmptyC = 1.0e30;
 
 template <int METRIC, bool BF16TAB>
 __device__ __forceinline__ void finalize_body(
     const int32_t* __restrict__ count, const double* __restrict__ V,
     const double* __restrict__ psi, const double* __restrict__ gmean, int32_t K, int32_t Kpad,
-    int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ atab,
-    float* __restrict__ avec, float* __restrict__ ascale, int with_var, int64_t bid) {
+    int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ ctab,
+    float* __restrict__ atab, float* __restrict__ avec, float* __restrict__ ascale, int with_var,
+    int64_t bid) {
   constexpr double ALPHA = METRIC == SIL_SQEUCLID ? -2.0 : -1.0;
   const int lane = threadIdx.x & 63;
   const int32_t k = static_cast<int32_t>(bid) * 4 + (threadIdx.x >> 6);
@@ -128,17 +129,7 @@ __device__ __forceinline__ void finalize_body(
         av = fmax(0.0, 1.0 - mu2);
       }
     }
-    if (BF16TAB) {  // c as three bf16 pieces in the slots D, D+1, D+2
-      const uint16_t c1 = f32_to_bf16_rne(static_cast<float>(c));
-      const double r1 = c - static_cast<double>(bf16_to_f32(c1));
-      const uint16_t c2 = f32_to_bf16_rne(static_cast<float>(r1));
-      const double r2 = r1 - static_cast<double>(bf16_to_f32(c2));
-      bthi[brow + D] = c1;
-      bthi[brow + D + 1] = c2;
-      bthi[brow + D + 2] = f32_to_bf16_rne(static_cast<float>(r2));
-    } else {
-      bt32[brow + D] = static_cast<float>(c);
-    }
+    ctab[k] = static_cast<float>(c);
     if (k < K) {
       avec[k] = static_cast<float>(av);
       ascale[k] = n >= 2 ? static_cast<float>(dn / (dn - 1.0)) : 0.0f;
@@ -150,10 +141,10 @@ template <int METRIC, bool BF16TAB>
 __global__ __launch_bounds__(256) void k_finalize(
     const int32_t* __restrict__ count, const double* __restrict__ V,
     const double* __restrict__ psi, const double* __restrict__ gmean, int32_t K, int32_t Kpad,
-    int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ atab,
-    float* __restrict__ avec, float* __restrict__ ascale, int with_var) {
-  finalize_body<METRIC, BF16TAB>(count, V, psi, gmean, K, Kpad, D, DPX, RS, btab, atab, avec,
-                                 ascale, with_var, blockIdx.x);
+    int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ ctab,
+    float* __restrict__ atab, float* __restrict__ avec, float* __restrict__ ascale, int with_var) {
+  finalize_body<METRIC, BF16TAB>(count, V, psi, gmean, K, Kpad, D, DPX, RS, btab, ctab, atab,
+                                 avec, ascale, with_var, blockIdx.x);
 }
 
 hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
@@ -164,8 +155,8 @@ hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w,
   const bool bf = p.dtype != SIL_F32;
 #define SIL_FIN(MT, BF)                                                                        \
   k_finalize<MT, BF><<<nb, 256, 0, st>>>(w.count, w.V, w.psi, w.gmean, p.K, p.Kpad, p.D, p.DPX, \
-                                         table_stride(p.DPX, p.dtype), w.btab, w.atab, w.avec,  \
-                                         w.ascale, p.assign ? 0 : 1)
+                                         table_stride(p.DPX, p.dtype), w.btab, w.ctab, w.atab,  \
+                                         w.avec, w.ascale, p.assign ? 0 : 1)
   if (p.metric == SIL_SQEUCLID) {
     if (bf) SIL_FIN(SIL_SQEUCLID, true);
     else SIL_FIN(SIL_SQEUCLID, false);
@@ -204,10 +195,10 @@ __global__ __launch_bounds__(256) void kb_fin(BatchDev b) {
   const int32_t RS = table_stride(q.DPX, SIL_F32);
   if (q.metric == SIL_SQEUCLID)
     finalize_body<SIL_SQEUCLID, false>(q.count, q.V, q.psi, q.gmean, q.K, q.Kpad, q.D, q.DPX, RS,
-                                       q.btab, q.atab, q.avec, q.ascale, 1, it);
+                                       q.btab, q.ctab, q.atab, q.avec, q.ascale, 1, it);
   else
     finalize_body<SIL_COSINE, false>(q.count, q.V, q.psi, q.gmean, q.K, q.Kpad, q.D, q.DPX, RS,
-                                     q.btab, q.atab, q.avec, q.ascale, 1, it);
+                                     q.btab, q.ctab, q.atab, q.avec, q.ascale, 1, it);
 }
 
 hipError_t launch_finalize_batched(const BatchLaunch& b, hipStream_t st) {

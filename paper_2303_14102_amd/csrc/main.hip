@@ -89,6 +89,7 @@ hipError_t launch_main(const Problem& p, const WsLayout& L, const WsPtrs& w, hip
   m.K = p.K;
   m.btab = w.btab;
   m.piece = static_cast<int64_t>(p.Kpad) * table_stride(p.DPX, p.dtype);
+  m.ctab = w.ctab;
   m.atab = w.atab;
   m.avec = w.avec;
   m.ascale = w.ascale;

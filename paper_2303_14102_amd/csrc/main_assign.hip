@@ -18,8 +18,8 @@ static void run_assign_dt(const MainArgs& m, int DPX, unsigned grid, hipStream_t
     case 32: run_assign<32, DT>(m, grid, st); break;
     case 48: run_assign<48, DT>(m, grid, st); break;
     case 80: run_assign<80, DT>(m, grid, st); break;
-    case 144: run_assign<144, DT>(m, grid, st); break;
-    default: run_assign<272, DT>(m, grid, st); break;
+    case 128: run_assign<128, DT>(m, grid, st); break;
+    default: run_assign<256, DT>(m, grid, st); break;
   }
 }
 

@@ -8,14 +8,14 @@
 //
 // Each problem runs the same per-row-block body as the single-problem kernel, picked by its GEMM
 // depth, metric and rows per block.  The next item's row ids and labels are loaded while the
-// current item runs (within a batch of queue items).  The LDS is laid out for the deepest depth (136) with a
+// current item runs (within a batch of queue items).  The LDS is laid out for the deepest depth (128) with a
 // two-stage table ring, so that two workgroups fit one CU for every depth.  The queue position
 // of the next batch of items is fetched while the current batch is computed.
 #include "main_kernels.h"
 
 namespace sil {
 
-static constexpr int kBatchDPXMax = 136;
+static constexpr int kBatchDPXMax = 128;
 constexpr int kBatchRS = table_stride(kBatchDPXMax, SIL_F32);
 using RingMax = Ring<1, kBatchRS * 4, 2>;
 constexpr int kBatchNBMax = 2;
@@ -38,6 +38,7 @@ static __device__ __forceinline__ MainArgs batch_args(const BatchProblem& q) {
   a.K = q.K;
   a.btab = q.btab;
   a.piece = static_cast<int64_t>(q.Kpad) * table_stride(q.DPX, SIL_F32);
+  a.ctab = q.ctab;
   a.atab = q.atab;
   a.avec = q.avec;
   a.ascale = q.ascale;
@@ -109,7 +110,7 @@ __device__ __forceinline__ void batch_body(const MainArgs& a, int DPX, int nb, i
       SIL_BODY(72, 1);
       break;
     default:
-      SIL_BODY(136, 1);
+      SIL_BODY(128, 1);
       break;
   }
 #undef SIL_BODY

@@ -3,13 +3,13 @@
 
 namespace sil {
 
-// Split products (2 or 3) with one row block per wave at depths up to 144 run with 32-cluster
+// Split products (2 or 3) with one row block per wave at depths up to 128 run with 32-cluster
 // tiles and three workgroups per CU, the other forms with 64-cluster tiles and two; measured on
 // the 128-dimension workload: 32-cluster tiles -9% (2 products), -2% (3), +5% (1).
 template <int DPX, int P, int METRIC>
 static void run_p(const MainArgs& m, unsigned grid, hipStream_t st) {
   constexpr int NB = bf16_nb(DPX, P);
-  if constexpr (P >= 2 && DPX <= 144 && NB == 1) {
+  if constexpr (P >= 2 && DPX <= 128 && NB == 1) {
     MainArgs m2 = m;
     m2.ntiles = m.ntiles * (kColTile / 32);
     k_main_bf16<DPX, NB, P, SIL_BF16, METRIC, false, 32><<<grid, 256, 0, st>>>(m2);
@@ -35,8 +35,8 @@ static void run_metric(const MainArgs& m, int DPX, int products, unsigned grid, 
     case 32: run_dp<32, METRIC>(m, products, grid, st); break;
     case 48: run_dp<48, METRIC>(m, products, grid, st); break;
     case 80: run_dp<80, METRIC>(m, products, grid, st); break;
-    case 144: run_dp<144, METRIC>(m, products, grid, st); break;
-    default: run_dp<272, METRIC>(m, products, grid, st); break;
+    case 128: run_dp<128, METRIC>(m, products, grid, st); break;
+    default: run_dp<256, METRIC>(m, products, grid, st); break;
   }
 }
 

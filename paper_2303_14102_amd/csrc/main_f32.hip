@@ -18,8 +18,8 @@ static void run_f32_dp(const MainArgs& m, int DPX, bool save, unsigned grid, hip
     case 24: run_f32<24, METRIC>(m, save, grid, st); break;
     case 40: run_f32<40, METRIC>(m, save, grid, st); break;
     case 72: run_f32<72, METRIC>(m, save, grid, st); break;
-    case 136: run_f32<136, METRIC>(m, save, grid, st); break;
-    default: run_f32<264, METRIC>(m, save, grid, st); break;
+    case 128: run_f32<128, METRIC>(m, save, grid, st); break;
+    default: run_f32<256, METRIC>(m, save, grid, st); break;
   }
 }
 

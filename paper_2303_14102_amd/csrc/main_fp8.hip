@@ -27,8 +27,8 @@ static void run_metric(const MainArgs& m, int DPX, int products, unsigned grid, 
     case 32: run_dp<32, METRIC>(m, products, grid, st); break;
     case 48: run_dp<48, METRIC>(m, products, grid, st); break;
     case 80: run_dp<80, METRIC>(m, products, grid, st); break;
-    case 144: run_dp<144, METRIC>(m, products, grid, st); break;
-    default: run_dp<272, METRIC>(m, products, grid, st); break;
+    case 128: run_dp<128, METRIC>(m, products, grid, st); break;
+    default: run_dp<256, METRIC>(m, products, grid, st); break;
   }
 }
 

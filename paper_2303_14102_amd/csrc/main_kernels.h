@@ -53,6 +53,7 @@ struct MainArgs {
   int32_t K;
   const void* btab;        // [pieces][Kpad][RS], RS = table_stride(DPX)
   int64_t piece;           // elements per piece (Kpad * RS)
+  const float* ctab;       // [Kpad] c_k, added to the cross term in the epilogue
   const float* atab;       // [K][DPX] mu' (a-path)
   const float* avec;
   const float* ascale;
@@ -218,7 +219,7 @@ __device__ __forceinline__ void make_blocks(const MainArgs& a, const RowPre<NB>&
 // Prologue shared by both kernel families.  Lane (r = lane%32, h = lane/32) holds, for each of
 // its NB row blocks, the chunks c = 2q + h (q < NQ) of W elements of row r: it decodes them,
 // centres / normalises, computes its halves of ||x'||^2 and of the a-path sum, and hands each
-// transformed chunk (with the constant-carrying slots [D, D+NC) set to 1) to emit(nb, q, vals).
+// transformed chunk (zero past D) to emit(nb, q, vals).
 // When D is a multiple of W every chunk is one aligned vector load, issued for the whole row
 // before any is used (addresses clamped in range, values masked afterwards).
 
@@ -280,7 +281,7 @@ __device__ __forceinline__ void load_f32w(const float* __restrict__ p, float* ou
   }
 }
 
-template <int DT, int W, int NQ, int NB, int METRIC, int NC, typename Emit>
+template <int DT, int W, int NQ, int NB, int METRIC, typename Emit>
 __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B, int lane,
                                          float (&nrow)[NB], float (&arow)[NB], Emit&& emit) {
   constexpr int DPX = 2 * NQ * W;
@@ -338,8 +339,6 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
         nx = fmaf(v[e], v[e], nx);
         const float dd = v[e] - at[e];
         ad = fmaf(dd, dd, ad);
-        const int idx = c0 + e;
-        if (idx >= a.D && idx < a.D + NC) v[e] = 1.0f;  // carries c_k through the GEMM
       }
       emit(nb, q, v);
     }
@@ -355,11 +354,12 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
   }
 }
 
-// Running minimum over one tile of the accumulators of block nb.
+// Running minimum over one tile of the accumulators of block nb.  cv is c_k of the lane's
+// column (every accumulator of a lane lies in that column): m = cross term + c_k.
 template <bool SAVE>
 __device__ __forceinline__ void tile_min(const f32x16_t& acc, float (&mn)[16], int32_t (&arg)[16],
                                          bool mixed, bool own_tile, int col, int cown, int t32,
-                                         const int32_t* lab_block, int h) {
+                                         const int32_t* lab_block, int h, float cv) {
   constexpr float BIG = 3.0e38f;
   if (mixed) {  // per-element own-cluster test against the block's labels
 #pragma unroll
@@ -368,7 +368,7 @@ __device__ __forceinline__ void tile_min(const f32x16_t& acc, float (&mn)[16], i
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int j = 4 * q + e;
-        const float v = (l4[e] == t32 + col) ? BIG : acc[j];
+        const float v = (l4[e] == t32 + col) ? BIG : acc[j] + cv;
         if constexpr (SAVE) {
           if (v < mn[j]) { mn[j] = v; arg[j] = t32 + col; }
         } else {
@@ -380,7 +380,7 @@ __device__ __forceinline__ void tile_min(const f32x16_t& acc, float (&mn)[16], i
     const bool me = col == cown;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const float v = me ? BIG : acc[j];
+      const float v = me ? BIG : acc[j] + cv;
       if constexpr (SAVE) {
         if (v < mn[j]) { mn[j] = v; arg[j] = t32 + col; }
       } else {
@@ -390,10 +390,11 @@ __device__ __forceinline__ void tile_min(const f32x16_t& acc, float (&mn)[16], i
   } else {
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
+      const float v = acc[j] + cv;
       if constexpr (SAVE) {
-        if (acc[j] < mn[j]) { mn[j] = acc[j]; arg[j] = t32 + col; }
+        if (v < mn[j]) { mn[j] = v; arg[j] = t32 + col; }
       } else {
-        mn[j] = fminf(mn[j], acc[j]);
+        mn[j] = fminf(mn[j], v);
       }
     }
   }
@@ -621,7 +622,7 @@ __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
   u32x4_t ahi[NB][S];
   u32x4_t alo[NB][P == 3 ? S : 1];
   float nrow[NB], arow[NB];
-  prologue<DT, 8, S, NB, METRIC, 3>(
+  prologue<DT, 8, S, NB, METRIC>(
       a, B, lane, nrow, arow, [&](int nb, int q, const float* v) __attribute__((always_inline)) {
         uint32_t hw[4], lw[4];
 #pragma unroll
@@ -693,26 +694,30 @@ __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
       }
     }
   };
-  // Running minimum over 32-cluster block blk (global index) of the tile sweep.
-  auto epi = [&](const f32x16_t (&acc)[NB], int blk) __attribute__((always_inline)) {
+  // Running minimum over 32-cluster block blk (global index) of the tile sweep; cv = c_k of
+  // the lane's column, loaded ahead of the block's MFMAs.
+  auto epi = [&](const f32x16_t (&acc)[NB], int blk, float cv) __attribute__((always_inline)) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
       tile_min<SAVE>(acc[nb], mn[nb], arg[nb], B.mixed[nb], blk == B.town[nb], col, B.cown[nb],
-                     32 * blk, lab_w + nb * 32, h);
+                     32 * blk, lab_w + nb * 32, h, cv);
   };
 
   if constexpr (TC == 64) {
     // Per tile: block 0's MFMAs, the previous block 1's minimum (under them), block 1's MFMAs,
     // block 0's minimum (under them).
     f32x16_t acc0[NB], acc1[NB];
+    float c1p = 0.0f;  // c_k of block 1 of the previous tile
     sweep<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, ring2, wave,
              lane, [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
+      const float c0 = a.ctab[64 * t + col], c1 = a.ctab[64 * t + 32 + col];
       gemm(st, 0, acc0, prefetch);
-      if (t > 0) epi(acc1, 2 * t - 1);
+      if (t > 0) epi(acc1, 2 * t - 1, c1p);
       gemm(st, 1, acc1, [] {});
-      epi(acc0, 2 * t);
+      epi(acc0, 2 * t, c0);
+      c1p = c1;
     });
-    epi(acc1, 2 * a.ntiles - 1);
+    epi(acc1, 2 * a.ntiles - 1, c1p);
   } else {
     // 32-cluster tiles (one block each): the other workgroups' waves on the SIMD fill the gap
     // of each minimum
@@ -720,8 +725,9 @@ __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
     f32x16_t acc0[NB];
     sweep<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, ring2, wave,
              lane, [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
+      const float c0 = a.ctab[32 * t + col];
       gemm(st, 0, acc0, prefetch);
-      epi(acc0, t);
+      epi(acc0, t, c0);
     });
   }
 
@@ -735,7 +741,7 @@ __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
 // TC: clusters per table tile, 64 (two workgroups per CU) or 32 (three per CU: the ring is half
 // as large and the kernel fits 168 registers; a.ntiles counts tiles of TC clusters).
 template <int DPX, int NB, int P, int DT, int METRIC, bool SAVE, int TC = kColTile>
-__global__ __launch_bounds__(256, DPX > 144 ? 1 : (TC == 32 ? 3 : 2)) void k_main_bf16(MainArgs a) {
+__global__ __launch_bounds__(256, DPX > 128 ? 1 : (TC == 32 ? 3 : 2)) void k_main_bf16(MainArgs a) {
   constexpr int NPC = P >= 2 ? 2 : 1;
   constexpr int RS = table_stride(DPX, SIL_BF16);
   using R = Ring<NPC, RS * 2, 3, TC>;
@@ -794,7 +800,7 @@ __device__ __forceinline__ void main_f32_body(const MainArgs& a, int64_t wb, con
 
   f32x4_t areg[NB][NQ];
   float nrow[NB], arow[NB];
-  prologue<SIL_F32, 4, NQ, NB, METRIC, 1>(
+  prologue<SIL_F32, 4, NQ, NB, METRIC>(
       a, B, lane, nrow, arow, [&](int nb, int q, const float* v) __attribute__((always_inline)) {
         areg[nb][q] = f32x4_t{v[0], v[1], v[2], v[3]};
       });
@@ -831,22 +837,25 @@ __device__ __forceinline__ void main_f32_body(const MainArgs& a, int64_t wb, con
         }
     }
   };
-  auto epi = [&](const f32x16_t (&acc)[NB], int blk) __attribute__((always_inline)) {
+  auto epi = [&](const f32x16_t (&acc)[NB], int blk, float cv) __attribute__((always_inline)) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
       tile_min<SAVE>(acc[nb], mn[nb], arg[nb], B.mixed[nb], blk == B.town[nb], col, B.cown[nb],
-                     32 * blk, lab_w + nb * 32, h);
+                     32 * blk, lab_w + nb * 32, h, cv);
   };
 
   f32x16_t acc0[NB], acc1[NB];
+  float c1p = 0.0f;  // c_k of block 1 of the previous tile
   sweep<R>(static_cast<const char*>(a.btab), a.piece * 4, a.ntiles, ring0, ring1, ring2, wave, lane,
            [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
+    const float c0 = a.ctab[64 * t + col], c1 = a.ctab[64 * t + 32 + col];
     gemm(st, 0, acc0, prefetch);
-    if (t > 0) epi(acc1, 2 * t - 1);
+    if (t > 0) epi(acc1, 2 * t - 1, c1p);
     gemm(st, 1, acc1, [] {});
-    epi(acc0, 2 * t);
+    epi(acc0, 2 * t, c0);
+    c1p = c1;
   });
-  epi(acc1, 2 * a.ntiles - 1);
+  epi(acc1, 2 * a.ntiles - 1, c1p);
 
   __syncthreads();
   finish<NB, METRIC, SAVE>(a, wb, B, wave, lane, mn, arg, nrow, arow, lds_min + wave * NB * 32,
@@ -854,7 +863,7 @@ __device__ __forceinline__ void main_f32_body(const MainArgs& a, int64_t wb, con
 }
 
 template <int DPX, int NB, int METRIC, bool SAVE>
-__global__ __launch_bounds__(256, DPX > 144 ? 1 : 2) void k_main_f32(MainArgs a) {
+__global__ __launch_bounds__(256, DPX > 128 ? 1 : 2) void k_main_f32(MainArgs a) {
   constexpr int RS = table_stride(DPX, SIL_F32);
   using R = Ring<1, RS * 4>;
   __shared__ __attribute__((aligned(16))) uint8_t ring0[R::STAGE_BYTES];

@@ -24,17 +24,17 @@ constexpr int kMainWaves = 4;       // waves per workgroup in the fused GEMM+epi
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
-// GEMM depth of the fused kernels: the D coordinates plus the slots that carry the per-cluster
-// constant (three bf16 pieces, or one fp32), rounded up to an instantiated depth.
-constexpr int kDepthsBf16[] = {16, 32, 48, 80, 144, 272};
-constexpr int kDepthsF32[] = {16, 24, 40, 72, 136, 264};
+// GEMM depth of the fused kernels: the D coordinates rounded up to an instantiated depth (the
+// per-cluster constant is added in the epilogue, not carried in the depth).
+constexpr int kDepthsBf16[] = {16, 32, 48, 80, 128, 256};
+constexpr int kDepthsF32[] = {16, 24, 40, 72, 128, 256};
 inline int gemm_depth(int D, int dtype) {
   if (dtype == SIL_F32) {
     for (int v : kDepthsF32)
-      if (D + 1 <= v) return v;
+      if (D <= v) return v;
   } else {
     for (int v : kDepthsBf16)
-      if (D + 3 <= v) return v;
+      if (D <= v) return v;
   }
   return 0;
 }
@@ -60,7 +60,8 @@ struct WsLayout {
   size_t gmean;    // f64[DPX]       global mean (centring)
   size_t mvec;     // f32[DPX]       global mean as float (centring)
   size_t btab;     // GEMM operand: f32[Kpad*RS] or bf16[2][Kpad*RS] (hi, lo), RS the row stride:
-                   //   row k = [alpha mu'_k (D), c_k (1 fp32 or 3 bf16 pieces), 0 ...]
+                   //   row k = [alpha mu'_k (D), 0 ...]
+  size_t ctab;     // f32[Kpad]      per-cluster constant c_k of the GEMM form (1e30: empty)
   size_t atab;     // f32[K*DPX]     cluster means (centred) for the a-path
   size_t avec;     // f32[K]         sigma_k^2 (sq. Euclidean) or 1-||mu_k||^2 (cosine)
   size_t ascale;   // f32[K]         N_k/(N_k-1), 0 for singletons
@@ -96,6 +97,7 @@ struct WsPtrs {
   double* gmean;
   float* mvec;
   void* btab;
+  float* ctab;
   float* atab;
   float* avec;
   float* ascale;
@@ -163,7 +165,7 @@ bool bwd_fits_lds(int32_t K, int32_t D);
 // batched evaluation: many problems (labelings of one or several data sets) per launch
 
 constexpr int kBatchMaxProblems = 1024;
-constexpr int kBatchMaxD = 128;  // fp32 storage, GEMM depth <= 136
+constexpr int kBatchMaxD = 128;  // fp32 storage, GEMM depth <= 128
 
 // One problem of a batch as the kernels see it (device memory, written by the plan).
 struct BatchProblem {
@@ -193,6 +195,7 @@ struct BatchProblem {
   double* gmean;
   float* mvec;
   void* btab;
+  float* ctab;
   float* atab;
   float* avec;
   float* ascale;
