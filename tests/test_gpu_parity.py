@@ -195,6 +195,18 @@ def test_larger_parity(dev, case):
     run_case(dev, b.X, b.labels, k, metric, form, products)
 
 
+# many clusters: above 16,384 the label histogram leaves LDS for global atomics, above 4,096 the
+# scatter places rows one by one, and the sweep runs hundreds of cluster tiles; 65,536 is the limit
+@pytest.mark.parametrize("case", [(100_003, 32, 20_000, "sqeuclid", "bf16", 3, 0, 81),
+                                  (150_001, 24, 16_385, "cosine", "f32", 0, 1, 82),
+                                  (200_000, 8, 65_536, "sqeuclid", "f32", 0, 0, 83)],
+                         ids=lambda c: f"N{c[0]}-D{c[1]}-K{c[2]}-{c[3]}-{c[4]}")
+def test_many_clusters_parity(dev, case):
+    n, d, k, metric, form, products, single, seed = case
+    b = wl.make_small(n, d, k, seed=seed, singletons=single)
+    run_case(dev, b.X, b.labels, k, metric, form, products)
+
+
 # approximate Euclidean form (square roots of the point-to-cluster mean squared distances)
 APPROX_CASES = [
     # (N, D, K, form, products, singletons, seed)
