@@ -24,7 +24,8 @@ _SO = os.path.join(HERE, "_silhouette_oracle.so")
 F32, BF16, FP8_E4M3, F64 = 0, 1, 2, 3
 SQEUCLID, COSINE = 0, 1
 EUCLID_APPROX = 2  # square roots of the point-to-cluster mean squared distances (Section V)
-METRICS = {"sqeuclid": SQEUCLID, "cosine": COSINE, "euclid_approx": EUCLID_APPROX}
+KL = 3  # generalized Kullback-Leibler divergence of positive vectors (a Bregman divergence)
+METRICS = {"sqeuclid": SQEUCLID, "cosine": COSINE, "euclid_approx": EUCLID_APPROX, "kl": KL}
 
 ERRORS = {
     -1: "bad argument",
@@ -33,6 +34,7 @@ ERRORS = {
     -5: "zero-norm point under the cosine distance",
     -6: "non-finite value in X",
     -9: "out of host memory",
+    -10: "entry outside the distance's domain (KL needs positive entries)",
 }
 
 

@@ -20,6 +20,9 @@
  *    clusters is an error.  For the gradient a tie picks the lowest cluster id.
  *  - cosine: Eq.15 writes ||X||; read ||X_i||.  A zero row is an error (Eq.12 divides by it).
  *  - labels are 0-based ids in [0, K).
+ *  - generalized Kullback-Leibler divergence (Section V names other metrics): the distance from
+ *    point i to point j is d(x_i, x_j), point first (the divergence is not symmetric); every entry
+ *    must be positive.
  *
  * Input storage: X is float32 [N,D] row-major, or float64, or bf16 bit patterns (uint16), or
  * fp8 e4m3fn codes (uint8) with a float32 per-column scale.  The oracle decodes the stored
@@ -34,7 +37,7 @@
 #endif
 
 enum { ORC_F32 = 0, ORC_BF16 = 1, ORC_FP8_E4M3 = 2, ORC_F64 = 3 };
-enum { ORC_SQEUCLID = 0, ORC_COSINE = 1, ORC_EUCLID_APPROX = 2 };
+enum { ORC_SQEUCLID = 0, ORC_COSINE = 1, ORC_EUCLID_APPROX = 2, ORC_KL = 3 };
 enum {
   ORC_OK = 0,
   ORC_E_ARG = -1,
@@ -42,7 +45,8 @@ enum {
   ORC_E_FEW_CLUSTERS = -4,
   ORC_E_ZERO_NORM = -5,
   ORC_E_NONFINITE = -6,
-  ORC_E_NOMEM = -9
+  ORC_E_NOMEM = -9,
+  ORC_E_DOMAIN = -10
 };
 
 /* ---------------------------------------------------------------------------------------- */
@@ -107,7 +111,9 @@ static int orc_check_args(const void* X, int dtype, const float* col_scale, cons
   if (!X || !labels || N < 1 || D < 1 || K < 1) return ORC_E_ARG;
   if (dtype < ORC_F32 || dtype > ORC_F64) return ORC_E_ARG;
   if (dtype == ORC_FP8_E4M3 && !col_scale) return ORC_E_ARG;
-  if (metric != ORC_SQEUCLID && metric != ORC_COSINE && metric != ORC_EUCLID_APPROX) return ORC_E_ARG;
+  if (metric != ORC_SQEUCLID && metric != ORC_COSINE && metric != ORC_EUCLID_APPROX &&
+      metric != ORC_KL)
+    return ORC_E_ARG;
   return ORC_OK;
 }
 
@@ -122,6 +128,8 @@ static int orc_check_args(const void* X, int dtype, const float* col_scale, cons
  *                       xi_{X} = sum_l x_l^2                                    (Eq.5)
  *   cosine:             V[k][l] = Omega_{Gamma_k l} = sum_{j in k} c_jl/||C_j|| (Eq.15, Eq.16)
  *                       psi[k]  = 0
+ *   generalized KL:     V[k][l] = sum_{j in k} log c_jl,  psi[k] = sum_{j in k} sum_l c_jl
+ *                       (the Bregman statistics below; every entry must be positive)
  * Sums run over j in increasing row order.
  */
 int orc_cluster_stats(const void* X, int dtype, const float* col_scale, const int32_t* labels,
@@ -145,7 +153,16 @@ int orc_cluster_stats(const void* X, int dtype, const float* col_scale, const in
     }
     if (rc) break;
     count[k] += 1;
-    if (metric != ORC_COSINE) {
+    if (metric == ORC_KL) {
+      double sx = 0.0;
+      for (int32_t l = 0; l < D; ++l) {
+        if (!(x[l] > 0.0)) { rc = ORC_E_DOMAIN; break; }
+        V[(int64_t)k * D + l] += log(x[l]);
+        sx += x[l];
+      }
+      if (rc) break;
+      psi[k] += sx;
+    } else if (metric != ORC_COSINE) {
       for (int32_t l = 0; l < D; ++l) V[(int64_t)k * D + l] += x[l];
       psi[k] += xi;
     } else {
@@ -162,6 +179,21 @@ int orc_cluster_stats(const void* X, int dtype, const float* col_scale, const in
 /* pass 2: mean distance from a point to every cluster, then s_i                             */
 
 /*
+ * The generalized Kullback-Leibler divergence of positive vectors, the Bregman divergence of
+ * phi(x) = sum_l (x_l log x_l - x_l):
+ *   d(x, y) = phi(x) - phi(y) - grad phi(y).(x - y) = sum_l (x_l log(x_l / y_l) - x_l + y_l).
+ * It is not symmetric; the Silhouette of point i uses d(x_i, x_j) with x_i first.  Section V notes
+ * that a similar approach serves other metrics: averaging over y in cluster k needs only
+ * sum_y log y (a vector) and sum_y sum_l y_l (a scalar), since grad phi(y).y - phi(y) = sum_l y_l.
+ * d(x, x) = 0, so the readings of the squared Euclidean distance (self-exclusion included) apply.
+ */
+static double orc_kl_distance(const double* x, const double* y, int32_t D) {
+  double d = 0.0;
+  for (int32_t l = 0; l < D; ++l) d += x[l] * log(x[l] / y[l]) - x[l] + y[l];
+  return d;
+}
+
+/*
  * m[k] = d(X_i, Gamma_k), the mean distance from point i to the members of cluster k, self
  * included (Eq.3), from the cluster statistics alone:
  *   squared Euclidean (Eq.11): m_k = xi_{X_i} + Psi_k / N_k - 2 * (sum_l Y_kl x_il) / N_k
@@ -172,6 +204,20 @@ int orc_cluster_stats(const void* X, int dtype, const float* col_scale, const in
 static void orc_point_means(const double* x, int32_t D, int32_t K, int metric,
                             const int64_t* count, const double* V, const double* psi,
                             double* m) {
+  if (metric == ORC_KL) {
+    /* Bregman form of the generalized KL divergence (see orc_kl_distance):
+     *   m_k = phi(x) + psi_k / N_k - sum_l x_l V_kl / N_k,  phi(x) = sum_l (x_l log x_l - x_l) */
+    double phi = 0.0;
+    for (int32_t l = 0; l < D; ++l) phi += x[l] * log(x[l]) - x[l];
+    for (int32_t k = 0; k < K; ++k) {
+      if (count[k] == 0) { m[k] = NAN; continue; }
+      double dot = 0.0;
+      for (int32_t l = 0; l < D; ++l) dot += x[l] * V[(int64_t)k * D + l];
+      const double nk = (double)count[k];
+      m[k] = phi + psi[k] / nk - dot / nk;
+    }
+    return;
+  }
   double xi = 0.0;
   for (int32_t l = 0; l < D; ++l) xi += x[l] * x[l];
   double norm = sqrt(xi);
@@ -325,6 +371,9 @@ int orc_brute_silhouette(const void* X, int dtype, const float* col_scale, const
       if (!isfinite(all[i * (int64_t)D + l])) { rc = ORC_E_NONFINITE; goto done; }
     count[labels[i]] += 1;
   }
+  if (metric == ORC_KL)
+    for (int64_t e = 0; e < N * (int64_t)D; ++e)
+      if (!(all[e] > 0.0)) { rc = ORC_E_DOMAIN; goto done; }
   if (orc_nonempty(count, K) < 2) { rc = ORC_E_FEW_CLUSTERS; goto done; }
   if (metric == ORC_COSINE)
     for (int64_t i = 0; i < N; ++i) {
@@ -349,7 +398,9 @@ int orc_brute_silhouette(const void* X, int dtype, const float* col_scale, const
             if (j == i) continue;
             const double* xj = all + j * (int64_t)D;
             double d = 0.0;
-            if (metric != ORC_COSINE) {
+            if (metric == ORC_KL) {
+              d = orc_kl_distance(xi, xj, D);
+            } else if (metric != ORC_COSINE) {
               for (int32_t l = 0; l < D; ++l) d += (xi[l] - xj[l]) * (xi[l] - xj[l]);
             } else {
               double dot = 0.0, ni = 0.0, nj = 0.0;
@@ -428,6 +479,10 @@ int orc_brute_scores_at(const void* X, int dtype, const float* col_scale, const 
     for (int32_t l = 0; l < D; ++l) ni += xi[l] * xi[l];
     if (!isfinite(ni)) { rc = ORC_E_NONFINITE; break; }
     if (metric == ORC_COSINE && ni == 0.0) { rc = ORC_E_ZERO_NORM; break; }
+    if (metric == ORC_KL)
+      for (int32_t l = 0; l < D; ++l)
+        if (!(xi[l] > 0.0)) rc = ORC_E_DOMAIN;
+    if (rc) break;
     int bad = ORC_OK;
     memset(part, 0, sizeof(double) * (size_t)nthr * (size_t)K);
 #pragma omp parallel num_threads(nthr)
@@ -448,7 +503,14 @@ int orc_brute_scores_at(const void* X, int dtype, const float* col_scale, const 
           if (j == i) continue;
           orc_row(X, dtype, col_scale, j, D, xj);
           double d = 0.0;
-          if (metric != ORC_COSINE) {
+          if (metric == ORC_KL) {
+            for (int32_t l = 0; l < D; ++l)
+              if (!(xj[l] > 0.0)) {
+#pragma omp atomic write
+                bad = ORC_E_DOMAIN;
+              }
+            d = orc_kl_distance(xi, xj, D);
+          } else if (metric != ORC_COSINE) {
             for (int32_t l = 0; l < D; ++l) d += (xi[l] - xj[l]) * (xi[l] - xj[l]);
           } else {
             double dot = 0.0, nj = 0.0;
@@ -517,7 +579,7 @@ int orc_brute_scores_at(const void* X, int dtype, const float* col_scale, const 
  */
 int orc_gradient(const void* X, int dtype, const float* col_scale, const int32_t* labels,
                  int64_t N, int32_t D, int32_t K, int metric, double* dX) {
-  if (metric == ORC_EUCLID_APPROX) return ORC_E_ARG;
+  if (metric == ORC_EUCLID_APPROX || metric == ORC_KL) return ORC_E_ARG;
   int rc = orc_check_args(X, dtype, col_scale, labels, N, D, K, metric);
   if (rc) return rc;
   int64_t* count = (int64_t*)malloc(sizeof(int64_t) * (size_t)K);

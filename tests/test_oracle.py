@@ -28,7 +28,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")
 
 
 def _eval_closed_form(expr: str) -> float:
-    return float(eval(expr, {"__builtins__": {}}, {"sqrt": math.sqrt}))
+    return float(eval(expr, {"__builtins__": {}}, {"sqrt": math.sqrt, "log": math.log}))
 
 
 # ---------------------------------------------------------------------------------------------
