@@ -271,7 +271,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="blobs-50m-d128-k1000",
                     help="a named blob workload, or ksweep (the batched k-sweep, its own JSON line)")
-    ap.add_argument("--metric", default="sqeuclid", choices=["sqeuclid", "cosine"])
+    ap.add_argument("--metric", default="sqeuclid", choices=["sqeuclid", "cosine", "kl"])
     ap.add_argument("--form", default="bf16", choices=["bf16", "fp8", "f32"])
     ap.add_argument("--products", type=int, default=3)
     ap.add_argument("--stream", action="store_true",
@@ -446,6 +446,11 @@ def main():
     t0 = time.perf_counter()
     blobs = wl.make_blobs(spec, dev)
     X32, labels = blobs.X, blobs.labels
+    if args.metric == "kl":
+        # the generalized KL divergence needs positive vectors: exponentiated blob coordinates
+        if args.form == "fp8" or args.kmeans or args.mahalanobis or args.stream:
+            sys.exit("--metric kl runs the plain Silhouette with fp32 or bf16 storage")
+        X32 = torch.exp(X32 * 0.25)
     col_scale = None
     if args.form == "bf16":
         X = wl.to_bf16(X32)
@@ -470,7 +475,8 @@ def main():
 
     from paper_2303_14102_amd import _lib
     lib = _lib.load()
-    fn_c = lib.silhouette_sqeuclid if args.metric == "sqeuclid" else lib.silhouette_cosine
+    fn_c = {"sqeuclid": lib.silhouette_sqeuclid, "cosine": lib.silhouette_cosine,
+            "kl": lib.silhouette_kl}[args.metric]
     if args.euclid_approx and args.metric != "sqeuclid":
         sys.exit("--euclid-approx applies to the squared Euclidean entry point")
     flags = _lib.SIL_FLAG_EUCLID_APPROX if args.euclid_approx else 0
@@ -494,6 +500,7 @@ def main():
 
     out = {
         "metric": ("Approximate-Euclidean " if args.euclid_approx else "")
+        + ("Generalized-KL " if args.metric == "kl" else "")
         + "Silhouette points/s at D=128,K=1000; bf16-MFMA vs fp32 form at |dS|<1e-4",
         "value": spec.n / (ms * 1e-3),
         "unit": "points/s",
@@ -510,7 +517,8 @@ def main():
                    "metric": args.metric, "storage": args.form,
                    "products": args.products if args.form != "f32" else None,
                    "centred": args.metric == "sqeuclid",
-                   **({"euclid_approx": True} if args.euclid_approx else {})},
+                   **({"euclid_approx": True} if args.euclid_approx else {}),
+                   **({"data_transform": "exp(x/4) of the blob coordinates"} if args.metric == "kl" else {})},
         "phases_ms": {"stats": phases[0], "finalize": phases[1], "gemm_epilogue": phases[2],
                       "reduce": phases[3]},
         "S": S_form,

@@ -46,14 +46,16 @@ typedef enum {
   SIL_E_ZERO_NORM = -5,    /* (device) a zero row under the cosine distance */
   SIL_E_NONFINITE = -6,    /* (device) NaN or infinity in X */
   SIL_E_WORKSPACE = -7,    /* workspace NULL, misaligned or smaller than required */
-  SIL_E_HIP = -8           /* a HIP runtime call failed */
+  SIL_E_HIP = -8,          /* a HIP runtime call failed */
+  SIL_E_DOMAIN = -9        /* (device) an entry outside the distance's domain (KL: not > 0) */
 } sil_status;
 
 /* Storage of X.  SIL_BF16: bfloat16 values.  SIL_FP8_E4M3: OCP e4m3fn codes, element (i,l)
  * worth code * col_scale[l]. */
 typedef enum { SIL_F32 = 0, SIL_BF16 = 1, SIL_FP8_E4M3 = 2 } sil_dtype;
 
-typedef enum { SIL_SQEUCLID = 0, SIL_COSINE = 1 } sil_metric;
+/* SIL_KL: the generalized Kullback-Leibler divergence of positive vectors (silhouette_kl). */
+typedef enum { SIL_SQEUCLID = 0, SIL_COSINE = 1, SIL_KL = 2 } sil_metric;
 
 /* Option bits for `flags`. */
 enum {
@@ -154,6 +156,23 @@ int silhouette_kmeans_step(const void* X, int32_t dtype, const float* col_scale,
                            const int32_t* labels, int64_t N, int32_t D, int32_t K,
                            int32_t products, int32_t flags, int32_t* labels_out, double* inertia,
                            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Silhouette under the generalized Kullback-Leibler divergence of positive vectors,
+ *   d(x, y) = sum_l (x_l log(x_l / y_l) - x_l + y_l),
+ * the Bregman divergence of phi(x) = sum_l (x_l log x_l - x_l) (Section V notes that a similar
+ * approach serves other metrics).  The distance from point i to point j is d(x_i, x_j), point
+ * first.  Its mean over cluster k needs only sum_{y in k} log y and sum_{y in k} sum_l y_l:
+ *   m(x, k) = phi(x) + (sum_y sum_l y_l) / N_k - x . (sum_y log y) / N_k,
+ * which the statistics pass and the fused kernel form like Eq.11.  Every entry of X must be
+ * positive: otherwise the device reports SIL_E_DOMAIN (S and s become NaN).  Storage: fp32 or
+ * bf16 (SIL_E_DTYPE for fp8).  flags: 0 (SIL_E_ARG for SIL_FLAG_SAVE_FOR_GRAD or
+ * SIL_FLAG_EUCLID_APPROX; SIL_FLAG_NO_CENTRE is ignored, nothing is centred).  Workspace:
+ * silhouette_workspace_bytes(N, D, K, SIL_KL, dtype, 0).  Other arguments as silhouette_sqeuclid.
+ */
+int silhouette_kl(const void* X, int32_t dtype, const float* col_scale, const int32_t* labels,
+                  int64_t N, int32_t D, int32_t K, int32_t products, int32_t flags, float* s,
+                  double* S, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Silhouette under a fixed-matrix Mahalanobis distance d(x, y) = (x - y)^T M (x - y), M = L^T L

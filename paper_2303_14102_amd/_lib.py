@@ -17,9 +17,10 @@ SIL_OK = 0
 STATUS = {
     0: "SIL_OK", -1: "SIL_E_ARG", -2: "SIL_E_DTYPE", -3: "SIL_E_LABEL", -4: "SIL_E_FEW_CLUSTERS",
     -5: "SIL_E_ZERO_NORM", -6: "SIL_E_NONFINITE", -7: "SIL_E_WORKSPACE", -8: "SIL_E_HIP",
+    -9: "SIL_E_DOMAIN",
 }
 SIL_F32, SIL_BF16, SIL_FP8_E4M3 = 0, 1, 2
-SIL_SQEUCLID, SIL_COSINE = 0, 1
+SIL_SQEUCLID, SIL_COSINE, SIL_KL = 0, 1, 2
 SIL_FLAG_NO_CENTRE = 1 << 0
 SIL_FLAG_SAVE_FOR_GRAD = 1 << 1
 SIL_FLAG_EUCLID_APPROX = 1 << 2
@@ -30,6 +31,7 @@ SIGNATURES = {
     "silhouette_workspace_bytes": (_SZ, [_I64, _I32, _I32, _I32, _I32, _I32]),
     "silhouette_sqeuclid": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "silhouette_cosine": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "silhouette_kl": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "silhouette_cluster_stats": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
     "silhouette_stream_workspace_bytes": (_SZ, [_I64, _I64, _I32, _I32, _I32, _I32, _I32]),
     "silhouette_stream": (ctypes.c_int, [_I32, _P, _I32, _P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P, _I64, _P, _SZ, _P]),

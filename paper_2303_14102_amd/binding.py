@@ -12,7 +12,7 @@ import torch
 
 from . import _lib as L
 
-METRIC = {"sqeuclid": L.SIL_SQEUCLID, "cosine": L.SIL_COSINE}
+METRIC = {"sqeuclid": L.SIL_SQEUCLID, "cosine": L.SIL_COSINE, "kl": L.SIL_KL}
 
 
 def _dtype_code(X: torch.Tensor) -> int:
@@ -66,9 +66,11 @@ def silhouette(X: torch.Tensor, labels: torch.Tensor, K: int, metric: str = "sqe
                workspace: Optional[torch.Tensor] = None, check_status: bool = False):
     """Per-point s_i (float32 [N] or None) and the mean S (float64 0-d tensor on the device).
 
-    products: bf16/fp8 cross-term products (1, 2, 3; 0 = library default).  centre: subtract
-    the global mean first (squared Euclidean only).  euclid_approx: the approximate Euclidean
-    form (square roots of the point-to-cluster mean squared distances; squared Euclidean only).
+    metric: "sqeuclid", "cosine" or "kl" (the generalized Kullback-Leibler divergence of positive
+    vectors, fp32 or bf16 storage).  products: bf16/fp8 cross-term products (1, 2, 3; 0 = library
+    default).  centre: subtract the global mean first (squared Euclidean only).  euclid_approx:
+    the approximate Euclidean form (square roots of the point-to-cluster mean squared distances;
+    squared Euclidean only).
     workspace: a uint8 device tensor of at least workspace_bytes(...) bytes, reused across
     calls; allocated here when None.
     """
@@ -80,7 +82,8 @@ def silhouette(X: torch.Tensor, labels: torch.Tensor, K: int, metric: str = "sqe
         workspace = new_workspace(N, D, K, metric, X.dtype, flags, X.device)
     s = torch.empty(N, dtype=torch.float32, device=X.device) if want_s else None
     S = torch.empty((), dtype=torch.float64, device=X.device)
-    fn = L.load().silhouette_sqeuclid if metric == "sqeuclid" else L.load().silhouette_cosine
+    lib = L.load()
+    fn = {"sqeuclid": lib.silhouette_sqeuclid, "cosine": lib.silhouette_cosine, "kl": lib.silhouette_kl}[metric]
     rc = fn(_ptr(X), _dtype_code(X), _ptr(col_scale), _ptr(labels), N, D, int(K), int(products), flags,
             _ptr(s), _ptr(S), _ptr(workspace), workspace.numel(), _stream(X.device))
     L.check(rc, f"silhouette_{metric}")

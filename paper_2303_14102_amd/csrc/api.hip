@@ -92,7 +92,7 @@ static int check_common(const void* X, int32_t dtype, const float* col_scale,
                         const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t metric,
                         const void* ws, size_t ws_bytes, int32_t flags, WsLayout* L) {
   if (!shape_ok(N, D, K) || !X || !labels) return SIL_E_ARG;
-  if (metric != SIL_SQEUCLID && metric != SIL_COSINE) return SIL_E_ARG;
+  if (metric != SIL_SQEUCLID && metric != SIL_COSINE && metric != SIL_KL) return SIL_E_ARG;
   if (dtype != SIL_F32 && dtype != SIL_BF16 && dtype != SIL_FP8_E4M3) return SIL_E_DTYPE;
   if (dtype == SIL_FP8_E4M3 && !col_scale) return SIL_E_DTYPE;
   *L = make_layout(N, D, K, metric, dtype, flags);
@@ -127,8 +127,13 @@ static int forward(int32_t metric, const void* X, int32_t dtype, const float* co
   if ((flags & SIL_FLAG_EUCLID_APPROX) &&
       (metric != SIL_SQEUCLID || (flags & SIL_FLAG_SAVE_FOR_GRAD)))
     return SIL_E_ARG;
+  if (metric == SIL_KL) {  // no backward; fp32 or bf16 storage
+    if (flags & (SIL_FLAG_SAVE_FOR_GRAD | SIL_FLAG_EUCLID_APPROX)) return SIL_E_ARG;
+    if (dtype == SIL_FP8_E4M3) return SIL_E_DTYPE;
+  }
   const WsPtrs w = carve(L, ws);
   if ((flags & SIL_FLAG_SAVE_FOR_GRAD) && dtype != SIL_F32) return SIL_E_DTYPE;
+  products = run_products(metric, dtype, flags, products);
   const int64_t nblocks = ceil_div(N, main_rows_per_block(dtype, L.DPX, products));
   Problem p{X, col_scale, labels, N, D, L.DPX, K, L.Kpad, dtype, metric, products, flags, s, S,
             nblocks};
@@ -242,6 +247,13 @@ int silhouette_sqeuclid(const void* X, int32_t dtype, const float* col_scale,
                  ws_bytes, stream);
 }
 
+int silhouette_kl(const void* X, int32_t dtype, const float* col_scale, const int32_t* labels,
+                  int64_t N, int32_t D, int32_t K, int32_t products, int32_t flags, float* s,
+                  double* S, void* ws, size_t ws_bytes, void* stream) {
+  return forward(SIL_KL, X, dtype, col_scale, labels, N, D, K, products,
+                 flags & ~SIL_FLAG_NO_CENTRE, s, S, ws, ws_bytes, stream);
+}
+
 int silhouette_cosine(const void* X, int32_t dtype, const float* col_scale, const int32_t* labels,
                       int64_t N, int32_t D, int32_t K, int32_t products, int32_t flags, float* s,
                       double* S, void* ws, size_t ws_bytes, void* stream) {
@@ -342,6 +354,7 @@ const char* silhouette_strerror(int status) {
     case SIL_E_NONFINITE: return "X holds a NaN or an infinity";
     case SIL_E_WORKSPACE: return "workspace missing, misaligned or too small";
     case SIL_E_HIP: return "a HIP runtime call failed";
+    case SIL_E_DOMAIN: return "an entry lies outside the distance's domain (KL needs positive entries)";
     default: return "unknown status";
   }
 }

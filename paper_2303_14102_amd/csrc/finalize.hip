@@ -67,7 +67,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One wave per (padded) cluster.  GEMM table row k (DPX entries):
 //   fp32:  [alpha mu'_k (D), 0 ...]
 //   bf16:  hi = [bf16(alpha mu'_k) (D), 0 ...], lo = [bf16(alpha mu'_k - hi) (D), 0 ...]
-// alpha = -2 (squared Euclidean) or -1 (cosine) is a power of two, so alpha mu' splits exactly
+// alpha = -2 (squared Euclidean) or -1 (cosine, KL) is a power of two, so alpha mu' splits exactly
 // like mu'.  The constant c_k goes to ctab (fp32), which the fused kernels add to the cross term
 // before the minimum.  Empty and padding clusters get c_k = kEmptyC (large and finite) and a
 // zero mean.
@@ -124,6 +124,11 @@ __device__ __forceinline__ void finalize_body(
         // form gives ||x' - mu'_k||^2, the K-means assignment's distance
         c = with_var ? muc2 + sigma2 : muc2;
         av = sigma2;
+      } else if (METRIC == SIL_KL) {
+        // V holds sum log y and psi sum_y sum_l y: the table row is -(mean log y), the
+        // constant the mean of sum_l y, which the a-path adds too
+        c = psi[k] / dn;
+        av = c;
       } else {
         c = 1.0;
         av = fmax(0.0, 1.0 - mu2);
@@ -160,6 +165,9 @@ hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w,
   if (p.metric == SIL_SQEUCLID) {
     if (bf) SIL_FIN(SIL_SQEUCLID, true);
     else SIL_FIN(SIL_SQEUCLID, false);
+  } else if (p.metric == SIL_KL) {
+    if (bf) SIL_FIN(SIL_KL, true);
+    else SIL_FIN(SIL_KL, false);
   } else {
     if (bf) SIL_FIN(SIL_COSINE, true);
     else SIL_FIN(SIL_COSINE, false);

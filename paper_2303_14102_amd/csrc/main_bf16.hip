@@ -44,8 +44,10 @@ void launch_main_bf16(const MainArgs& m, int DPX, int metric, int products, unsi
                       hipStream_t st) {
   if (metric == SIL_SQEUCLID)
     run_metric<SIL_SQEUCLID>(m, DPX, products, grid, st);
-  else
+  else if (metric == SIL_COSINE)
     run_metric<SIL_COSINE>(m, DPX, products, grid, st);
+  else
+    run_metric<SIL_KL>(m, DPX, products, grid, st);
 }
 
 }  // namespace sil

@@ -23,12 +23,27 @@ static void run_f32_dp(const MainArgs& m, int DPX, bool save, unsigned grid, hip
   }
 }
 
+template <int DPX>
+static void run_f32_kl(const MainArgs& m, unsigned grid, hipStream_t st) {
+  k_main_f32<DPX, 1, SIL_KL, false><<<grid, 256, 0, st>>>(m);
+}
+
 void launch_main_f32(const MainArgs& m, int DPX, int metric, bool save, unsigned grid,
                      hipStream_t st) {
-  if (metric == SIL_SQEUCLID)
+  if (metric == SIL_SQEUCLID) {
     run_f32_dp<SIL_SQEUCLID>(m, DPX, save, grid, st);
-  else
+  } else if (metric == SIL_COSINE) {
     run_f32_dp<SIL_COSINE>(m, DPX, save, grid, st);
+  } else {  // the KL divergence has no backward, so no kernels that keep a_i, b_i
+    switch (DPX) {
+      case 16: run_f32_kl<16>(m, grid, st); break;
+      case 24: run_f32_kl<24>(m, grid, st); break;
+      case 40: run_f32_kl<40>(m, grid, st); break;
+      case 72: run_f32_kl<72>(m, grid, st); break;
+      case 128: run_f32_kl<128>(m, grid, st); break;
+      default: run_f32_kl<256>(m, grid, st); break;
+    }
+  }
 }
 
 }  // namespace sil

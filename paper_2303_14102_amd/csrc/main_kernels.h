@@ -218,8 +218,8 @@ __device__ __forceinline__ void make_blocks(const MainArgs& a, const RowPre<NB>&
 // ------------------------------------------------------------------------------------------
 // Prologue shared by both kernel families.  Lane (r = lane%32, h = lane/32) holds, for each of
 // its NB row blocks, the chunks c = 2q + h (q < NQ) of W elements of row r: it decodes them,
-// centres / normalises, computes its halves of ||x'||^2 and of the a-path sum, and hands each
-// transformed chunk (zero past D) to emit(nb, q, vals).
+// centres / normalises, computes its halves of ||x'||^2 (phi(x) for KL) and of the a-path sum,
+// and hands each transformed chunk (zero past D) to emit(nb, q, vals).
 // When D is a multiple of W every chunk is one aligned vector load, issued for the whole row
 // before any is used (addresses clamped in range, values masked afterwards).
 
@@ -332,13 +332,21 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
       float v[W];
 #pragma unroll
       for (int e = 0; e < W; ++e) {
-        if constexpr (METRIC == SIL_COSINE)
-          v[e] = xv[q][e] * inv;
-        else
-          v[e] = ok ? xv[q][e] - mv[e] : 0.0f;  // mvec is zero when not centring
-        nx = fmaf(v[e], v[e], nx);
-        const float dd = v[e] - at[e];
-        ad = fmaf(dd, dd, ad);
+        if constexpr (METRIC == SIL_KL) {
+          // phi(x) = sum x log x - x for the row term, x . (mean log y) of the own cluster for
+          // the a-path; x is not centred (the divergence is not translation invariant)
+          v[e] = ok ? xv[q][e] : 0.0f;
+          nx += v[e] > 0.0f ? v[e] * logf(v[e]) - v[e] : 0.0f;
+          ad = fmaf(v[e], at[e], ad);
+        } else {
+          if constexpr (METRIC == SIL_COSINE)
+            v[e] = xv[q][e] * inv;
+          else
+            v[e] = ok ? xv[q][e] - mv[e] : 0.0f;  // mvec is zero when not centring
+          nx = fmaf(v[e], v[e], nx);
+          const float dd = v[e] - at[e];
+          ad = fmaf(dd, dd, ad);
+        }
       }
       emit(nb, q, v);
     }
@@ -347,7 +355,12 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
     nrow[nb] = nx;
     if (o >= 0) {
       const float sc = a.ascale[o];
-      arow[nb] = METRIC == SIL_SQEUCLID ? sc * (ad + a.avec[o]) : sc * 0.5f * (a.avec[o] + ad);
+      if constexpr (METRIC == SIL_SQEUCLID)
+        arow[nb] = sc * (ad + a.avec[o]);
+      else if constexpr (METRIC == SIL_COSINE)
+        arow[nb] = sc * 0.5f * (a.avec[o] + ad);
+      else  // m_io = phi(x) + c_o - x . (mean log y)_o
+        arow[nb] = sc * (nx + a.avec[o] - ad);
     } else {
       arow[nb] = 0.0f;
     }
@@ -459,7 +472,7 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Bloc
     const int64_t row = B.row[nb];
     const int32_t o = B.lab[nb];
     float b = lds_min[nb * 32 + r];
-    if constexpr (METRIC == SIL_SQEUCLID) b += nrow[nb];
+    if constexpr (METRIC != SIL_COSINE) b += nrow[nb];  // ||x'||^2, or phi(x) for KL
     b = fmaxf(b, 0.0f);
     if constexpr (SAVE) {
       if (a.assign) {  // K-means assignment: nearest mean and the squared distance to it

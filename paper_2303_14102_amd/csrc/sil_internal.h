@@ -155,6 +155,15 @@ hipError_t launch_copy_stats(const Problem& p, const WsLayout& L, const WsPtrs& 
 // rows per workgroup of the fused kernel for this problem (host and workspace sizing)
 int main_rows_per_block(int dtype, int DPX, int products);
 
+// Split products the bf16 kernel runs for a requested count.  When X is stored bf16 and x' = x
+// (squared Euclidean without centring, KL) the low bf16 half of x' is zero, so the third product
+// adds only zeros: the two-product kernel gives the same sums with a third less MFMA work.
+inline int run_products(int metric, int dtype, int flags, int products) {
+  const bool exact = dtype == SIL_BF16 && (metric == SIL_KL || (metric == SIL_SQEUCLID &&
+                                                                (flags & SIL_FLAG_NO_CENTRE)));
+  return exact && products == 3 ? 2 : products;
+}
+
 // backward (dS/dX) from the a_i, b_i, neighbour ids kept by a forward call
 hipError_t launch_backward(const Problem& p, const WsLayout& L, const WsPtrs& w, const double* gS,
                            float* dX, hipStream_t st);

@@ -4,6 +4,10 @@
 //   Y_k   = sum_{j in k} x_j                  (Eq.8)       squared Euclidean
 //   Psi_k = sum_{j in k} ||x_j||^2            (Eq.5, Eq.6)
 //   Omega_k = sum_{j in k} x_j / ||x_j||      (Eq.15, Eq.16) cosine
+//   sum_{j in k} log x_j, sum_{j in k} sum_l x_jl              generalized KL (the Bregman
+//                                              statistics of the divergence; positive entries;
+//                                              each log in fp32 (the entries are fp32 or bf16
+//                                              values), the sums in FP64)
 //
 // The paper accumulates Y and Psi together in one pass with per-worker partial sums that one
 // node then adds up (footnotes to Eq.6 and Eq.9).  On the GPU the "workers" are waves, and the
@@ -340,7 +344,7 @@ __device__ __forceinline__ void segreduce_body(
   int64_t rs = offset[kc], re = offset[kc + 1];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   double accq = 0.0;
-  bool bad_value = false, zero_norm = false;
+  bool bad_value = false, zero_norm = false, domain = false;
 
   auto flush = [&]() {
     for (int off = G; off < 64; off <<= 1)
@@ -378,8 +382,14 @@ __device__ __forceinline__ void segreduce_body(
         if (col < D) {
           const double v = load_elem<DT>(X, col_scale, row, D, col);
           bad_value |= !isfinite(v);
-          x[e] = v;
-          sq = fma(x[e], x[e], sq);
+          if constexpr (METRIC == SIL_KL) {  // sum log y and sum_l y (positive entries only)
+            domain |= !(v > 0.0);
+            x[e] = v > 0.0 ? static_cast<double>(logf(static_cast<float>(v))) : 0.0;
+            sq += v;
+          } else {
+            x[e] = v;
+            sq = fma(x[e], x[e], sq);
+          }
         }
       }
     }
@@ -395,7 +405,7 @@ __device__ __forceinline__ void segreduce_body(
     while (true) {
       if (!done && pos < re) {
         for (int e = 0; e < 4; ++e) acc[e] += x[e];
-        if constexpr (METRIC == SIL_SQEUCLID) accq += sq;
+        if constexpr (METRIC != SIL_COSINE) accq += sq;
         done = true;
       }
       if (__all(done)) break;
@@ -408,6 +418,7 @@ __device__ __forceinline__ void segreduce_body(
   flush();
   if (bad_value) set_status(hdr, SIL_E_NONFINITE);
   if (zero_norm) set_status(hdr, SIL_E_ZERO_NORM);
+  if (domain) set_status(hdr, SIL_E_DOMAIN);
 }
 
 template <int DT, int METRIC>
@@ -474,7 +485,7 @@ __device__ __forceinline__ void segreduce_vec_body(
 #pragma unroll
   for (int e = 0; e < E; ++e) acc[e] = 0.0;
   double accq = 0.0;
-  bool bad_value = false, zero_norm = false;
+  bool bad_value = false, zero_norm = false, domain = false;
 
   auto flush = [&]() __attribute__((always_inline)) {
     for (int off = G; off < 64; off <<= 1)
@@ -507,7 +518,13 @@ __device__ __forceinline__ void segreduce_vec_body(
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       bad_value |= valid && !isfinite(x[e]);
-      sq = fma(x[e], x[e], sq);
+      if constexpr (METRIC == SIL_KL) {  // sum log y and sum_l y (positive entries only)
+        domain |= valid && !(x[e] > 0.0);
+        sq += x[e];
+        x[e] = x[e] > 0.0 ? static_cast<double>(logf(static_cast<float>(x[e]))) : 0.0;
+      } else {
+        sq = fma(x[e], x[e], sq);
+      }
     }
     if constexpr (METRIC == SIL_COSINE) {
       double rowsq = sq;
@@ -538,7 +555,7 @@ __device__ __forceinline__ void segreduce_vec_body(
         prepare(raw[u], true, x, sq);
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[e] += x[e];
-        if constexpr (METRIC == SIL_SQEUCLID) accq += sq;
+        if constexpr (METRIC != SIL_COSINE) accq += sq;
       }
       continue;
     }
@@ -552,7 +569,7 @@ __device__ __forceinline__ void segreduce_vec_body(
         if (!done && pos < re) {
 #pragma unroll
           for (int e = 0; e < E; ++e) acc[e] += x[e];
-          if constexpr (METRIC == SIL_SQEUCLID) accq += sq;
+          if constexpr (METRIC != SIL_COSINE) accq += sq;
           done = true;
         }
         if (__all(done)) break;
@@ -566,6 +583,7 @@ __device__ __forceinline__ void segreduce_vec_body(
   flush();
   if (bad_value) set_status(hdr, SIL_E_NONFINITE);
   if (zero_norm) set_status(hdr, SIL_E_ZERO_NORM);
+  if (domain) set_status(hdr, SIL_E_DOMAIN);
 }
 
 template <int DT, int METRIC>
@@ -820,6 +838,9 @@ hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hi
     if (p.dtype == SIL_F32) SIL_SEG(SIL_F32, SIL_SQEUCLID);
     else if (p.dtype == SIL_BF16) SIL_SEG(SIL_BF16, SIL_SQEUCLID);
     else SIL_SEG(SIL_FP8_E4M3, SIL_SQEUCLID);
+  } else if (p.metric == SIL_KL) {  // fp32 or bf16 storage
+    if (p.dtype == SIL_F32) SIL_SEG(SIL_F32, SIL_KL);
+    else SIL_SEG(SIL_BF16, SIL_KL);
   } else {
     if (p.dtype == SIL_F32) SIL_SEG(SIL_F32, SIL_COSINE);
     else if (p.dtype == SIL_BF16) SIL_SEG(SIL_BF16, SIL_COSINE);

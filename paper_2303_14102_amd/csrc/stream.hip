@@ -185,6 +185,7 @@ static int stream_forward(int32_t metric, const void* Xh, int32_t dtype, const f
   if (dtype == SIL_FP8_E4M3 && !col_scale) return SIL_E_DTYPE;
   if (products == 0) products = 3;
   if (products < 1 || products > 3) return SIL_E_ARG;
+  products = run_products(metric, dtype, flags, products);
   const StreamLayout SL = stream_layout(N, chunk_rows, D, K, metric, dtype, flags);
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) || ws_bytes < SL.total)
     return SIL_E_WORKSPACE;

@@ -140,8 +140,21 @@ def test_mahalanobis_host_checks(lib):
     assert sz(0, 8, 4, 0) == 0
 
 
+def test_kl_host_checks(lib):
+    from paper_2303_14102_amd import _lib
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x100000)
+    f = lib.silhouette_kl
+    assert f(fake, 2, fake, fake, 10, 4, 2, 0, 0, None, fake, ws, 1 << 30, None) == -2   # fp8
+    assert f(fake, 0, None, fake, 10, 4, 2, 0, _lib.SIL_FLAG_SAVE_FOR_GRAD, None, fake, ws, 1 << 30, None) == -1
+    assert f(fake, 0, None, fake, 10, 4, 2, 0, _lib.SIL_FLAG_EUCLID_APPROX, None, fake, ws, 1 << 30, None) == -1
+    assert f(fake, 0, None, fake, 10, 4, 2, 4, 0, None, fake, ws, 1 << 30, None) == -1   # products
+    assert f(fake, 0, None, fake, 10, 4, 2, 0, 0, None, fake, ws, 16, None) == -7        # workspace
+    assert lib.silhouette_workspace_bytes(100, 8, 4, _lib.SIL_KL, 0, 0) > 0
+
+
 def test_strerror(lib):
-    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, 99):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, 99):
         assert isinstance(lib.silhouette_strerror(code), bytes)
 
 
