@@ -258,9 +258,9 @@ def bench_stream(args, spec, X, col_scale, labels, dev):
 
 def stats_kernel(args, spec):
     """Name of the statistics pass's reduction kernel for this run: whole-wave rows for squared
-    Euclidean fp32 / bf16 rows of 256, 512 or 1024 bytes, 16-byte chunks otherwise."""
+    Euclidean or KL fp32 / bf16 rows of 256, 512 or 1024 bytes, 16-byte chunks otherwise."""
     rb = spec.d * {"f32": 4, "bf16": 2, "fp8": 1}[args.form]
-    row = args.metric == "sqeuclid" and args.form != "fp8" and rb in (256, 512, 1024)
+    row = args.metric in ("sqeuclid", "kl") and args.form != "fp8" and rb in (256, 512, 1024)
     return "k_segreduce_row" if row else "k_segreduce_vec"
 
 

@@ -602,13 +602,15 @@ __global__ __launch_bounds__(256) void k_segreduce_vec(
 // sorted positions are wave-uniform: row ids come from scalar loads of perm, run boundaries are
 // scalar branches, and Psi is reduced across the wave only when a run is stored.  Batches of U
 // rows are double-buffered: the rows of batch t + 1 and the ids of batch t + 2 are in flight
-// while batch t is accumulated.  Runs are stored as in k_segreduce.
-template <int DT, int CH>
+// while batch t is accumulated.  Runs are stored as in k_segreduce.  METRIC is the squared
+// Euclidean distance (sums of x and ||x||^2) or KL (sums of log x and of the entries).
+template <int DT, int CH, int METRIC = SIL_SQEUCLID>
 __device__ __forceinline__ void segreduce_row_body(
     const void* __restrict__ X, const int32_t* __restrict__ perm, const int32_t* __restrict__ offset, int32_t K, int32_t D,
     int64_t nseg, double* __restrict__ V, double* __restrict__ psi,
     double* __restrict__ segpart, int32_t* __restrict__ hdr, int64_t bid) {
   static_assert(DT == SIL_F32 || DT == SIL_BF16, "fp32 or bf16 rows");
+  static_assert(METRIC == SIL_SQEUCLID || METRIC == SIL_KL, "squared Euclidean or KL sums");
   constexpr int ESZ = DT == SIL_F32 ? 4 : 2;
   constexpr int E = CH / ESZ;
   constexpr int NW = CH / 4;
@@ -630,7 +632,7 @@ __device__ __forceinline__ void segreduce_row_body(
 #pragma unroll
   for (int e = 0; e < E; ++e) acc[e] = 0.0;
   double accq = 0.0;
-  bool bad_value = false;
+  bool bad_value = false, domain = false;
 
   auto flush = [&]() __attribute__((always_inline)) {
     for (int off = 1; off < 64; off <<= 1) accq += shfl_xor_f64(accq, off);
@@ -666,8 +668,14 @@ __device__ __forceinline__ void segreduce_row_body(
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       bad_value |= !isfinite(x[e]);
-      acc[e] += x[e];
-      accq = fma(x[e], x[e], accq);
+      if constexpr (METRIC == SIL_KL) {  // log in fp32 (x is an fp32 value), sums in FP64
+        domain |= !(x[e] > 0.0);
+        accq += x[e];
+        acc[e] += x[e] > 0.0 ? static_cast<double>(logf(static_cast<float>(x[e]))) : 0.0;
+      } else {
+        acc[e] += x[e];
+        accq = fma(x[e], x[e], accq);
+      }
     }
   };
 
@@ -728,15 +736,17 @@ __device__ __forceinline__ void segreduce_row_body(
   }
   flush();
   if (bad_value) set_status(hdr, SIL_E_NONFINITE);
+  if (domain) set_status(hdr, SIL_E_DOMAIN);
 }
 
-template <int DT, int CH>
+template <int DT, int CH, int METRIC>
 __global__ __launch_bounds__(256) void k_segreduce_row(
     const void* __restrict__ X, const int32_t* __restrict__ perm,
     const int32_t* __restrict__ offset, int32_t K, int32_t D, int64_t nseg,
     double* __restrict__ V, double* __restrict__ psi, double* __restrict__ segpart,
     int32_t* __restrict__ hdr) {
-  segreduce_row_body<DT, CH>(X, perm, offset, K, D, nseg, V, psi, segpart, hdr, blockIdx.x);
+  segreduce_row_body<DT, CH, METRIC>(X, perm, offset, K, D, nseg, V, psi, segpart, hdr,
+                                     blockIdx.x);
 }
 
 // Sums of clusters whose sorted range spans several segments.  One thread per (cluster,
@@ -774,19 +784,19 @@ __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ off
 
 // ------------------------------------------------------------------------------------------
 
-template <int DT>
+template <int DT, int METRIC>
 static void launch_seg_row(const Problem& p, const WsLayout& L, const WsPtrs& w, int ch,
                            unsigned nblk, hipStream_t st) {
-  if constexpr (DT != SIL_FP8_E4M3) {
+  if constexpr (DT != SIL_FP8_E4M3 && METRIC != SIL_COSINE) {
     if (ch == 4)
-      k_segreduce_row<DT, 4><<<nblk, 256, 0, st>>>(p.X, w.perm, w.offset, p.K, p.D,
-                                                   L.nseg, w.V, w.psi, w.segpart, w.hdr);
+      k_segreduce_row<DT, 4, METRIC><<<nblk, 256, 0, st>>>(p.X, w.perm, w.offset, p.K, p.D,
+                                                           L.nseg, w.V, w.psi, w.segpart, w.hdr);
     else if (ch == 8)
-      k_segreduce_row<DT, 8><<<nblk, 256, 0, st>>>(p.X, w.perm, w.offset, p.K, p.D,
-                                                   L.nseg, w.V, w.psi, w.segpart, w.hdr);
+      k_segreduce_row<DT, 8, METRIC><<<nblk, 256, 0, st>>>(p.X, w.perm, w.offset, p.K, p.D,
+                                                           L.nseg, w.V, w.psi, w.segpart, w.hdr);
     else
-      k_segreduce_row<DT, 16><<<nblk, 256, 0, st>>>(p.X, w.perm, w.offset, p.K, p.D,
-                                                    L.nseg, w.V, w.psi, w.segpart, w.hdr);
+      k_segreduce_row<DT, 16, METRIC><<<nblk, 256, 0, st>>>(p.X, w.perm, w.offset, p.K, p.D,
+                                                            L.nseg, w.V, w.psi, w.segpart, w.hdr);
   }
 }
 
@@ -820,12 +830,12 @@ hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hi
   int32_t Gv, G, E;
   stats_lanes(p.D, p.dtype, &Gv, &G, &E);
   const bool vec = Gv != 0;
-  // whole-wave rows (squared Euclidean, fp32 or bf16 rows of 256, 512 or 1024 bytes)
-  const int rowch = p.metric == SIL_SQEUCLID ? row_chunk(p.D, p.dtype) : 0;
+  // whole-wave rows (squared Euclidean or KL, fp32 or bf16 rows of 256, 512 or 1024 bytes)
+  const int rowch = p.metric != SIL_COSINE ? row_chunk(p.D, p.dtype) : 0;
 #define SIL_SEG(DT, MT)                                                                         \
   do {                                                                                          \
-    if (rowch && MT == SIL_SQEUCLID)                                                            \
-      launch_seg_row<DT>(p, L, w, rowch, nblk, st);                                             \
+    if (rowch && MT != SIL_COSINE)                                                              \
+      launch_seg_row<DT, MT>(p, L, w, rowch, nblk, st);                                         \
     else if (vec)                                                                               \
       k_segreduce_vec<DT, MT><<<nblk, 256, 0, st>>>(p.X, p.col_scale, w.perm, w.offset, p.K,    \
                                                     p.D, Gv, L.nseg, w.V, w.psi, w.segpart,     \

@@ -67,6 +67,7 @@ CASES = [
     (2_000, 256, 40, "f32", 0, 0, 4),
     (1_500, 3, 5, "bf16", 1, 1, 5),
     (140_001, 64, 300, "bf16", 3, 0, 6),
+    (60_001, 128, 257, "f32", 0, 1, 9),   # whole-wave row statistics, 512-byte rows
 ]
 
 
@@ -98,13 +99,16 @@ def test_kl_scale_invariance(dev):
     assert float((s1 - s2).abs().max()) <= 1e-4 and abs(S1.item() - S2.item()) <= 1e-6
 
 
-def test_kl_domain_error(dev):
+@pytest.mark.parametrize("d,form", [(16, "f32"), (128, "bf16"), (64, "f32")])
+def test_kl_domain_error(dev, d, form):
+    # a zero entry: chunked statistics (D = 16) and whole-wave rows (256-byte rows)
     from paper_2303_14102_amd import _lib
     from paper_2303_14102_amd import binding as sil
-    X, lab = positive_blobs(3_000, 16, 6, 8, 0)
+    X, lab = positive_blobs(3_000, d, 6, 8, 0)
     X[1_234, 5] = 0.0
+    Xd = storage(X.to(dev), form)[0]
     with pytest.raises(_lib.SilhouetteError) as e:
-        sil.silhouette(X.to(dev), lab.to(dev), 6, "kl", check_status=True)
+        sil.silhouette(Xd, lab.to(dev), 6, "kl", check_status=True)
     assert e.value.code == -9
-    s, S = sil.silhouette(X.to(dev), lab.to(dev), 6, "kl")
+    s, S = sil.silhouette(Xd, lab.to(dev), 6, "kl")
     assert math.isnan(S.item()) and torch.isnan(s).all()
