@@ -256,6 +256,21 @@ def bench_stream(args, spec, X, col_scale, labels, dev):
     print(json.dumps(res), flush=True)
 
 
+def offset_ratio(X32):
+    """|m| / rms |x - m| of the data (m the global mean): the folded centring's cross-term error
+    scales with |x| <= |m| + |x - m| where the three-product form's scales with |x - m|."""
+    import torch
+    m = torch.zeros(X32.shape[1], dtype=torch.float64, device=X32.device)
+    ss = torch.zeros((), dtype=torch.float64, device=X32.device)
+    step = 1 << 22
+    for r0 in range(0, X32.shape[0], step):
+        m += X32[r0:r0 + step].double().sum(0)
+    m /= X32.shape[0]
+    for r0 in range(0, X32.shape[0], step):
+        ss += ((X32[r0:r0 + step].double() - m) ** 2).sum()
+    return float(m.norm() / torch.sqrt(ss / X32.shape[0]))
+
+
 def stats_kernel(args, spec):
     """Name of the statistics pass's reduction kernel for this run: whole-wave rows for squared
     Euclidean or KL fp32 / bf16 rows of 256, 512 or 1024 bytes, 16-byte chunks otherwise."""
@@ -273,7 +288,9 @@ def parse():
                     help="a named blob workload, or ksweep (the batched k-sweep, its own JSON line)")
     ap.add_argument("--metric", default="sqeuclid", choices=["sqeuclid", "cosine", "kl"])
     ap.add_argument("--form", default="bf16", choices=["bf16", "fp8", "f32"])
-    ap.add_argument("--products", type=int, default=3)
+    ap.add_argument("--products", type=int, default=0,
+                    help="bf16/fp8 split products (0: 2 for bf16 squared Euclidean, where the centring "
+                         "folds into c_k, and for bf16 KL; else 3)")
     ap.add_argument("--stream", action="store_true",
                     help="out-of-core: X and labels in pinned host memory, streamed in chunks")
     ap.add_argument("--chunk-rows", type=int, default=4_000_000)
@@ -423,6 +440,8 @@ def bench_ksweep(args):
 
 def main():
     args = parse()
+    if args.products == 0:
+        args.products = 2 if args.form == "bf16" and args.metric in ("sqeuclid", "kl") else 3
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU form is a design note, not a measured path)", file=sys.stderr)
@@ -517,6 +536,9 @@ def main():
                    "metric": args.metric, "storage": args.form,
                    "products": args.products if args.form != "f32" else None,
                    "centred": args.metric == "sqeuclid",
+                   **({"centring": "folded into c_k (x enters the GEMM exact)",
+                       "mean_offset_ratio": offset_ratio(X32)}
+                      if args.metric == "sqeuclid" and args.form == "bf16" and args.products == 2 else {}),
                    **({"euclid_approx": True} if args.euclid_approx else {}),
                    **({"data_transform": "exp(x/4) of the blob coordinates"} if args.metric == "kl" else {})},
         "phases_ms": {"stats": phases[0], "finalize": phases[1], "gemm_epilogue": phases[2],

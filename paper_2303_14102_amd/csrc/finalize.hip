@@ -69,8 +69,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 //   bf16:  hi = [bf16(alpha mu'_k) (D), 0 ...], lo = [bf16(alpha mu'_k - hi) (D), 0 ...]
 // alpha = -2 (squared Euclidean) or -1 (cosine, KL) is a power of two, so alpha mu' splits exactly
 // like mu'.  The constant c_k goes to ctab (fp32), which the fused kernels add to the cross term
-// before the minimum.  Empty and padding clusters get c_k = kEmptyC (large and finite) and a
-// zero mean.
+// before the minimum; with fold set (the folded centring of the two-product bf16 kernels) it
+// also carries 2 m.mu'_k, m being the fp32 centring vector mvec.  Empty and padding clusters get
+// c_k = kEmptyC (large and finite) and a zero mean.
 constexpr double kEmptyC = 1.0e30;
 
 template <int METRIC, bool BF16TAB>
@@ -79,7 +80,7 @@ __device__ __forceinline__ void finalize_body(
     const double* __restrict__ psi, const double* __restrict__ gmean, int32_t K, int32_t Kpad,
     int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ ctab,
     float* __restrict__ atab, float* __restrict__ avec, float* __restrict__ ascale, int with_var,
-    int64_t bid) {
+    const float* __restrict__ mvec, int fold, int64_t bid) {
   constexpr double ALPHA = METRIC == SIL_SQEUCLID ? -2.0 : -1.0;
   const int lane = threadIdx.x & 63;
   const int32_t k = static_cast<int32_t>(bid) * 4 + (threadIdx.x >> 6);
@@ -92,7 +93,7 @@ __device__ __forceinline__ void finalize_body(
   const int64_t arow = static_cast<int64_t>(k) * DPX; // a-path row
   const int32_t n = k < K ? count[k] : 0;
   const double dn = static_cast<double>(n);
-  double mu2 = 0.0, muc2 = 0.0;
+  double mu2 = 0.0, muc2 = 0.0, mdot = 0.0;
   for (int r = 0; r < nrep; ++r) {
     const int l = lane + 64 * r;
     if (l >= RS) break;
@@ -103,6 +104,7 @@ __device__ __forceinline__ void finalize_body(
     }
     mu2 += mu * mu;
     muc2 += muc * muc;
+    if (fold && l < D) mdot = fma(static_cast<double>(mvec[l]), muc, mdot);
     const double g = ALPHA * muc;  // exact scaling
     if (BF16TAB) {
       const uint16_t hi = f32_to_bf16_rne(static_cast<float>(g));
@@ -115,6 +117,7 @@ __device__ __forceinline__ void finalize_body(
   }
   mu2 = wave_sum(mu2);
   muc2 = wave_sum(muc2);
+  if (fold) mdot = wave_sum(mdot);
   if (lane == 0) {
     double c = kEmptyC, av = 0.0;
     if (n > 0) {
@@ -123,6 +126,7 @@ __device__ __forceinline__ void finalize_body(
         // equals Psi_k/N_k when the centring vector is zero; without the variance term the GEMM
         // form gives ||x' - mu'_k||^2, the K-means assignment's distance
         c = with_var ? muc2 + sigma2 : muc2;
+        if (fold) c -= ALPHA * mdot;  // + 2 m.mu'_k
         av = sigma2;
       } else if (METRIC == SIL_KL) {
         // V holds sum log y and psi sum_y sum_l y: the table row is -(mean log y), the
@@ -147,9 +151,10 @@ __global__ __launch_bounds__(256) void k_finalize(
     const int32_t* __restrict__ count, const double* __restrict__ V,
     const double* __restrict__ psi, const double* __restrict__ gmean, int32_t K, int32_t Kpad,
     int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ ctab,
-    float* __restrict__ atab, float* __restrict__ avec, float* __restrict__ ascale, int with_var) {
+    float* __restrict__ atab, float* __restrict__ avec, float* __restrict__ ascale, int with_var,
+    const float* __restrict__ mvec, int fold) {
   finalize_body<METRIC, BF16TAB>(count, V, psi, gmean, K, Kpad, D, DPX, RS, btab, ctab, atab,
-                                 avec, ascale, with_var, blockIdx.x);
+                                 avec, ascale, with_var, mvec, fold, blockIdx.x);
 }
 
 hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
@@ -158,10 +163,11 @@ hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w,
                                                         w.mvec);
   const unsigned nb = static_cast<unsigned>(ceil_div(p.Kpad, 4));
   const bool bf = p.dtype != SIL_F32;
+  const int fold = centre && !p.assign && fold_centre(p.dtype, p.products, p.metric) ? 1 : 0;
 #define SIL_FIN(MT, BF)                                                                        \
   k_finalize<MT, BF><<<nb, 256, 0, st>>>(w.count, w.V, w.psi, w.gmean, p.K, p.Kpad, p.D, p.DPX, \
                                          table_stride(p.DPX, p.dtype), w.btab, w.ctab, w.atab,  \
-                                         w.avec, w.ascale, p.assign ? 0 : 1)
+                                         w.avec, w.ascale, p.assign ? 0 : 1, w.mvec, fold)
   if (p.metric == SIL_SQEUCLID) {
     if (bf) SIL_FIN(SIL_SQEUCLID, true);
     else SIL_FIN(SIL_SQEUCLID, false);
@@ -203,10 +209,12 @@ __global__ __launch_bounds__(256) void kb_fin(BatchDev b) {
   const int32_t RS = table_stride(q.DPX, SIL_F32);
   if (q.metric == SIL_SQEUCLID)
     finalize_body<SIL_SQEUCLID, false>(q.count, q.V, q.psi, q.gmean, q.K, q.Kpad, q.D, q.DPX, RS,
-                                       q.btab, q.ctab, q.atab, q.avec, q.ascale, 1, it);
+                                       q.btab, q.ctab, q.atab, q.avec, q.ascale, 1, nullptr, 0,
+                                       it);
   else
     finalize_body<SIL_COSINE, false>(q.count, q.V, q.psi, q.gmean, q.K, q.Kpad, q.D, q.DPX, RS,
-                                     q.btab, q.ctab, q.atab, q.avec, q.ascale, 1, it);
+                                     q.btab, q.ctab, q.atab, q.avec, q.ascale, 1, nullptr, 0,
+                                     it);
 }
 
 hipError_t launch_finalize_batched(const BatchLaunch& b, hipStream_t st) {

@@ -222,6 +222,8 @@ __device__ __forceinline__ void make_blocks(const MainArgs& a, const RowPre<NB>&
 // and hands each transformed chunk (zero past D) to emit(nb, q, vals).
 // When D is a multiple of W every chunk is one aligned vector load, issued for the whole row
 // before any is used (addresses clamped in range, values masked afterwards).
+// RAW (squared Euclidean): emit hands over x itself rather than x' = x - m, for the kernels whose
+// tables fold the centring into c_k; the row and a-path terms still use x'.
 
 template <int DT>
 struct RawChunk;
@@ -281,7 +283,7 @@ __device__ __forceinline__ void load_f32w(const float* __restrict__ p, float* ou
   }
 }
 
-template <int DT, int W, int NQ, int NB, int METRIC, typename Emit>
+template <int DT, int W, int NQ, int NB, int METRIC, bool RAW, typename Emit>
 __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B, int lane,
                                          float (&nrow)[NB], float (&arow)[NB], Emit&& emit) {
   constexpr int DPX = 2 * NQ * W;
@@ -348,7 +350,15 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
           ad = fmaf(dd, dd, ad);
         }
       }
-      emit(nb, q, v);
+      if constexpr (RAW) {
+        static_assert(METRIC == SIL_SQEUCLID, "the folded centring is squared Euclidean");
+        float u[W];
+#pragma unroll
+        for (int e = 0; e < W; ++e) u[e] = ok ? xv[q][e] : 0.0f;
+        emit(nb, q, u);
+      } else {
+        emit(nb, q, v);
+      }
     }
     nx += __shfl_xor(nx, 32, 64);
     ad += __shfl_xor(ad, 32, 64);
@@ -635,7 +645,7 @@ __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
   u32x4_t ahi[NB][S];
   u32x4_t alo[NB][P == 3 ? S : 1];
   float nrow[NB], arow[NB];
-  prologue<DT, 8, S, NB, METRIC>(
+  prologue<DT, 8, S, NB, METRIC, kFoldCentre<DT, P, METRIC>>(
       a, B, lane, nrow, arow, [&](int nb, int q, const float* v) __attribute__((always_inline)) {
         uint32_t hw[4], lw[4];
 #pragma unroll
@@ -813,7 +823,7 @@ __device__ __forceinline__ void main_f32_body(const MainArgs& a, int64_t wb, con
 
   f32x4_t areg[NB][NQ];
   float nrow[NB], arow[NB];
-  prologue<SIL_F32, 4, NQ, NB, METRIC>(
+  prologue<SIL_F32, 4, NQ, NB, METRIC, false>(
       a, B, lane, nrow, arow, [&](int nb, int q, const float* v) __attribute__((always_inline)) {
         areg[nb][q] = f32x4_t{v[0], v[1], v[2], v[3]};
       });

@@ -155,6 +155,18 @@ hipError_t launch_copy_stats(const Problem& p, const WsLayout& L, const WsPtrs& 
 // rows per workgroup of the fused kernel for this problem (host and workspace sizing)
 int main_rows_per_block(int dtype, int DPX, int products);
 
+// Folded centring.  The two-product bf16 kernels for the squared Euclidean distance take x
+// itself (exact in bf16 storage) into the GEMM rather than x' = x - m, and the constant carries
+// the centring instead: -2 x'.mu'_k = -2 x.mu'_k + 2 m.mu'_k.  Both products then multiply an
+// exact x, so only the split of mu'_k limits the cross term: relative 2^-16 of |x| |mu'_k|,
+// where the three-product form on x' reaches 2^-16 of |x'| |mu'_k|.  m is the fp32 centring
+// vector the row term uses, so the two agree.
+template <int DT, int P, int METRIC>
+inline constexpr bool kFoldCentre = DT == SIL_BF16 && P == 2 && METRIC == SIL_SQEUCLID;
+inline bool fold_centre(int dtype, int products, int metric) {
+  return dtype == SIL_BF16 && products == 2 && metric == SIL_SQEUCLID;
+}
+
 // Split products the bf16 kernel runs for a requested count.  When X is stored bf16 and x' = x
 // (squared Euclidean without centring, KL) the low bf16 half of x' is zero, so the third product
 // adds only zeros: the two-product kernel gives the same sums with a third less MFMA work.

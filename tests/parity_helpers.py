@@ -22,6 +22,8 @@ def cross_term_eps(form, products, metric, centre, D):
     if form == "f32":
         return acc
     exact_x = metric == "sqeuclid" and not centre  # bf16/fp8 storage is exact in bf16 uncentred
+    if products == 2 and form == "bf16" and metric == "sqeuclid":
+        exact_x = True  # x itself enters the GEMM (folded centring); see fold_norms
     mu_split = 2.0 ** -16                    # hi + lo carries ~16 bits of the mean
     if products == 3:
         return 2.0 ** -16 + acc
@@ -54,14 +56,19 @@ def bound_from_stats(form, products, metric, centre, rows, stats, a, b, root=Fal
         cmax = 1.0
     nx = np.linalg.norm(xp, axis=1)
     eps = cross_term_eps(form, products, metric, centre, D)
+    nxc = nx  # norm of the GEMM operand
+    if metric == "sqeuclid" and centre and form == "bf16" and products == 2:
+        # folded centring: the GEMM multiplies x itself, and c_k carries 2 m.mu'_k
+        nxc = np.linalg.norm(rows, axis=1)
+        cmax = cmax + 2 * np.abs(mup @ m).max()
     if root:  # the squared quantities and their bounds, then the roots' interval widths
         a2, b2 = np.asarray(a) ** 2, np.asarray(b) ** 2
-        db2 = 2 * eps * nx * np.linalg.norm(mup, axis=1).max() + 4 * U32 * (nx ** 2 + cmax)
+        db2 = 2 * eps * nxc * np.linalg.norm(mup, axis=1).max() + 4 * U32 * (nx ** 2 + nxc ** 2 + cmax)
         da2 = 4 * U32 * (D + 8) * (a2 + np.abs(a2))
         da = np.sqrt(a2 + da2) - np.sqrt(np.maximum(a2 - da2, 0.0))
         db = np.sqrt(b2 + db2) - np.sqrt(np.maximum(b2 - db2, 0.0))
         return 2 * (da + db) / np.maximum(np.maximum(a, b), 1e-30) + 4 * U32
-    db = 2 * eps * nx * np.linalg.norm(mup, axis=1).max() + 4 * U32 * (nx ** 2 + cmax)
+    db = 2 * eps * nxc * np.linalg.norm(mup, axis=1).max() + 4 * U32 * (nx ** 2 + nxc ** 2 + cmax)
     da = 4 * U32 * (D + 8) * (a + np.abs(a))
     return 2 * (da + db) / np.maximum(np.maximum(a, b), 1e-30) + 4 * U32
 
