@@ -73,7 +73,7 @@ __global__ void k_poison_labels(const int32_t* __restrict__ hdr, int32_t* __rest
 int main_rows_per_block(int dtype, int DPX, int products) {
   if (dtype == SIL_F32) return kMainWaves * 32;
   if (products < 1 || products > 3) products = 3;
-  return kMainWaves * 32 * bf16_nb(DPX, products);
+  return kMainWaves * 32 * bf16_nb(DPX, products, dtype);
 }
 
 hipError_t launch_main(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {

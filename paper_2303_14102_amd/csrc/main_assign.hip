@@ -8,7 +8,7 @@ namespace sil {
 
 template <int DPX, int DT>
 static void run_assign(const MainArgs& m, unsigned grid, hipStream_t st) {
-  k_main_bf16<DPX, bf16_nb(DPX, 3), 3, DT, SIL_SQEUCLID, true><<<grid, 256, 0, st>>>(m);
+  k_main_bf16<DPX, bf16_nb(DPX, 3, DT), 3, DT, SIL_SQEUCLID, true><<<grid, 256, 0, st>>>(m);
 }
 
 template <int DT>

@@ -4,11 +4,12 @@
 namespace sil {
 
 // Split products (2 or 3) with one row block per wave at depths up to 128 run with 32-cluster
-// tiles and three workgroups per CU, the other forms with 64-cluster tiles and two; measured on
-// the 128-dimension workload: 32-cluster tiles -9% (2 products), -2% (3), +5% (1).
+// tiles and three workgroups per CU, the other forms with 64-cluster tiles and two.  Measured on
+// the 128-dimension workload with one row block: 32-cluster tiles -9% (2 products), -2% (3),
+// +5% (1); two products with two row blocks (64-cluster tiles): a further -8%.
 template <int DPX, int P, int METRIC>
 static void run_p(const MainArgs& m, unsigned grid, hipStream_t st) {
-  constexpr int NB = bf16_nb(DPX, P);
+  constexpr int NB = bf16_nb(DPX, P, SIL_BF16);
   if constexpr (P >= 2 && DPX <= 128 && NB == 1) {
     MainArgs m2 = m;
     m2.ntiles = m.ntiles * (kColTile / 32);

@@ -7,7 +7,7 @@ namespace sil {
 // more registers).
 template <int DPX, int P, int METRIC>
 static void run_p(const MainArgs& m, unsigned grid, hipStream_t st) {
-  k_main_bf16<DPX, bf16_nb(DPX, P), P, SIL_FP8_E4M3, METRIC, false><<<grid, 256, 0, st>>>(m);
+  k_main_bf16<DPX, bf16_nb(DPX, P, SIL_FP8_E4M3), P, SIL_FP8_E4M3, METRIC, false><<<grid, 256, 0, st>>>(m);
 }
 
 template <int DPX, int METRIC>

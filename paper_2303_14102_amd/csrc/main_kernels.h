@@ -921,7 +921,12 @@ void launch_main_fp8(const MainArgs& m, int DPX, int metric, int products, unsig
                      hipStream_t st);
 
 // Row blocks of 32 per wave for the bf16 family: two unless the split operands of three
-// products (or a deep row) would not fit the register budget of two waves per SIMD.
-constexpr int bf16_nb(int DPX, int P) { return (P == 3 || DPX > 80) ? 1 : 2; }
+// products (or a deep row) would not fit the register budget of two waves per SIMD.  Two row
+// blocks read each table fragment from LDS once for 64 rows, which halves the LDS traffic per
+// MFMA: at depth 128 with two products it is as large as the MFMA time with one block.  fp8
+// storage stops at depth 80 (its decode would spill at 128).
+constexpr int bf16_nb(int DPX, int P, int DT) {
+  return (P == 3 || DPX > (DT == SIL_BF16 ? 128 : 80)) ? 1 : 2;
+}
 
 }  // namespace sil

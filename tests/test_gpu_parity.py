@@ -189,6 +189,8 @@ LARGER_CASES = [
     (133_333, 48, 256, "sqeuclid", "bf16", 1, 0, 64),
     (135_000, 128, 1000, "cosine", "bf16", 3, 1, 65),
     (150_001, 128, 1000, "sqeuclid", "bf16", 2, 1, 66),
+    (120_007, 100, 300, "cosine", "bf16", 1, 1, 67),   # two row blocks per wave at depth 128
+    (99_999, 120, 129, "sqeuclid", "bf16", 2, 0, 68),
 ]
 
 
