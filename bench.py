@@ -289,8 +289,8 @@ def parse():
     ap.add_argument("--metric", default="sqeuclid", choices=["sqeuclid", "cosine", "kl"])
     ap.add_argument("--form", default="bf16", choices=["bf16", "fp8", "f32"])
     ap.add_argument("--products", type=int, default=0,
-                    help="bf16/fp8 split products (0: 2 for bf16 squared Euclidean, where the centring "
-                         "folds into c_k, and for bf16 KL; else 3)")
+                    help="bf16/fp8 split products (0: 2 for bf16 storage, where x enters the GEMM exact; "
+                         "3 for fp8)")
     ap.add_argument("--stream", action="store_true",
                     help="out-of-core: X and labels in pinned host memory, streamed in chunks")
     ap.add_argument("--chunk-rows", type=int, default=4_000_000)
@@ -441,7 +441,7 @@ def bench_ksweep(args):
 def main():
     args = parse()
     if args.products == 0:
-        args.products = 2 if args.form == "bf16" and args.metric in ("sqeuclid", "kl") else 3
+        args.products = 2 if args.form == "bf16" else 3
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU form is a design note, not a measured path)", file=sys.stderr)
@@ -539,6 +539,8 @@ def main():
                    **({"centring": "folded into c_k (x enters the GEMM exact)",
                        "mean_offset_ratio": offset_ratio(X32)}
                       if args.metric == "sqeuclid" and args.form == "bf16" and args.products == 2 else {}),
+                   **({"normalisation": "1/|x| applied after the minimum (x enters the GEMM exact)"}
+                      if args.metric == "cosine" and args.form == "bf16" and args.products == 2 else {}),
                    **({"euclid_approx": True} if args.euclid_approx else {}),
                    **({"data_transform": "exp(x/4) of the blob coordinates"} if args.metric == "kl" else {})},
         "phases_ms": {"stats": phases[0], "finalize": phases[1], "gemm_epilogue": phases[2],

@@ -133,8 +133,8 @@ __device__ __forceinline__ void finalize_body(
         // constant the mean of sum_l y, which the a-path adds too
         c = psi[k] / dn;
         av = c;
-      } else {
-        c = 1.0;
+      } else {  // cosine: the finish adds the 1 of 1 - z.mu_k after the minimum
+        c = 0.0;
         av = fmax(0.0, 1.0 - mu2);
       }
     }

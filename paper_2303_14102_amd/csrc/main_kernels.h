@@ -222,8 +222,9 @@ __device__ __forceinline__ void make_blocks(const MainArgs& a, const RowPre<NB>&
 // and hands each transformed chunk (zero past D) to emit(nb, q, vals).
 // When D is a multiple of W every chunk is one aligned vector load, issued for the whole row
 // before any is used (addresses clamped in range, values masked afterwards).
-// RAW (squared Euclidean): emit hands over x itself rather than x' = x - m, for the kernels whose
-// tables fold the centring into c_k; the row and a-path terms still use x'.
+// RAW: emit hands over x itself rather than x' = x - m (squared Euclidean: the tables fold the
+// centring into c_k) or z = x / |x| (cosine: the finish scales by 1 / |x|); the row and a-path
+// terms still use x' or z.  For cosine, nrow holds the finish's scale: 1 / |x| (RAW) or 1.
 
 template <int DT>
 struct RawChunk;
@@ -351,7 +352,7 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
         }
       }
       if constexpr (RAW) {
-        static_assert(METRIC == SIL_SQEUCLID, "the folded centring is squared Euclidean");
+        static_assert(METRIC == SIL_SQEUCLID || METRIC == SIL_COSINE, "raw x: squared Euclidean or cosine");
         float u[W];
 #pragma unroll
         for (int e = 0; e < W; ++e) u[e] = ok ? xv[q][e] : 0.0f;
@@ -362,7 +363,10 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
     }
     nx += __shfl_xor(nx, 32, 64);
     ad += __shfl_xor(ad, 32, 64);
-    nrow[nb] = nx;
+    if constexpr (METRIC == SIL_COSINE)
+      nrow[nb] = RAW ? inv : 1.0f;
+    else
+      nrow[nb] = nx;
     if (o >= 0) {
       const float sc = a.ascale[o];
       if constexpr (METRIC == SIL_SQEUCLID)
@@ -482,7 +486,10 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Bloc
     const int64_t row = B.row[nb];
     const int32_t o = B.lab[nb];
     float b = lds_min[nb * 32 + r];
-    if constexpr (METRIC != SIL_COSINE) b += nrow[nb];  // ||x'||^2, or phi(x) for KL
+    if constexpr (METRIC == SIL_COSINE)
+      b = fmaf(nrow[nb], b, 1.0f);  // 1 + min_k(-z.mu_k), or the raw form's 1 + min_k(-x.mu_k) / |x|
+    else
+      b += nrow[nb];  // ||x'||^2, or phi(x) for KL
     b = fmaxf(b, 0.0f);
     if constexpr (SAVE) {
       if (a.assign) {  // K-means assignment: nearest mean and the squared distance to it
@@ -645,7 +652,7 @@ __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
   u32x4_t ahi[NB][S];
   u32x4_t alo[NB][P == 3 ? S : 1];
   float nrow[NB], arow[NB];
-  prologue<DT, 8, S, NB, METRIC, kFoldCentre<DT, P, METRIC>>(
+  prologue<DT, 8, S, NB, METRIC, kRawX<DT, P, METRIC>>(
       a, B, lane, nrow, arow, [&](int nb, int q, const float* v) __attribute__((always_inline)) {
         uint32_t hw[4], lw[4];
 #pragma unroll

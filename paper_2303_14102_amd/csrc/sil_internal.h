@@ -161,8 +161,14 @@ int main_rows_per_block(int dtype, int DPX, int products);
 // exact x, so only the split of mu'_k limits the cross term: relative 2^-16 of |x| |mu'_k|,
 // where the three-product form on x' reaches 2^-16 of |x'| |mu'_k|.  m is the fp32 centring
 // vector the row term uses, so the two agree.
+//
+// The cosine form does the same with the normalisation: the GEMM multiplies x rather than
+// z = x / |x|, and the finish scales the row's minimum by 1 / |x|, since
+// min_k (1 - z.mu_k) = 1 + (1 / |x|) min_k (-x.mu_k).  The cross term is then accurate to 2^-16
+// of |mu_k| as for BF16x3 on z.
 template <int DT, int P, int METRIC>
-inline constexpr bool kFoldCentre = DT == SIL_BF16 && P == 2 && METRIC == SIL_SQEUCLID;
+inline constexpr bool kRawX =
+    DT == SIL_BF16 && P == 2 && (METRIC == SIL_SQEUCLID || METRIC == SIL_COSINE);
 inline bool fold_centre(int dtype, int products, int metric) {
   return dtype == SIL_BF16 && products == 2 && metric == SIL_SQEUCLID;
 }

@@ -22,8 +22,10 @@ def cross_term_eps(form, products, metric, centre, D):
     if form == "f32":
         return acc
     exact_x = metric == "sqeuclid" and not centre  # bf16/fp8 storage is exact in bf16 uncentred
-    if products == 2 and form == "bf16" and metric == "sqeuclid":
-        exact_x = True  # x itself enters the GEMM (folded centring); see fold_norms
+    if products == 2 and form == "bf16" and metric in ("sqeuclid", "cosine"):
+        # x itself enters the GEMM: the folded centring (squared Euclidean, the bound then uses
+        # |x|), or the cosine form scaled by 1 / |x| after the minimum (relative to |z| = 1)
+        exact_x = True
     mu_split = 2.0 ** -16                    # hi + lo carries ~16 bits of the mean
     if products == 3:
         return 2.0 ** -16 + acc
