@@ -398,7 +398,7 @@ __device__ __forceinline__ void segreduce_body(
     for (int off = 1; off < G; off <<= 1) rowsq += shfl_xor_f64(rowsq, off);
     if constexpr (METRIC == SIL_COSINE) {
       if (valid && rowsq == 0.0) zero_norm = true;
-      const double inv = 1.0 / sqrt(rowsq);
+      const double inv = rsqrt(rowsq);  // 1 / |x| to an ulp or two
       for (int e = 0; e < 4; ++e) x[e] *= inv;
     }
     bool done = !valid;
@@ -530,7 +530,7 @@ __device__ __forceinline__ void segreduce_vec_body(
       double rowsq = sq;
       for (int off = 1; off < G; off <<= 1) rowsq += shfl_xor_f64(rowsq, off);
       if (valid && rowsq == 0.0) zero_norm = true;
-      const double inv = valid ? 1.0 / sqrt(rowsq) : 0.0;
+      const double inv = valid ? rsqrt(rowsq) : 0.0;  // 1 / |x| to an ulp or two
 #pragma unroll
       for (int e = 0; e < E; ++e) x[e] *= inv;
     }
