@@ -150,7 +150,10 @@ int silhouette_cosine_backward(const void* X, int32_t dtype, const float* col_sc
  *   labels_out  device, int32 [N]; may be the same buffer as `labels` (the labels are read only
  *               by the statistics pass, before any label is written)
  *   inertia     device, float64 [1]
- *   products    0 or 3 (bf16 / fp8 storage run the BF16x3 form; ignored for fp32)
+ *   products    0 or 3: the BF16x3 form for bf16 / fp8 storage; 2 (bf16 storage only): the
+ *               stored x itself with the centring folded into the per-cluster constant, as in
+ *               silhouette_sqeuclid.  With fp32 storage only 0 and 3 are accepted (both mean
+ *               fp32 MFMA).
  *   flags       0 or SIL_FLAG_NO_CENTRE
  * The distances are formed like the forward call's (centred, split products, fp32 accumulation),
  * so a point whose two nearest means lie within that rounding of each other may take either.

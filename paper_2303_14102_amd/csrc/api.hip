@@ -163,11 +163,13 @@ static int kmeans(const void* X, int32_t dtype, const float* col_scale, const in
                         &L);
   if (rc) return rc;
   if (!labels_out || !inertia) return SIL_E_ARG;
-  if (products != 0 && products != 3) return SIL_E_ARG;
+  if (products == 0) products = 3;
+  if (products != 3 && !(products == 2 && dtype == SIL_BF16)) return SIL_E_ARG;
   const WsPtrs w = carve(L, ws);
+  // one row block per wave (the argmin kernels), whatever the product count
   const int64_t nblocks = ceil_div(N, main_rows_per_block(dtype, L.DPX, 3));
-  Problem p{X, col_scale, labels, N, D, L.DPX, K, L.Kpad, dtype, SIL_SQEUCLID, 3, flags, nullptr,
-            inertia, nblocks};
+  Problem p{X, col_scale, labels, N, D, L.DPX, K, L.Kpad, dtype, SIL_SQEUCLID, products, flags,
+            nullptr, inertia, nblocks};
   p.labels_out = labels_out;
   p.assign = 1;
   p.min_nonempty = 1;

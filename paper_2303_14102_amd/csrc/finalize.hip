@@ -163,7 +163,7 @@ hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w,
                                                         w.mvec);
   const unsigned nb = static_cast<unsigned>(ceil_div(p.Kpad, 4));
   const bool bf = p.dtype != SIL_F32;
-  const int fold = centre && !p.assign && fold_centre(p.dtype, p.products, p.metric) ? 1 : 0;
+  const int fold = centre && fold_centre(p.dtype, p.products, p.metric) ? 1 : 0;
 #define SIL_FIN(MT, BF)                                                                        \
   k_finalize<MT, BF><<<nb, 256, 0, st>>>(w.count, w.V, w.psi, w.gmean, p.K, p.Kpad, p.D, p.DPX, \
                                          table_stride(p.DPX, p.dtype), w.btab, w.ctab, w.atab,  \

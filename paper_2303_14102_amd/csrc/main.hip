@@ -108,7 +108,7 @@ hipError_t launch_main(const Problem& p, const WsLayout& L, const WsPtrs& w, hip
     if (p.dtype == SIL_F32)
       launch_main_f32(m, p.DPX, SIL_SQEUCLID, true, grid, st);
     else
-      launch_main_assign(m, p.DPX, p.dtype, grid, st);
+      launch_main_assign(m, p.DPX, p.dtype, p.products, grid, st);
   } else if (p.dtype == SIL_F32) {
     launch_main_f32(m, p.DPX, p.metric, (p.flags & SIL_FLAG_SAVE_FOR_GRAD) != 0, grid, st);
   } else if (p.dtype == SIL_BF16) {

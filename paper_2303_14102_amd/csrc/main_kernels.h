@@ -922,8 +922,10 @@ void launch_main_f32(const MainArgs& m, int DPX, int metric, bool save, unsigned
                      hipStream_t st);
 void launch_main_bf16(const MainArgs& m, int DPX, int metric, int products, unsigned grid,
                       hipStream_t st);
-// K-means assignment with bf16 MFMA (X stored bf16 or fp8), three products, squared Euclidean
-void launch_main_assign(const MainArgs& m, int DPX, int dtype, unsigned grid, hipStream_t st);
+// K-means assignment with bf16 MFMA (X stored bf16 or fp8), squared Euclidean: three products,
+// or two with folded centring for bf16 storage; one row block per wave
+void launch_main_assign(const MainArgs& m, int DPX, int dtype, int products, unsigned grid,
+                        hipStream_t st);
 void launch_main_fp8(const MainArgs& m, int DPX, int metric, int products, unsigned grid,
                      hipStream_t st);
 

@@ -114,10 +114,12 @@ def storage(X32: torch.Tensor, form: str):
     return q, sc, wl.host_codes(q)
 
 
-def kmeans_dist_bound(form, centre, X, labels, K):
+def kmeans_dist_bound(form, centre, X, labels, K, products=3):
     """Per-point bound on |d~(x_i, mu_k) - d(x_i, mu_k)| for the K-means assignment's squared
     distance ||x'||^2 + ||mu'_k||^2 - 2 x'.mu'_k, formed like the Silhouette's b-path (cross term
-    to relative accuracy eps, fp32 rounding of the sum), with the means of the given labels."""
+    to relative accuracy eps, fp32 rounding of the sum), with the means of the given labels.
+    products = 2 with bf16 storage: the folded centring (the cross term multiplies x itself and
+    the constant carries 2 m.mu'_k)."""
     X = np.asarray(X, np.float64)
     D = X.shape[1]
     ids = np.unique(labels)
@@ -126,5 +128,10 @@ def kmeans_dist_bound(form, centre, X, labels, K):
     xp, mup = X - m, mu - m
     nx = np.linalg.norm(xp, axis=1)
     nmu = np.linalg.norm(mup, axis=1)
-    eps = cross_term_eps(form, 3, "sqeuclid", centre, D)
-    return 2 * eps * nx * nmu.max() + 4 * U32 * (nx ** 2 + (nmu ** 2).max())
+    eps = cross_term_eps(form, products, "sqeuclid", centre, D)
+    cmax = (nmu ** 2).max()
+    nxc = nx
+    if form == "bf16" and products == 2 and centre:
+        nxc = np.linalg.norm(X, axis=1)
+        cmax = cmax + 2 * np.abs(mup @ m).max()
+    return 2 * eps * nxc * nmu.max() + 4 * U32 * (nx ** 2 + nxc ** 2 + cmax)

@@ -93,7 +93,9 @@ def test_kmeans_host_checks(lib):
     # (X, dtype, col_scale, labels, N, D, K, products, flags, labels_out, inertia, ws, bytes, stream)
     assert f(fake, 0, None, fake, 10, 4, 2, 0, _lib.SIL_FLAG_SAVE_FOR_GRAD, fake, fake, ws, 1 << 30, None) == -1
     assert f(fake, 0, None, fake, 10, 4, 2, 0, _lib.SIL_FLAG_EUCLID_APPROX, fake, fake, ws, 1 << 30, None) == -1
-    assert f(fake, 1, None, fake, 10, 4, 2, 2, 0, fake, fake, ws, 1 << 30, None) == -1   # products
+    assert f(fake, 1, None, fake, 10, 4, 2, 1, 0, fake, fake, ws, 1 << 30, None) == -1   # products
+    assert f(fake, 0, None, fake, 10, 4, 2, 2, 0, fake, fake, ws, 1 << 30, None) == -1   # 2: bf16 only
+    assert f(fake, 2, fake, fake, 10, 4, 2, 2, 0, fake, fake, ws, 1 << 30, None) == -1
     assert f(fake, 0, None, fake, 10, 4, 2, 0, 0, None, fake, ws, 1 << 30, None) == -1   # labels_out
     assert f(fake, 0, None, fake, 10, 4, 2, 0, 0, fake, None, ws, 1 << 30, None) == -1   # inertia
     assert f(fake, 0, None, fake, 10, 4, 1, 0, 0, fake, fake, ws, 1 << 30, None) == -1   # K

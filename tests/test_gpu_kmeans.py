@@ -23,11 +23,11 @@ def dev():
     return torch.device("cuda:0")
 
 
-def check_step(lab_gpu, inertia_gpu, Xh, lab_in, K, form, centre=True):
+def check_step(lab_gpu, inertia_gpu, Xh, lab_in, K, form, centre=True, products=3):
     """Xh: the values as stored (dequantised), widened here to binary64."""
     Xh = np.asarray(Xh, np.float64)
     lab_ref, inertia_ref, d1, d2 = oracle.kmeans_step(Xh, lab_in, K)
-    bound = kmeans_dist_bound(form, centre, Xh, lab_in, K)
+    bound = kmeans_dist_bound(form, centre, Xh, lab_in, K, products)
     clear = (d2 - d1) > 2 * bound
     same = lab_gpu == lab_ref
     assert np.all(same[clear]), f"{(~same[clear]).sum()} points with a clear nearest mean differ"
@@ -45,30 +45,37 @@ def check_step(lab_gpu, inertia_gpu, Xh, lab_in, K, form, centre=True):
 
 
 CASES = [
-    # (N, D, K, form, singletons, relabel, sigma, seed)
-    (5_037, 40, 70, "f32", 2, 0.2, 2.0, 1),
-    (3_001, 128, 100, "bf16", 1, 0.3, 3.0, 2),
-    (2_000, 256, 40, "bf16", 0, 0.2, 1.5, 3),
-    (4_099, 16, 33, "fp8", 1, 0.2, 2.0, 4),
-    (1_500, 3, 5, "f32", 1, 0.3, 4.0, 5),
-    (1_500, 3, 5, "bf16", 0, 0.3, 4.0, 6),
-    (150_001, 64, 300, "bf16", 0, 0.1, 2.0, 7),
-    (140_333, 72, 257, "f32", 1, 0.1, 2.0, 8),
+    # (N, D, K, form, singletons, relabel, sigma, seed, products)
+    (5_037, 40, 70, "f32", 2, 0.2, 2.0, 1, 0),
+    (3_001, 128, 100, "bf16", 1, 0.3, 3.0, 2, 0),
+    (2_000, 256, 40, "bf16", 0, 0.2, 1.5, 3, 0),
+    (4_099, 16, 33, "fp8", 1, 0.2, 2.0, 4, 0),
+    (1_500, 3, 5, "f32", 1, 0.3, 4.0, 5, 0),
+    (1_500, 3, 5, "bf16", 0, 0.3, 4.0, 6, 0),
+    (150_001, 64, 300, "bf16", 0, 0.1, 2.0, 7, 0),
+    (140_333, 72, 257, "f32", 1, 0.1, 2.0, 8, 0),
+    # two products on the exact x, folded centring
+    (3_001, 128, 100, "bf16", 1, 0.3, 3.0, 9, 2),
+    (2_000, 256, 40, "bf16", 0, 0.2, 1.5, 10, 2),
+    (120_001, 128, 1000, "bf16", 1, 0.1, 2.0, 11, 2),
+    (1_500, 3, 5, "bf16", 0, 0.3, 4.0, 12, 2),
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"N{c[0]}-D{c[1]}-K{c[2]}-{c[3]}")
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"N{c[0]}-D{c[1]}-K{c[2]}-{c[3]}-P{c[8]}")
 def test_kmeans_step_parity(dev, case):
     from paper_2303_14102_amd import binding as sil
-    n, d, k, form, single, relabel, sigma, seed = case
+    n, d, k, form, single, relabel, sigma, seed, products = case
     b = wl.make_small(n, d, k, seed=seed, singletons=single, relabel=relabel, sigma=sigma)
     Kt = k + 2  # two unused ids
     Xd, sc, codes = storage(b.X.to(dev), form)
-    print(f"[kmeans] N={n} D={d} K={Kt} form={form}", flush=True)
-    lab_out, inertia = sil.kmeans_step(Xd, b.labels.to(dev), Kt, col_scale=sc, check_status=True)
+    print(f"[kmeans] N={n} D={d} K={Kt} form={form} products={products}", flush=True)
+    lab_out, inertia = sil.kmeans_step(Xd, b.labels.to(dev), Kt, products=products, col_scale=sc,
+                                       check_status=True)
     cs = None if sc is None else sc.cpu().numpy()
     Xh = dequantised(codes, cs)
-    moved, near = check_step(lab_out.cpu().numpy(), inertia.item(), Xh, b.labels.numpy(), Kt, form)
+    moved, near = check_step(lab_out.cpu().numpy(), inertia.item(), Xh, b.labels.numpy(), Kt, form,
+                             products=products or 3)
     print(f"  moved-vs-oracle {moved}, near ties {near}, inertia {inertia.item():.6e}", flush=True)
 
 
@@ -130,7 +137,9 @@ def test_kmeans_errors(dev):
     torch.cuda.synchronize()
     assert torch.all(out == -1) and torch.isnan(inertia)
     Xb = X.to(torch.bfloat16)
-    for products in (1, 2):
-        with pytest.raises(_lib.SilhouetteError) as e:
-            sil.kmeans_step(Xb, b.labels.to(dev), 5, products=products)
-        assert e.value.code == -1
+    with pytest.raises(_lib.SilhouetteError) as e:  # one product is not offered
+        sil.kmeans_step(Xb, b.labels.to(dev), 5, products=1)
+    assert e.value.code == -1
+    with pytest.raises(_lib.SilhouetteError) as e:  # two products need bf16 storage
+        sil.kmeans_step(X, b.labels.to(dev), 5, products=2)
+    assert e.value.code == -1

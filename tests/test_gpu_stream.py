@@ -30,29 +30,33 @@ def host_copy(Xd):
 
 
 CASES = [
-    # (N, D, K, metric, form, chunk_rows, approx, seed)
-    (20_011, 40, 70, "sqeuclid", "f32", 4_097, False, 1),
-    (20_011, 40, 70, "cosine", "bf16", 1_000, False, 2),
-    (9_999, 128, 100, "sqeuclid", "bf16", 9_999, False, 3),
-    (9_999, 128, 100, "sqeuclid", "bf16", 50_000, False, 4),
-    (12_345, 16, 33, "sqeuclid", "fp8", 3_000, False, 5),
-    (15_000, 64, 50, "sqeuclid", "f32", 2_048, True, 6),
-    (150_001, 64, 300, "sqeuclid", "bf16", 40_000, False, 7),
+    # (N, D, K, metric, form, chunk_rows, approx, seed, products)
+    (20_011, 40, 70, "sqeuclid", "f32", 4_097, False, 1, 0),
+    (20_011, 40, 70, "cosine", "bf16", 1_000, False, 2, 0),
+    (9_999, 128, 100, "sqeuclid", "bf16", 9_999, False, 3, 0),
+    (9_999, 128, 100, "sqeuclid", "bf16", 50_000, False, 4, 0),
+    (12_345, 16, 33, "sqeuclid", "fp8", 3_000, False, 5, 0),
+    (15_000, 64, 50, "sqeuclid", "f32", 2_048, True, 6, 0),
+    (150_001, 64, 300, "sqeuclid", "bf16", 40_000, False, 7, 0),
+    # two products on the exact x: the folded centring uses the whole data set's mean
+    (40_003, 128, 200, "sqeuclid", "bf16", 10_000, False, 8, 2),
+    (40_003, 128, 200, "cosine", "bf16", 12_000, False, 9, 2),
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"N{c[0]}-D{c[1]}-{c[3]}-{c[4]}-c{c[5]}{'-approx' if c[6] else ''}")
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"N{c[0]}-D{c[1]}-{c[3]}-{c[4]}-c{c[5]}-P{c[8]}{'-approx' if c[6] else ''}")
 def test_stream_equals_in_memory(dev, case):
     from paper_2303_14102_amd import binding as sil
-    n, d, k, metric, form, chunk, approx, seed = case
+    n, d, k, metric, form, chunk, approx, seed, products = case
     b = wl.make_small(n, d, k, seed=seed, singletons=1)
     Xd, sc, codes = storage(b.X.to(dev), form)
     lab_d = b.labels.to(dev)
     print(f"[stream] {case}", flush=True)
-    s_mem, S_mem = sil.silhouette(Xd, lab_d, k, metric, col_scale=sc, euclid_approx=approx, check_status=True)
+    s_mem, S_mem = sil.silhouette(Xd, lab_d, k, metric, products=products, col_scale=sc,
+                                  euclid_approx=approx, check_status=True)
     s_st, S_st = sil.silhouette_stream(host_copy(Xd), b.labels.contiguous().pin_memory(), k, metric,
-                                       chunk_rows=chunk, col_scale=sc, euclid_approx=approx, device=dev,
-                                       check_status=True)
+                                       chunk_rows=chunk, products=products, col_scale=sc,
+                                       euclid_approx=approx, device=dev, check_status=True)
     dmax = float((s_st - s_mem.cpu()).abs().max())
     print(f"  S_mem={S_mem.item():.12f} S_stream={S_st.item():.12f} max|ds|={dmax:.2e}", flush=True)
     assert dmax <= 2e-6
@@ -61,8 +65,8 @@ def test_stream_equals_in_memory(dev, case):
     m = "euclid_approx" if approx else metric
     cs = None if sc is None else sc.cpu().numpy()
     s_ref, S_ref, a, bb, _ = oracle.silhouette(codes, b.labels.numpy(), k, m, col_scale=cs, details=True)
-    bound = per_point_bound(form, 3 if form != "f32" else 0, m, True, dequantised(codes, cs), b.labels.numpy(),
-                            k, a, bb)
+    bound = per_point_bound(form, (products or 3) if form != "f32" else 0, m, True, dequantised(codes, cs),
+                            b.labels.numpy(), k, a, bb)
     assert np.all(np.abs(s_st.numpy().astype(np.float64) - s_ref) <= bound)
     assert abs(S_st.item() - S_ref) <= TOL_S_MEAN[form]
 
