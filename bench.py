@@ -302,6 +302,8 @@ def parse():
     ap.add_argument("--euclid-approx", action="store_true",
                     help="the approximate Euclidean form (square roots of the mean squared distances)")
     ap.add_argument("--fp32-steps", type=int, default=4)
+    ap.add_argument("--x3-steps", type=int, default=10, help="steps of the BF16x3 comparison")
+    ap.add_argument("--no-x3", action="store_true", help="skip the BF16x3 comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the fp32-form comparison")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check on sampled points")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
@@ -576,6 +578,29 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # the BF16x3 form (three products on the centred / normalised point) in the same run: the
+    # two-product form on the exact x is the default only at the same accuracy
+    s3 = None
+    if args.form == "bf16" and args.products == 2 and args.metric in ("sqeuclid", "cosine") \
+            and not args.no_x3:
+        s3 = torch.empty(spec.n, dtype=torch.float32, device=dev)
+        S3 = torch.empty((), dtype=torch.float64, device=dev)
+
+        def step3():
+            rc = fn_c(sil._ptr(X), dcode, cs_ptr, sil._ptr(labels), spec.n, spec.d, spec.k, 3, flags,
+                      sil._ptr(s3), sil._ptr(S3), sil._ptr(ws), ws.numel(), stream)
+            if rc:
+                raise _lib.SilhouetteError(rc, "step3")
+
+        log(f"timing the BF16x3 form: {args.x3_steps} steps")
+        ms3, ph3, _ = timed_steps(step3, args.x3_steps, 1, torch)
+        _lib.check(sil.status(ws), "device status BF16x3")
+        out["bf16x3_form"] = {"products": 3, "ms_per_step": ms3, "value": spec.n / (ms3 * 1e-3),
+                              "S": S3.item(), "gemm_epilogue_ms": ph3[2],
+                              "frac": useful / (ph3[2] * 1e-3) / peak,
+                              "dS_vs_two_product_form": abs(S3.item() - S_form)}
+        log(f"BF16x3 form: {ms3:.3f} ms/step, S={S3.item():.10f}")
+
     if not args.no_fp32 and args.form != "f32":
         ws32 = sil.new_workspace(spec.n, spec.d, spec.k, args.metric, torch.float32, 0, dev)
         S32 = torch.empty((), dtype=torch.float64, device=dev)
@@ -594,6 +619,8 @@ def main():
                             "gemm_frac_of_fp32_peak": useful / (ph32[2] * 1e-3) / PEAK["fp32"]}
         out["speedup_vs_fp32_form"] = ms32 / ms
         out["dS_vs_fp32_form"] = abs(S_form - S32.item())
+        if s3 is not None:
+            out["bf16x3_form"]["dS_vs_fp32_form"] = abs(out["bf16x3_form"]["S"] - S32.item())
         log(f"fp32 form: {ms32:.3f} ms/step, S={S32.item():.10f}")
         del ws32
 
@@ -617,6 +644,9 @@ def main():
                         "max_abs_ds_sampled": float(np.abs(s_gpu - s_ref).max()),
                         "S_vs_sum_of_s": abs(S_form - s_all.sum() / spec.n),
                         "oracle_stats_s": time.perf_counter() - t0}
+        if s3 is not None:
+            out["bf16x3_form"]["max_abs_ds_sampled"] = float(
+                np.abs(s3.cpu().numpy()[idx].astype(np.float64) - s_ref).max())
         log(f"check: {out['check']}")
 
     if not args.no_cpu:
