@@ -603,18 +603,23 @@ __global__ __launch_bounds__(256) void k_segreduce_vec(
 // scalar branches, and Psi is reduced across the wave only when a run is stored.  Batches of U
 // rows are double-buffered: the rows of batch t + 1 and the ids of batch t + 2 are in flight
 // while batch t is accumulated.  Runs are stored as in k_segreduce.  METRIC is the squared
-// Euclidean distance (sums of x and ||x||^2) or KL (sums of log x and of the entries).
+// Euclidean distance (sums of x and ||x||^2), KL (sums of log x and of the entries) or cosine
+// (sums of x / ||x||).  For cosine the norms of a batch's U rows are reduced across the wave
+// together: each halving step exchanges half of a lane's remaining row sums with the partner
+// lane, so U rows cost about U FP64 exchanges instead of 6 U; lane l ends with the norm of row
+// (l >> (6 - log2 U)), and each row's 1 / ||x|| is read from its lane with readlane.
 template <int DT, int CH, int METRIC = SIL_SQEUCLID>
 __device__ __forceinline__ void segreduce_row_body(
     const void* __restrict__ X, const int32_t* __restrict__ perm, const int32_t* __restrict__ offset, int32_t K, int32_t D,
     int64_t nseg, double* __restrict__ V, double* __restrict__ psi,
     double* __restrict__ segpart, int32_t* __restrict__ hdr, int64_t bid) {
   static_assert(DT == SIL_F32 || DT == SIL_BF16, "fp32 or bf16 rows");
-  static_assert(METRIC == SIL_SQEUCLID || METRIC == SIL_KL, "squared Euclidean or KL sums");
+  static_assert(METRIC == SIL_SQEUCLID || METRIC == SIL_KL || METRIC == SIL_COSINE, "metric");
   constexpr int ESZ = DT == SIL_F32 ? 4 : 2;
   constexpr int E = CH / ESZ;
   constexpr int NW = CH / 4;
-  constexpr int U = NW == 1 ? 16 : NW == 2 ? 8 : 4;
+  // rows per batch; cosine halves it (its row sums and norms would need twice the registers)
+  constexpr int U = (NW == 1 ? 16 : NW == 2 ? 8 : 4) / (METRIC == SIL_COSINE ? 2 : 1);
   constexpr int64_t RB = 64 * CH;
   typedef uint32_t chunk_t __attribute__((ext_vector_type(NW == 1 ? 2 : NW)));
   const int lane = threadIdx.x & 63;
@@ -632,7 +637,7 @@ __device__ __forceinline__ void segreduce_row_body(
 #pragma unroll
   for (int e = 0; e < E; ++e) acc[e] = 0.0;
   double accq = 0.0;
-  bool bad_value = false, domain = false;
+  bool bad_value = false, domain = false, zero_norm = false;
 
   auto flush = [&]() __attribute__((always_inline)) {
     for (int off = 1; off < 64; off <<= 1) accq += shfl_xor_f64(accq, off);
@@ -654,8 +659,7 @@ __device__ __forceinline__ void segreduce_row_body(
     accq = 0.0;
   };
 
-  auto add_row = [&](chunk_t raw) __attribute__((always_inline)) {
-    double x[E];
+  auto decode = [&](chunk_t raw, double* x) __attribute__((always_inline)) {
 #pragma unroll
     for (int w = 0; w < (NW == 1 ? 1 : NW); ++w) {
       if constexpr (DT == SIL_F32) {
@@ -665,6 +669,11 @@ __device__ __forceinline__ void segreduce_row_body(
         x[2 * w + 1] = static_cast<double>(__uint_as_float(raw[w] & 0xffff0000u));
       }
     }
+  };
+  // inv: 1 / ||x|| of the row (cosine only)
+  auto add_row = [&](chunk_t raw, double inv) __attribute__((always_inline)) {
+    double x[E];
+    decode(raw, x);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       bad_value |= !isfinite(x[e]);
@@ -672,10 +681,51 @@ __device__ __forceinline__ void segreduce_row_body(
         domain |= !(x[e] > 0.0);
         accq += x[e];
         acc[e] += x[e] > 0.0 ? static_cast<double>(logf(static_cast<float>(x[e]))) : 0.0;
+      } else if constexpr (METRIC == SIL_COSINE) {
+        acc[e] = fma(x[e], inv, acc[e]);
       } else {
         acc[e] += x[e];
         accq = fma(x[e], x[e], accq);
       }
+    }
+    if constexpr (METRIC == SIL_COSINE) zero_norm |= isinf(inv);
+  };
+  // 1 / ||x|| of the batch's U rows (cosine): the halving reduction described above
+  constexpr int LU = U == 16 ? 4 : U == 8 ? 3 : U == 4 ? 2 : 1;
+  static_assert((1 << LU) == U, "batch of 2, 4, 8 or 16 rows");
+  auto row_inv = [&](const chunk_t* raw, double* inv) __attribute__((always_inline)) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      double x[E];
+      decode(raw[u], x);
+      double sq = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) sq = fma(x[e], x[e], sq);
+      v[u] = sq;
+    }
+#pragma unroll
+    for (int st = 0; st < LU; ++st) {
+      const int m = 32 >> st;
+      const int half = U >> (st + 1);
+      const bool up = (lane & m) != 0;
+#pragma unroll
+      for (int j = 0; j < half; ++j) {
+        const double send = up ? v[j] : v[j + half];
+        const double keep = up ? v[j + half] : v[j];
+        v[j] = keep + shfl_xor_f64(send, m);
+      }
+    }
+#pragma unroll
+    for (int m = 32 >> LU; m >= 1; m >>= 1) v[0] += shfl_xor_f64(v[0], m);
+    const double mine = rsqrt(v[0]);  // row (lane >> (6 - LU)); +inf for a zero row
+    const uint64_t b = __double_as_longlong(mine);
+    const int lo = static_cast<int>(static_cast<uint32_t>(b)), hi = static_cast<int>(b >> 32);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t l = static_cast<uint32_t>(__builtin_amdgcn_readlane(lo, u << (6 - LU)));
+      const uint32_t h = static_cast<uint32_t>(__builtin_amdgcn_readlane(hi, u << (6 - LU)));
+      inv[u] = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(h) << 32) | l));
     }
   };
 
@@ -713,9 +763,16 @@ __device__ __forceinline__ void segreduce_row_body(
     chunk_t nxt[U];
     fetch_rows(ids, nxt);
     fetch_ids(p + 2 * U, ids);
+    double inv[U];
+    if constexpr (METRIC == SIL_COSINE) {
+      row_inv(raw, inv);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) inv[u] = 1.0;
+    }
     if (p + U <= re && p + U <= p1) {  // the whole batch belongs to the current run
 #pragma unroll
-      for (int u = 0; u < U; ++u) add_row(raw[u]);
+      for (int u = 0; u < U; ++u) add_row(raw[u], inv[u]);
     } else {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -727,7 +784,7 @@ __device__ __forceinline__ void segreduce_row_body(
             rs = offset[kc];
             re = offset[kc + 1];
           }
-          add_row(raw[u]);
+          add_row(raw[u], inv[u]);
         }
       }
     }
@@ -736,6 +793,7 @@ __device__ __forceinline__ void segreduce_row_body(
   }
   flush();
   if (bad_value) set_status(hdr, SIL_E_NONFINITE);
+  if (zero_norm) set_status(hdr, SIL_E_ZERO_NORM);
   if (domain) set_status(hdr, SIL_E_DOMAIN);
 }
 
@@ -787,7 +845,7 @@ __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ off
 template <int DT, int METRIC>
 static void launch_seg_row(const Problem& p, const WsLayout& L, const WsPtrs& w, int ch,
                            unsigned nblk, hipStream_t st) {
-  if constexpr (DT != SIL_FP8_E4M3 && METRIC != SIL_COSINE) {
+  if constexpr (DT != SIL_FP8_E4M3) {
     if (ch == 4)
       k_segreduce_row<DT, 4, METRIC><<<nblk, 256, 0, st>>>(p.X, w.perm, w.offset, p.K, p.D,
                                                            L.nseg, w.V, w.psi, w.segpart, w.hdr);
@@ -830,11 +888,11 @@ hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hi
   int32_t Gv, G, E;
   stats_lanes(p.D, p.dtype, &Gv, &G, &E);
   const bool vec = Gv != 0;
-  // whole-wave rows (squared Euclidean or KL, fp32 or bf16 rows of 256, 512 or 1024 bytes)
-  const int rowch = p.metric != SIL_COSINE ? row_chunk(p.D, p.dtype) : 0;
+  // whole-wave rows (fp32 or bf16 rows of 256, 512 or 1024 bytes)
+  const int rowch = row_chunk(p.D, p.dtype);
 #define SIL_SEG(DT, MT)                                                                         \
   do {                                                                                          \
-    if (rowch && MT != SIL_COSINE)                                                              \
+    if (rowch)                                                                                  \
       launch_seg_row<DT, MT>(p, L, w, rowch, nblk, st);                                         \
     else if (vec)                                                                               \
       k_segreduce_vec<DT, MT><<<nblk, 256, 0, st>>>(p.X, p.col_scale, w.perm, w.offset, p.K,    \

@@ -74,7 +74,8 @@ def test_stats_parity(dev, metric, form):
     np.testing.assert_allclose(psi.cpu().numpy(), p_ref, rtol=1e-12, atol=0)
 
 
-# squared Euclidean statistics of rows of 256, 512 or 1024 bytes (the whole-wave row reduction)
+# statistics of rows of 256, 512 or 1024 bytes (the whole-wave row reduction; for cosine the
+# batch's row norms are reduced across the wave together)
 ROW_CASES = [(128, "bf16"), (256, "bf16"), (64, "f32"), (128, "f32"), (256, "f32")]
 
 
@@ -90,31 +91,48 @@ def row_case_labels(rng):
     return lab[rng.permutation(len(lab))], K
 
 
+@pytest.mark.parametrize("metric", ["sqeuclid", "cosine"])
 @pytest.mark.parametrize("D,form", ROW_CASES, ids=lambda v: str(v))
-def test_stats_row_reduction(dev, D, form):
+def test_stats_row_reduction(dev, D, form, metric):
     from paper_2303_14102_amd import binding as sil
     rng = np.random.default_rng(D + len(form))
     lab, K = row_case_labels(rng)
     X = torch.from_numpy(rng.standard_normal((len(lab), D)).astype(np.float32) * 3 + 1)
     Xd, sc, codes = storage(X.to(dev), form)
-    print(f"[stats-row] N={len(lab)} D={D} K={K} form={form}", flush=True)
-    count, V, psi = sil.cluster_stats(Xd, torch.from_numpy(lab).to(dev), K, "sqeuclid")
-    c_ref, V_ref, p_ref = oracle.cluster_stats(codes, lab, K, "sqeuclid")
+    print(f"[stats-row] N={len(lab)} D={D} K={K} form={form} metric={metric}", flush=True)
+    count, V, psi = sil.cluster_stats(Xd, torch.from_numpy(lab).to(dev), K, metric)
+    c_ref, V_ref, p_ref = oracle.cluster_stats(codes, lab, K, metric)
     assert np.array_equal(count.cpu().numpy(), c_ref)
     scale = np.abs(V_ref).max()
     np.testing.assert_allclose(V.cpu().numpy(), V_ref, rtol=1e-12, atol=1e-12 * scale)
     np.testing.assert_allclose(psi.cpu().numpy(), p_ref, rtol=1e-12, atol=0)
 
 
-def test_stats_row_reduction_nonfinite(dev):
+@pytest.mark.parametrize("metric", ["sqeuclid", "cosine"])
+def test_stats_row_reduction_nonfinite(dev, metric):
     from paper_2303_14102_amd import _lib
     from paper_2303_14102_amd import binding as sil
     b = wl.make_small(9_000, 128, 6, seed=9)
     X = b.X.clone()
     X[4321, 77] = float("inf")
     with pytest.raises(_lib.SilhouetteError) as e:
-        sil.silhouette(X.to(dev).to(torch.bfloat16), b.labels.to(dev), 6, check_status=True)
+        sil.silhouette(X.to(dev).to(torch.bfloat16), b.labels.to(dev), 6, metric, check_status=True)
     assert e.value.code == -6
+
+
+@pytest.mark.parametrize("D,form", [(128, "bf16"), (64, "f32"), (256, "f32")])
+def test_stats_row_reduction_zero_norm(dev, D, form):
+    # a zero row in the middle of a batch, and one as the last row of the data
+    from paper_2303_14102_amd import _lib
+    from paper_2303_14102_amd import binding as sil
+    for row in (5_003, 8_999):
+        b = wl.make_small(9_000, D, 6, seed=10)
+        X = b.X.clone()
+        X[row] = 0.0
+        Xd = storage(X.to(dev), form)[0]
+        with pytest.raises(_lib.SilhouetteError) as e:
+            sil.silhouette(Xd, b.labels.to(dev), 6, "cosine", check_status=True)
+        assert e.value.code == -5
 
 
 @pytest.mark.parametrize("K", [4096, 4097, 9000])
