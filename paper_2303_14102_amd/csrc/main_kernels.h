@@ -735,29 +735,35 @@ __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
 
   if constexpr (TC == 64) {
     // Per tile: block 0's MFMAs, the previous block 1's minimum (under them), block 1's MFMAs,
-    // block 0's minimum (under them).
+    // block 0's minimum (under them).  Block 1 of the last tile is skipped when it holds only
+    // padding clusters (K mod 64 in 1 .. 32): they never win the minimum.
     f32x16_t acc0[NB], acc1[NB];
     float c1p = 0.0f;  // c_k of block 1 of the previous tile
+    const bool last_b1 = 64 * (a.ntiles - 1) + 32 < a.K;
     sweep<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, ring2, wave,
              lane, [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
       const float c0 = a.ctab[64 * t + col], c1 = a.ctab[64 * t + 32 + col];
       gemm(st, 0, acc0, prefetch);
       if (t > 0) epi(acc1, 2 * t - 1, c1p);
-      gemm(st, 1, acc1, [] {});
+      if (t + 1 < a.ntiles || last_b1) gemm(st, 1, acc1, [] {});
       epi(acc0, 2 * t, c0);
       c1p = c1;
     });
-    epi(acc1, 2 * a.ntiles - 1, c1p);
+    if (last_b1) epi(acc1, 2 * a.ntiles - 1, c1p);
   } else {
     // 32-cluster tiles (one block each): the other workgroups' waves on the SIMD fill the gap
     // of each minimum
     static_assert(TC == 32, "tiles of 32 or 64 clusters");
     f32x16_t acc0[NB];
+    // the last tile is skipped when it holds only padding clusters (its prefetch issues nothing)
+    const bool last_real = 32 * (a.ntiles - 1) < a.K;
     sweep<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, ring2, wave,
              lane, [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
-      const float c0 = a.ctab[32 * t + col];
-      gemm(st, 0, acc0, prefetch);
-      epi(acc0, t, c0);
+      if (t + 1 < a.ntiles || last_real) {
+        const float c0 = a.ctab[32 * t + col];
+        gemm(st, 0, acc0, prefetch);
+        epi(acc0, t, c0);
+      }
     });
   }
 
@@ -874,18 +880,20 @@ __device__ __forceinline__ void main_f32_body(const MainArgs& a, int64_t wb, con
                      32 * blk, lab_w + nb * 32, h, cv);
   };
 
+  // block 1 of the last tile is skipped when it holds only padding clusters (as in the bf16 body)
   f32x16_t acc0[NB], acc1[NB];
   float c1p = 0.0f;  // c_k of block 1 of the previous tile
+  const bool last_b1 = 64 * (a.ntiles - 1) + 32 < a.K;
   sweep<R>(static_cast<const char*>(a.btab), a.piece * 4, a.ntiles, ring0, ring1, ring2, wave, lane,
            [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
     const float c0 = a.ctab[64 * t + col], c1 = a.ctab[64 * t + 32 + col];
     gemm(st, 0, acc0, prefetch);
     if (t > 0) epi(acc1, 2 * t - 1, c1p);
-    gemm(st, 1, acc1, [] {});
+    if (t + 1 < a.ntiles || last_b1) gemm(st, 1, acc1, [] {});
     epi(acc0, 2 * t, c0);
     c1p = c1;
   });
-  epi(acc1, 2 * a.ntiles - 1, c1p);
+  if (last_b1) epi(acc1, 2 * a.ntiles - 1, c1p);
 
   __syncthreads();
   finish<NB, METRIC, SAVE>(a, wb, B, wave, lane, mn, arg, nrow, arow, lds_min + wave * NB * 32,
