@@ -192,6 +192,88 @@ def bench_mahalanobis(args, spec, X, col_scale, labels, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_backward(args, spec, X32, labels, dev):
+    """S and dS/dX on fp32 embeddings (the differentiation workload): a forward call that keeps
+    a_i, b_i and the neighbouring cluster, then the adjoint kernels.  The step is forward plus
+    backward; the adjoint alone is timed with events on the library's stream and set against
+    its HBM roofline (read X twice, write dX, read the saves and labels)."""
+    import numpy as np
+    import torch
+
+    from paper_2303_14102_amd import _lib
+    from paper_2303_14102_amd import binding as sil
+    lib = _lib.load()
+    metric = args.metric
+    flags = _lib.SIL_FLAG_SAVE_FOR_GRAD
+    ws = sil.new_workspace(spec.n, spec.d, spec.k, metric, torch.float32, flags, dev)
+    S = torch.empty((), dtype=torch.float64, device=dev)
+    gS = torch.ones((), dtype=torch.float64, device=dev)
+    dX = torch.empty_like(X32)
+    stream = sil._stream(dev)
+    fwd = lib.silhouette_sqeuclid if metric == "sqeuclid" else lib.silhouette_cosine
+    bwd = lib.silhouette_sqeuclid_backward if metric == "sqeuclid" else lib.silhouette_cosine_backward
+
+    def forward():
+        rc = fwd(sil._ptr(X32), 0, None, sil._ptr(labels), spec.n, spec.d, spec.k, 0, flags, None,
+                 sil._ptr(S), sil._ptr(ws), ws.numel(), stream)
+        if rc:
+            raise _lib.SilhouetteError(rc, "forward")
+
+    def backward():
+        rc = bwd(sil._ptr(X32), 0, None, sil._ptr(labels), spec.n, spec.d, spec.k, flags, sil._ptr(gS),
+                 sil._ptr(dX), sil._ptr(ws), ws.numel(), stream)
+        if rc:
+            raise _lib.SilhouetteError(rc, "backward")
+
+    def step():
+        forward()
+        backward()
+
+    log(f"timing forward + backward ({metric}): warmup {args.warmup}, steps {args.steps}")
+    ms, phases, _ = timed_steps(step, args.steps, args.warmup, torch)
+    _lib.check(sil.status(ws), "device status")
+    # the adjoint alone, on the same saves
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nb = max(1, args.steps)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(nb):
+        backward()
+    ev1.record()
+    torch.cuda.synchronize()
+    bwd_ms = ev0.elapsed_time(ev1) / nb
+    alg = spec.n * (12 * spec.d + 16)
+    res = {
+        "metric": f"Silhouette and dS/dX points/s at N={spec.n},D={spec.d},K={spec.k} (fp32, labels fixed)",
+        "value": spec.n / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": spec.name, "n": spec.n, "d": spec.d, "k": spec.k, "metric": metric,
+                   "storage": "f32", "step": "forward (saves) + backward"},
+        "phases_ms": {"stats": phases[0], "finalize": phases[1], "gemm_epilogue": phases[2],
+                      "reduce": phases[3], "backward": bwd_ms},
+        "S": S.item(),
+        "roofline": {"bound": "hbm", "achieved": alg / (bwd_ms * 1e-3) / 1e9, "peak": PEAK["hbm"] / 1e9,
+                     "unit": "GB/s", "frac": alg / (bwd_ms * 1e-3) / PEAK["hbm"], "traffic": None,
+                     "kernel": "kb_accum + kb_reduce + kb_dx",
+                     "algorithmic_bytes": alg,
+                     "note": "per point: X read twice, dX written (12 D bytes), saves and label (16 B)"},
+        "dX_norm": float(dX.double().norm()),
+    }
+    if not args.no_cpu:
+        import oracle
+        n = min(args.cpu_sample, 200_000)
+        Xs = X32[:n].cpu().numpy()
+        ls = labels[:n].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.gradient(Xs, ls, spec.k, metric)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": n / dt, "unit": "points/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"first {n} rows of {spec.name}: FP64 oracle forward and gradient, {dt:.1f} s"}
+    print(json.dumps(res), flush=True)
+
+
 def bench_stream(args, spec, X, col_scale, labels, dev):
     """Out-of-core form: X and labels moved to pinned host memory (the device copy is freed), then
     every step streams them through the device twice in chunks.  The rate includes the PCIe
@@ -297,6 +379,8 @@ def parse():
     ap.add_argument("--chunk-rows", type=int, default=4_000_000)
     ap.add_argument("--mahalanobis", action="store_true",
                     help="the Silhouette under a fixed Mahalanobis distance (M = L^T L, random L)")
+    ap.add_argument("--backward", action="store_true",
+                    help="forward + adjoint on the differentiation workload (blobs-1m-d256-k64, fp32)")
     ap.add_argument("--kmeans", action="store_true",
                     help="time one K-means (Lloyd) step on the workload instead of the Silhouette")
     ap.add_argument("--euclid-approx", action="store_true",
@@ -458,6 +542,12 @@ def main():
     if args.workload == "ksweep":
         return bench_ksweep(args)
     dev = torch.device("cuda:0")
+    if args.backward:
+        if args.workload == "blobs-50m-d128-k1000":
+            args.workload = "blobs-1m-d256-k64"
+        args.form = "f32"
+        if args.metric not in ("sqeuclid", "cosine"):
+            sys.exit("--backward: squared Euclidean or cosine")
     spec = wl.WORKLOADS[args.workload]
     if args.n:
         spec = wl.scaled(spec, args.n)
@@ -483,6 +573,8 @@ def main():
     torch.cuda.synchronize()
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
+    if args.backward:
+        return bench_backward(args, spec, X32, labels, dev)
     if args.kmeans:
         return bench_kmeans(args, spec, X, col_scale, labels, dev)
     if args.mahalanobis:
