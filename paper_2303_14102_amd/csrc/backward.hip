@@ -231,8 +231,10 @@ int bwd_accum_workgroups(int64_t N) {
   return static_cast<int>(w < 512 ? w : 512);
 }
 
+// The per-workgroup partials of A_k, B_k in LDS: up to the 160 KB of one CU (gfx950), so that
+// K (D + 1) = 64 x 257 FP64 values (the 256-dimension, 64-cluster case) stay off global atomics.
 bool bwd_fits_lds(int32_t K, int32_t D) {
-  return static_cast<int64_t>(K) * (D + 1) * 8 <= 128 * 1024;
+  return static_cast<int64_t>(K) * (D + 1) * 8 <= 160 * 1024;
 }
 
 hipError_t launch_backward(const Problem& p, const WsLayout& L, const WsPtrs& w, const double* gS,
