@@ -615,7 +615,8 @@ def main():
     out = {
         "metric": ("Approximate-Euclidean " if args.euclid_approx else "")
         + ("Generalized-KL " if args.metric == "kl" else "")
-        + "Silhouette points/s at D=128,K=1000; bf16-MFMA vs fp32 form at |dS|<1e-4",
+        + (f"Silhouette points/s at D={spec.d},K={spec.k}; "
+           + ("bf16-MFMA vs fp32 form at |dS|<1e-4" if args.form != "f32" else "fp32 form")),
         "value": spec.n / (ms * 1e-3),
         "unit": "points/s",
         "n_gpus": 1,
