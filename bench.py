@@ -262,7 +262,7 @@ def bench_backward(args, spec, X32, labels, dev):
     }
     if not args.no_cpu:
         import oracle
-        n = min(args.cpu_sample, 200_000)
+        n = min(args.cpu_sample, spec.n)
         Xs = X32[:n].cpu().numpy()
         ls = labels[:n].cpu().numpy()
         t0 = time.perf_counter()
