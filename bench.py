@@ -372,8 +372,8 @@ def parse():
     ap.add_argument("--metric", default="sqeuclid", choices=["sqeuclid", "cosine", "kl"])
     ap.add_argument("--form", default="bf16", choices=["bf16", "fp8", "f32"])
     ap.add_argument("--products", type=int, default=0,
-                    help="bf16/fp8 split products (0: 2 for bf16 storage, where x enters the GEMM exact; "
-                         "3 for fp8)")
+                    help="bf16/fp8 split products (0: 2, where x - fp8: its codes - enters the GEMM "
+                         "exact)")
     ap.add_argument("--stream", action="store_true",
                     help="out-of-core: X and labels in pinned host memory, streamed in chunks")
     ap.add_argument("--chunk-rows", type=int, default=4_000_000)
@@ -528,7 +528,7 @@ def bench_ksweep(args):
 def main():
     args = parse()
     if args.products == 0:
-        args.products = 2 if args.form == "bf16" else 3
+        args.products = 2
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU form is a design note, not a measured path)", file=sys.stderr)
@@ -634,9 +634,9 @@ def main():
                    "centred": args.metric == "sqeuclid",
                    **({"centring": "folded into c_k (x enters the GEMM exact)",
                        "mean_offset_ratio": offset_ratio(X32)}
-                      if args.metric == "sqeuclid" and args.form == "bf16" and args.products == 2 else {}),
+                      if args.metric == "sqeuclid" and args.form in ("bf16", "fp8") and args.products == 2 else {}),
                    **({"normalisation": "1/|x| applied after the minimum (x enters the GEMM exact)"}
-                      if args.metric == "cosine" and args.form == "bf16" and args.products == 2 else {}),
+                      if args.metric == "cosine" and args.form in ("bf16", "fp8") and args.products == 2 else {}),
                    **({"euclid_approx": True} if args.euclid_approx else {}),
                    **({"data_transform": "exp(x/4) of the blob coordinates"} if args.metric == "kl" else {})},
         "phases_ms": {"stats": phases[0], "finalize": phases[1], "gemm_epilogue": phases[2],
@@ -674,7 +674,7 @@ def main():
     # the BF16x3 form (three products on the centred / normalised point) in the same run: the
     # two-product form on the exact x is the default only at the same accuracy
     s3 = None
-    if args.form == "bf16" and args.products == 2 and args.metric in ("sqeuclid", "cosine") \
+    if args.form in ("bf16", "fp8") and args.products == 2 and args.metric in ("sqeuclid", "cosine") \
             and not args.no_x3:
         s3 = torch.empty(spec.n, dtype=torch.float32, device=dev)
         S3 = torch.empty((), dtype=torch.float64, device=dev)

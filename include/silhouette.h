@@ -90,7 +90,8 @@ size_t silhouette_workspace_bytes(int64_t N, int32_t D, int32_t K, int32_t metri
  *   products   number of bf16 MFMA products for the point-to-cluster-mean cross term when X is
  *              bf16 or fp8: 1 (hi x hi), 2 (adds x x mean_lo), 3 (adds x_lo x mean_hi); 0 picks
  *              the default (3).  Ignored for SIL_F32, which uses fp32 MFMA.  With bf16 storage,
- *              2 multiplies the stored x itself (exact in bf16): the centring moves into the
+ *              2 multiplies the stored x itself (exact in bf16; with fp8 storage its e4m3 codes,
+ *              the column scales going into the cluster-side table): the centring moves into the
  *              per-cluster constant (cosine: 1/|x| scales the row's minimum), and the cross term
  *              is accurate to 2^-16 of |x| |mean| rather than of |x - m| |mean|, m the global
  *              mean.  That matches 3 while |m| is small against the data's spread, at two

@@ -69,8 +69,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 //   bf16:  hi = [bf16(alpha mu'_k) (D), 0 ...], lo = [bf16(alpha mu'_k - hi) (D), 0 ...]
 // alpha = -2 (squared Euclidean) or -1 (cosine, KL) is a power of two, so alpha mu' splits exactly
 // like mu'.  The constant c_k goes to ctab (fp32), which the fused kernels add to the cross term
-// before the minimum; with fold set (the folded centring of the two-product bf16 kernels) it
-// also carries 2 m.mu'_k, m being the fp32 centring vector mvec.  Empty and padding clusters get
+// before the minimum; with fold set (the folded centring of the two-product kernels) it also
+// carries 2 m.mu'_k, m being the fp32 centring vector mvec.  With tscale set (fp8 codes in the
+// GEMM) entry l of the table row is multiplied by the column scale tscale[l].  Empty and padding clusters get
 // c_k = kEmptyC (large and finite) and a zero mean.
 constexpr double kEmptyC = 1.0e30;
 
@@ -80,7 +81,7 @@ __device__ __forceinline__ void finalize_body(
     const double* __restrict__ psi, const double* __restrict__ gmean, int32_t K, int32_t Kpad,
     int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ ctab,
     float* __restrict__ atab, float* __restrict__ avec, float* __restrict__ ascale, int with_var,
-    const float* __restrict__ mvec, int fold, int64_t bid) {
+    const float* __restrict__ mvec, int fold, const float* __restrict__ tscale, int64_t bid) {
   constexpr double ALPHA = METRIC == SIL_SQEUCLID ? -2.0 : -1.0;
   const int lane = threadIdx.x & 63;
   const int32_t k = static_cast<int32_t>(bid) * 4 + (threadIdx.x >> 6);
@@ -105,7 +106,8 @@ __device__ __forceinline__ void finalize_body(
     mu2 += mu * mu;
     muc2 += muc * muc;
     if (fold && l < D) mdot = fma(static_cast<double>(mvec[l]), muc, mdot);
-    const double g = ALPHA * muc;  // exact scaling
+    double g = ALPHA * muc;  // exact scaling
+    if (tscale && l < D) g *= static_cast<double>(tscale[l]);
     if (BF16TAB) {
       const uint16_t hi = f32_to_bf16_rne(static_cast<float>(g));
       bthi[brow + l] = hi;
@@ -152,9 +154,9 @@ __global__ __launch_bounds__(256) void k_finalize(
     const double* __restrict__ psi, const double* __restrict__ gmean, int32_t K, int32_t Kpad,
     int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ ctab,
     float* __restrict__ atab, float* __restrict__ avec, float* __restrict__ ascale, int with_var,
-    const float* __restrict__ mvec, int fold) {
+    const float* __restrict__ mvec, int fold, const float* __restrict__ tscale) {
   finalize_body<METRIC, BF16TAB>(count, V, psi, gmean, K, Kpad, D, DPX, RS, btab, ctab, atab,
-                                 avec, ascale, with_var, mvec, fold, blockIdx.x);
+                                 avec, ascale, with_var, mvec, fold, tscale, blockIdx.x);
 }
 
 hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
@@ -164,10 +166,14 @@ hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w,
   const unsigned nb = static_cast<unsigned>(ceil_div(p.Kpad, 4));
   const bool bf = p.dtype != SIL_F32;
   const int fold = centre && fold_centre(p.dtype, p.products, p.metric) ? 1 : 0;
+  // fp8 codes in the GEMM (the two-product kernels and not the argmin ones): scaled tables
+  const float* tscale =
+      p.dtype == SIL_FP8_E4M3 && !p.assign && raw_x(p.dtype, p.products, p.metric) ? p.col_scale
+                                                                                 : nullptr;
 #define SIL_FIN(MT, BF)                                                                        \
   k_finalize<MT, BF><<<nb, 256, 0, st>>>(w.count, w.V, w.psi, w.gmean, p.K, p.Kpad, p.D, p.DPX, \
                                          table_stride(p.DPX, p.dtype), w.btab, w.ctab, w.atab,  \
-                                         w.avec, w.ascale, p.assign ? 0 : 1, w.mvec, fold)
+                                         w.avec, w.ascale, p.assign ? 0 : 1, w.mvec, fold, tscale)
   if (p.metric == SIL_SQEUCLID) {
     if (bf) SIL_FIN(SIL_SQEUCLID, true);
     else SIL_FIN(SIL_SQEUCLID, false);
@@ -210,11 +216,11 @@ __global__ __launch_bounds__(256) void kb_fin(BatchDev b) {
   if (q.metric == SIL_SQEUCLID)
     finalize_body<SIL_SQEUCLID, false>(q.count, q.V, q.psi, q.gmean, q.K, q.Kpad, q.D, q.DPX, RS,
                                        q.btab, q.ctab, q.atab, q.avec, q.ascale, 1, nullptr, 0,
-                                       it);
+                                       nullptr, it);
   else
     finalize_body<SIL_COSINE, false>(q.count, q.V, q.psi, q.gmean, q.K, q.Kpad, q.D, q.DPX, RS,
                                      q.btab, q.ctab, q.atab, q.avec, q.ascale, 1, nullptr, 0,
-                                     it);
+                                     nullptr, it);
 }
 
 hipError_t launch_finalize_batched(const BatchLaunch& b, hipStream_t st) {

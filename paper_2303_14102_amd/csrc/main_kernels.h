@@ -91,8 +91,8 @@ __device__ __forceinline__ float e4m3_f32(uint32_t q) {
 }
 
 // W consecutive stored elements of row `row` starting at column c0, decoded to fp32; zero
-// outside [0, D) and for invalid rows.
-template <int DT, int W>
+// outside [0, D) and for invalid rows.  SCALE = false leaves fp8 codes unscaled.
+template <int DT, int W, bool SCALE = true>
 __device__ __forceinline__ void load_chunk(const void* __restrict__ X,
                                            const float* __restrict__ col_scale, int64_t row,
                                            bool row_ok, int32_t D, int32_t c0, float* out) {
@@ -141,8 +141,10 @@ __device__ __forceinline__ void load_chunk(const void* __restrict__ X,
 #pragma unroll
       for (int e = 0; e < W; ++e) out[e] = (c0 + e < D) ? e4m3_f32(p[e]) : 0.0f;
     }
+    if constexpr (SCALE) {
 #pragma unroll
-    for (int e = 0; e < W; ++e) out[e] *= (c0 + e < D) ? col_scale[c0 + e] : 0.0f;
+      for (int e = 0; e < W; ++e) out[e] *= (c0 + e < D) ? col_scale[c0 + e] : 0.0f;
+    }
   }
 }
 
@@ -224,7 +226,8 @@ __device__ __forceinline__ void make_blocks(const MainArgs& a, const RowPre<NB>&
 // before any is used (addresses clamped in range, values masked afterwards).
 // RAW: emit hands over x itself rather than x' = x - m (squared Euclidean: the tables fold the
 // centring into c_k) or z = x / |x| (cosine: the finish scales by 1 / |x|); the row and a-path
-// terms still use x' or z.  For cosine, nrow holds the finish's scale: 1 / |x| (RAW) or 1.
+// terms still use x' or z.  For fp8 storage it hands over the e4m3 codes, unscaled (the tables
+// carry the column scales).  For cosine, nrow holds the finish's scale: 1 / |x| (RAW) or 1.
 
 template <int DT>
 struct RawChunk;
@@ -247,7 +250,7 @@ __device__ __forceinline__ typename RawChunk<DT>::T load_raw(const void* __restr
     return *reinterpret_cast<const u32x2_t*>(static_cast<const uint8_t*>(X) + base);
 }
 
-template <int DT, int W>
+template <int DT, int W, bool SCALE = true>
 __device__ __forceinline__ void decode_raw(typename RawChunk<DT>::T raw,
                                            const float* __restrict__ col_scale, int32_t c0,
                                            bool valid, float* out) {
@@ -263,8 +266,12 @@ __device__ __forceinline__ void decode_raw(typename RawChunk<DT>::T raw,
   } else {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      out[e] = e4m3_f32((raw[0] >> (8 * e)) & 0xffu) * col_scale[c0 + e];
-      out[4 + e] = e4m3_f32((raw[1] >> (8 * e)) & 0xffu) * col_scale[c0 + 4 + e];
+      out[e] = e4m3_f32((raw[0] >> (8 * e)) & 0xffu);
+      out[4 + e] = e4m3_f32((raw[1] >> (8 * e)) & 0xffu);
+    }
+    if constexpr (SCALE) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) out[e] *= col_scale[c0 + e];
     }
   }
 #pragma unroll
@@ -288,8 +295,14 @@ template <int DT, int W, int NQ, int NB, int METRIC, bool RAW, typename Emit>
 __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B, int lane,
                                          float (&nrow)[NB], float (&arow)[NB], Emit&& emit) {
   constexpr int DPX = 2 * NQ * W;
+  constexpr bool CODES = RAW && DT == SIL_FP8_E4M3;  // xv holds unscaled fp8 codes
   const int h = lane >> 5;
   const bool vec = (a.D % W) == 0;  // wave-uniform
+  // the column scales of chunk c0 (fp8 codes), zero past D
+  auto scales = [&](int c0, float* sc) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < W; ++e) sc[e] = c0 + e < a.D ? a.col_scale[c0 + e] : 0.0f;
+  };
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const bool ok = B.ok[nb];
@@ -307,19 +320,26 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int c0 = (2 * q + h) * W;
-        decode_raw<DT, W>(raw[q], a.col_scale, c0 < a.D ? c0 : 0, ok && c0 < a.D, xv[q]);
+        decode_raw<DT, W, !CODES>(raw[q], a.col_scale, c0 < a.D ? c0 : 0, ok && c0 < a.D, xv[q]);
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) load_chunk<DT, W>(a.X, a.col_scale, row, ok, a.D, (2 * q + h) * W, xv[q]);
+      for (int q = 0; q < NQ; ++q)
+        load_chunk<DT, W, !CODES>(a.X, a.col_scale, row, ok, a.D, (2 * q + h) * W, xv[q]);
     }
     float inv = 1.0f;
     if constexpr (METRIC == SIL_COSINE) {
       float n2 = 0.0f;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
+      for (int q = 0; q < NQ; ++q) {
+        float sc[W];
+        if constexpr (CODES) scales((2 * q + h) * W, sc);
 #pragma unroll
-        for (int e = 0; e < W; ++e) n2 = fmaf(xv[q][e], xv[q][e], n2);
+        for (int e = 0; e < W; ++e) {
+          const float x = CODES ? xv[q][e] * sc[e] : xv[q][e];
+          n2 = fmaf(x, x, n2);
+        }
+      }
       n2 += __shfl_xor(n2, 32, 64);
       inv = n2 > 0.0f ? 1.0f / sqrtf(n2) : 0.0f;
     }
@@ -332,20 +352,30 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
       float mv[W], at[W];
       if constexpr (METRIC == SIL_SQEUCLID) load_f32w<W>(a.mvec + c0, mv);
       load_f32w<W>(a.atab + orow + c0, at);
+      float x[W];  // the stored values (fp8 codes times their column scales)
+      if constexpr (CODES) {
+        float sc[W];
+        scales(c0, sc);
+#pragma unroll
+        for (int e = 0; e < W; ++e) x[e] = xv[q][e] * sc[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < W; ++e) x[e] = xv[q][e];
+      }
       float v[W];
 #pragma unroll
       for (int e = 0; e < W; ++e) {
         if constexpr (METRIC == SIL_KL) {
           // phi(x) = sum x log x - x for the row term, x . (mean log y) of the own cluster for
           // the a-path; x is not centred (the divergence is not translation invariant)
-          v[e] = ok ? xv[q][e] : 0.0f;
+          v[e] = ok ? x[e] : 0.0f;
           nx += v[e] > 0.0f ? v[e] * logf(v[e]) - v[e] : 0.0f;
           ad = fmaf(v[e], at[e], ad);
         } else {
           if constexpr (METRIC == SIL_COSINE)
-            v[e] = xv[q][e] * inv;
+            v[e] = x[e] * inv;
           else
-            v[e] = ok ? xv[q][e] - mv[e] : 0.0f;  // mvec is zero when not centring
+            v[e] = ok ? x[e] - mv[e] : 0.0f;  // mvec is zero when not centring
           nx = fmaf(v[e], v[e], nx);
           const float dd = v[e] - at[e];
           ad = fmaf(dd, dd, ad);

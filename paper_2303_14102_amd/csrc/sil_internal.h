@@ -166,11 +166,18 @@ int main_rows_per_block(int dtype, int DPX, int products);
 // z = x / |x|, and the finish scales the row's minimum by 1 / |x|, since
 // min_k (1 - z.mu_k) = 1 + (1 / |x|) min_k (-x.mu_k).  The cross term is then accurate to 2^-16
 // of |mu_k| as for BF16x3 on z.
+//
+// With fp8 storage the GEMM multiplies the e4m3 codes themselves (exact in bf16 whatever the
+// column scales) and the tables carry the scales: x.mu = sum_l code_l (s_l mu_l).
 template <int DT, int P, int METRIC>
-inline constexpr bool kRawX =
-    DT == SIL_BF16 && P == 2 && (METRIC == SIL_SQEUCLID || METRIC == SIL_COSINE);
+inline constexpr bool kRawX = (DT == SIL_BF16 || DT == SIL_FP8_E4M3) && P == 2 &&
+                              (METRIC == SIL_SQEUCLID || METRIC == SIL_COSINE);
+inline bool raw_x(int dtype, int products, int metric) {
+  return (dtype == SIL_BF16 || dtype == SIL_FP8_E4M3) && products == 2 &&
+         (metric == SIL_SQEUCLID || metric == SIL_COSINE);
+}
 inline bool fold_centre(int dtype, int products, int metric) {
-  return dtype == SIL_BF16 && products == 2 && metric == SIL_SQEUCLID;
+  return raw_x(dtype, products, metric) && metric == SIL_SQEUCLID;
 }
 
 // Split products the bf16 kernel runs for a requested count.  When X is stored bf16 and x' = x

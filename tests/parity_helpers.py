@@ -22,9 +22,10 @@ def cross_term_eps(form, products, metric, centre, D):
     if form == "f32":
         return acc
     exact_x = metric == "sqeuclid" and not centre  # bf16/fp8 storage is exact in bf16 uncentred
-    if products == 2 and form == "bf16" and metric in ("sqeuclid", "cosine"):
-        # x itself enters the GEMM: the folded centring (squared Euclidean, the bound then uses
-        # |x|), or the cosine form scaled by 1 / |x| after the minimum (relative to |z| = 1)
+    if products == 2 and form in ("bf16", "fp8") and metric in ("sqeuclid", "cosine"):
+        # x itself enters the GEMM (fp8: its codes, the tables carrying the column scales): the
+        # folded centring (squared Euclidean, the bound then uses |x|), or the cosine form scaled
+        # by 1 / |x| after the minimum (relative to |z| = 1)
         exact_x = True
     mu_split = 2.0 ** -16                    # hi + lo carries ~16 bits of the mean
     if products == 3:
@@ -59,7 +60,7 @@ def bound_from_stats(form, products, metric, centre, rows, stats, a, b, root=Fal
     nx = np.linalg.norm(xp, axis=1)
     eps = cross_term_eps(form, products, metric, centre, D)
     nxc = nx  # norm of the GEMM operand
-    if metric == "sqeuclid" and centre and form == "bf16" and products == 2:
+    if metric == "sqeuclid" and centre and form in ("bf16", "fp8") and products == 2:
         # folded centring: the GEMM multiplies x itself, and c_k carries 2 m.mu'_k
         nxc = np.linalg.norm(rows, axis=1)
         cmax = cmax + 2 * np.abs(mup @ m).max()

@@ -78,7 +78,7 @@ def big(dev):
 
 
 BIG_CASES = [("sqeuclid", "bf16", 2), ("sqeuclid", "bf16", 3), ("cosine", "bf16", 2), ("cosine", "bf16", 3),
-             ("sqeuclid", "fp8", 3), ("sqeuclid", "f32", 0)]
+             ("sqeuclid", "fp8", 3), ("sqeuclid", "fp8", 2), ("sqeuclid", "f32", 0)]
 
 
 @pytest.mark.parametrize("metric,form,products", BIG_CASES, ids=lambda v: str(v))

@@ -183,16 +183,16 @@ CASES = [
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"N{c[0]}-D{c[1]}-K{c[2]}")
 @pytest.mark.parametrize("metric", ["sqeuclid", "cosine"])
 @pytest.mark.parametrize("form,products", [("f32", 0), ("bf16", 3), ("bf16", 2), ("bf16", 1),
-                                           ("fp8", 3)])
+                                           ("fp8", 3), ("fp8", 2)])
 def test_forward_parity(dev, case, metric, form, products):
     N, D, K, single, seed = case
     b = wl.make_small(N, D, K, seed=seed, singletons=single, sigma=1.5)
     Kt = K + 2  # two unused ids
     s, S, s_ref, S_ref = run_case(dev, b.X, b.labels, Kt, metric, form, products)
-    if form == "bf16" and products == 2:
-        # x enters the GEMM exact (folded centring; cosine scaled after the minimum): the
-        # three-product form's accuracy on data near the origin
-        assert abs(S - S_ref) <= TOL_S_MEAN["bf16"]
+    if form in ("bf16", "fp8") and products == 2:
+        # x (fp8: its codes) enters the GEMM exact (folded centring; cosine scaled after the
+        # minimum): the three-product form's accuracy on data near the origin
+        assert abs(S - S_ref) <= TOL_S_MEAN[form]
     # singletons score exactly 0
     sizes = np.bincount(b.labels.numpy(), minlength=Kt)
     assert np.all(s[sizes[b.labels.numpy()] == 1] == 0.0)
@@ -211,6 +211,9 @@ LARGER_CASES = [
     (120_007, 100, 300, "cosine", "bf16", 1, 1, 67),   # two row blocks per wave at depth 128
     (130_001, 128, 1000, "cosine", "bf16", 2, 1, 69),
     (99_999, 120, 129, "sqeuclid", "bf16", 2, 0, 68),
+    (131_200, 128, 400, "sqeuclid", "fp8", 2, 2, 70),   # fp8 codes in the GEMM, scaled tables
+    (120_001, 72, 300, "cosine", "fp8", 2, 1, 71),
+    (60_001, 256, 100, "sqeuclid", "fp8", 2, 0, 72),
 ]
 
 
@@ -284,6 +287,7 @@ def test_uncentred_and_offset_data(dev):
         assert abs(S - S_ref) <= TOL_S_MEAN[form]
     # folded centring (two products): the cross term's error grows with |x|, within the bound
     run_case(dev, X, b.labels, 20, "sqeuclid", "bf16", 2, centre=True)
+    run_case(dev, X, b.labels, 20, "sqeuclid", "fp8", 2, centre=True)
     s, S, s_ref, S_ref = run_case(dev, b.X, b.labels, 20, "sqeuclid", "f32", 0, centre=False)
     assert abs(S - S_ref) <= TOL_S_MEAN["f32"]
 

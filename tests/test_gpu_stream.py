@@ -41,6 +41,7 @@ CASES = [
     # two products on the exact x: the folded centring uses the whole data set's mean
     (40_003, 128, 200, "sqeuclid", "bf16", 10_000, False, 8, 2),
     (40_003, 128, 200, "cosine", "bf16", 12_000, False, 9, 2),
+    (30_011, 128, 150, "sqeuclid", "fp8", 8_000, False, 10, 2),
 ]
 
 
