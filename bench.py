@@ -355,10 +355,10 @@ def offset_ratio(X32):
 
 
 def stats_kernel(args, spec):
-    """Name of the statistics pass's reduction kernel for this run: whole-wave rows for squared
-    Euclidean or KL fp32 / bf16 rows of 256, 512 or 1024 bytes, 16-byte chunks otherwise."""
+    """Name of the statistics pass's reduction kernel for this run: whole-wave rows for fp32 / bf16
+    rows of 256, 512 or 1024 bytes and fp8 rows of 128 or 256 bytes, 16-byte chunks otherwise."""
     rb = spec.d * {"f32": 4, "bf16": 2, "fp8": 1}[args.form]
-    row = args.metric in ("sqeuclid", "kl") and args.form != "fp8" and rb in (256, 512, 1024)
+    row = rb in (256, 512, 1024) if args.form != "fp8" else spec.d in (128, 256)
     return "k_segreduce_row" if row else "k_segreduce_vec"
 
 

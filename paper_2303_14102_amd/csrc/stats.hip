@@ -610,16 +610,19 @@ __global__ __launch_bounds__(256) void k_segreduce_vec(
 // (l >> (6 - log2 U)), and each row's 1 / ||x|| is read from its lane with readlane.
 template <int DT, int CH, int METRIC = SIL_SQEUCLID>
 __device__ __forceinline__ void segreduce_row_body(
-    const void* __restrict__ X, const int32_t* __restrict__ perm, const int32_t* __restrict__ offset, int32_t K, int32_t D,
+    const void* __restrict__ X, const float* __restrict__ col_scale,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ offset, int32_t K, int32_t D,
     int64_t nseg, double* __restrict__ V, double* __restrict__ psi,
     double* __restrict__ segpart, int32_t* __restrict__ hdr, int64_t bid) {
-  static_assert(DT == SIL_F32 || DT == SIL_BF16, "fp32 or bf16 rows");
+  static_assert(DT == SIL_F32 || DT == SIL_BF16 || (DT == SIL_FP8_E4M3 && CH <= 4), "row form");
   static_assert(METRIC == SIL_SQEUCLID || METRIC == SIL_KL || METRIC == SIL_COSINE, "metric");
-  constexpr int ESZ = DT == SIL_F32 ? 4 : 2;
+  constexpr int ESZ = DT == SIL_F32 ? 4 : DT == SIL_BF16 ? 2 : 1;
   constexpr int E = CH / ESZ;
-  constexpr int NW = CH / 4;
-  // rows per batch; cosine halves it (its row sums and norms would need twice the registers)
-  constexpr int U = (NW == 1 ? 16 : NW == 2 ? 8 : 4) / (METRIC == SIL_COSINE ? 2 : 1);
+  constexpr int NW = CH >= 4 ? CH / 4 : 1;  // 32-bit words per lane (fp8 rows of 128 B: half of one)
+  // rows per batch; cosine and 4-byte fp8 chunks halve it (the row sums and norms, or the
+  // decoded values, would need twice the registers)
+  constexpr int U = (NW == 1 ? 16 : NW == 2 ? 8 : 4) / (METRIC == SIL_COSINE ? 2 : 1) /
+                    (DT == SIL_FP8_E4M3 && CH == 4 ? 2 : 1);
   constexpr int64_t RB = 64 * CH;
   typedef uint32_t chunk_t __attribute__((ext_vector_type(NW == 1 ? 2 : NW)));
   const int lane = threadIdx.x & 63;
@@ -630,6 +633,12 @@ __device__ __forceinline__ void segreduce_row_body(
   const int64_t p1 = min(nvalid, p0 + static_cast<int64_t>(kSegLen));
   if (p0 >= p1) return;
   const char* Xl = static_cast<const char*>(X) + lane * CH;
+  // fp8: the lane's columns lane * E .. + E keep their scales for every row
+  float sc[DT == SIL_FP8_E4M3 ? E : 1];
+  if constexpr (DT == SIL_FP8_E4M3) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) sc[e] = col_scale[lane * E + e];
+  }
 
   int32_t kc = find_cluster(offset, K, p0);
   int64_t rs = offset[kc], re = offset[kc + 1];
@@ -660,6 +669,13 @@ __device__ __forceinline__ void segreduce_row_body(
   };
 
   auto decode = [&](chunk_t raw, double* x) __attribute__((always_inline)) {
+    if constexpr (DT == SIL_FP8_E4M3) {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        x[e] = static_cast<double>(e4m3_to_f32(static_cast<uint8_t>(raw[0] >> (8 * e)))) *
+               static_cast<double>(sc[e]);
+      return;
+    }
 #pragma unroll
     for (int w = 0; w < (NW == 1 ? 1 : NW); ++w) {
       if constexpr (DT == SIL_F32) {
@@ -744,7 +760,9 @@ __device__ __forceinline__ void segreduce_row_body(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const char* src = Xl + static_cast<int64_t>(ids[u]) * RB;
-      if constexpr (NW == 1)
+      if constexpr (CH == 2)
+        raw[u] = chunk_t{static_cast<uint32_t>(*reinterpret_cast<const uint16_t*>(src)), 0u};
+      else if constexpr (NW == 1)
         raw[u] = chunk_t{*reinterpret_cast<const uint32_t*>(src), 0u};
       else
         raw[u] = *reinterpret_cast<const chunk_t*>(src);
@@ -799,12 +817,12 @@ __device__ __forceinline__ void segreduce_row_body(
 
 template <int DT, int CH, int METRIC>
 __global__ __launch_bounds__(256) void k_segreduce_row(
-    const void* __restrict__ X, const int32_t* __restrict__ perm,
+    const void* __restrict__ X, const float* __restrict__ col_scale, const int32_t* __restrict__ perm,
     const int32_t* __restrict__ offset, int32_t K, int32_t D, int64_t nseg,
     double* __restrict__ V, double* __restrict__ psi, double* __restrict__ segpart,
     int32_t* __restrict__ hdr) {
-  segreduce_row_body<DT, CH, METRIC>(X, perm, offset, K, D, nseg, V, psi, segpart, hdr,
-                                     blockIdx.x);
+  segreduce_row_body<DT, CH, METRIC>(X, col_scale, perm, offset, K, D, nseg, V, psi, segpart,
+                                     hdr, blockIdx.x);
 }
 
 // Sums of clusters whose sorted range spans several segments.  One thread per (cluster,
@@ -845,17 +863,18 @@ __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ off
 template <int DT, int METRIC>
 static void launch_seg_row(const Problem& p, const WsLayout& L, const WsPtrs& w, int ch,
                            unsigned nblk, hipStream_t st) {
-  if constexpr (DT != SIL_FP8_E4M3) {
-    if (ch == 4)
-      k_segreduce_row<DT, 4, METRIC><<<nblk, 256, 0, st>>>(p.X, w.perm, w.offset, p.K, p.D,
-                                                           L.nseg, w.V, w.psi, w.segpart, w.hdr);
-    else if (ch == 8)
-      k_segreduce_row<DT, 8, METRIC><<<nblk, 256, 0, st>>>(p.X, w.perm, w.offset, p.K, p.D,
-                                                           L.nseg, w.V, w.psi, w.segpart, w.hdr);
-    else
-      k_segreduce_row<DT, 16, METRIC><<<nblk, 256, 0, st>>>(p.X, w.perm, w.offset, p.K, p.D,
-                                                            L.nseg, w.V, w.psi, w.segpart, w.hdr);
+#define SIL_ROW(CH)                                                                            \
+  k_segreduce_row<DT, CH, METRIC><<<nblk, 256, 0, st>>>(p.X, p.col_scale, w.perm, w.offset, p.K, \
+                                                        p.D, L.nseg, w.V, w.psi, w.segpart, w.hdr)
+  if constexpr (DT == SIL_FP8_E4M3) {  // rows of 128 or 256 bytes
+    if (ch == 2) SIL_ROW(2);
+    else SIL_ROW(4);
+  } else {
+    if (ch == 4) SIL_ROW(4);
+    else if (ch == 8) SIL_ROW(8);
+    else SIL_ROW(16);
   }
+#undef SIL_ROW
 }
 
 hipError_t launch_sort(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
@@ -888,7 +907,7 @@ hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hi
   int32_t Gv, G, E;
   stats_lanes(p.D, p.dtype, &Gv, &G, &E);
   const bool vec = Gv != 0;
-  // whole-wave rows (fp32 or bf16 rows of 256, 512 or 1024 bytes)
+  // whole-wave rows (fp32 or bf16 rows of 256, 512 or 1024 bytes; fp8 rows of 128 or 256)
   const int rowch = row_chunk(p.D, p.dtype);
 #define SIL_SEG(DT, MT)                                                                         \
   do {                                                                                          \
@@ -969,11 +988,11 @@ __global__ __launch_bounds__(256) void kb_seg(BatchDev b) {
   const BatchProblem& q = batch_item(b, BP_SEG, &it);
   if (q.metric == SIL_SQEUCLID) {
     if (q.rowch == 4)
-      segreduce_row_body<SIL_F32, 4>(q.X, q.perm, q.offset, q.K, q.D, q.nseg, q.V, q.psi,
-                                     q.segpart, q.hdr, it);
+      segreduce_row_body<SIL_F32, 4>(q.X, nullptr, q.perm, q.offset, q.K, q.D, q.nseg, q.V,
+                                     q.psi, q.segpart, q.hdr, it);
     else if (q.rowch == 8)
-      segreduce_row_body<SIL_F32, 8>(q.X, q.perm, q.offset, q.K, q.D, q.nseg, q.V, q.psi,
-                                     q.segpart, q.hdr, it);
+      segreduce_row_body<SIL_F32, 8>(q.X, nullptr, q.perm, q.offset, q.K, q.D, q.nseg, q.V,
+                                     q.psi, q.segpart, q.hdr, it);
     else if (q.Gv)
       segreduce_vec_body<SIL_F32, SIL_SQEUCLID>(q.X, q.col_scale, q.perm, q.offset, q.K, q.D, q.Gv,
                                                 q.nseg, q.V, q.psi, q.segpart, q.hdr, it);
@@ -996,9 +1015,10 @@ __global__ __launch_bounds__(256) void kb_combine(BatchDev b) {
   combine_body(q.offset, q.K, q.D, q.segpart, q.V, q.psi, it);
 }
 
-// Bytes per lane of the whole-wave row reduction (fp32 or bf16 rows of 256, 512 or 1024 bytes),
-// else 0.
+// Bytes per lane of the whole-wave row reduction (fp32 or bf16 rows of 256, 512 or 1024 bytes;
+// fp8 rows of 128 or 256 bytes), else 0.
 int row_chunk(int32_t D, int32_t dtype) {
+  if (dtype == SIL_FP8_E4M3) return (D == 128 || D == 256) ? D / 64 : 0;
   if (dtype != SIL_F32 && dtype != SIL_BF16) return 0;
   const int64_t rb = static_cast<int64_t>(D) * (dtype == SIL_F32 ? 4 : 2);
   return (rb == 256 || rb == 512 || rb == 1024) ? static_cast<int>(rb / 64) : 0;

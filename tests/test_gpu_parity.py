@@ -76,7 +76,8 @@ def test_stats_parity(dev, metric, form):
 
 # statistics of rows of 256, 512 or 1024 bytes (the whole-wave row reduction; for cosine the
 # batch's row norms are reduced across the wave together)
-ROW_CASES = [(128, "bf16"), (256, "bf16"), (64, "f32"), (128, "f32"), (256, "f32")]
+ROW_CASES = [(128, "bf16"), (256, "bf16"), (64, "f32"), (128, "f32"), (256, "f32"), (128, "fp8"),
+             (256, "fp8")]
 
 
 def row_case_labels(rng):
@@ -100,8 +101,9 @@ def test_stats_row_reduction(dev, D, form, metric):
     X = torch.from_numpy(rng.standard_normal((len(lab), D)).astype(np.float32) * 3 + 1)
     Xd, sc, codes = storage(X.to(dev), form)
     print(f"[stats-row] N={len(lab)} D={D} K={K} form={form} metric={metric}", flush=True)
-    count, V, psi = sil.cluster_stats(Xd, torch.from_numpy(lab).to(dev), K, metric)
-    c_ref, V_ref, p_ref = oracle.cluster_stats(codes, lab, K, metric)
+    count, V, psi = sil.cluster_stats(Xd, torch.from_numpy(lab).to(dev), K, metric, col_scale=sc)
+    c_ref, V_ref, p_ref = oracle.cluster_stats(codes, lab, K, metric,
+                                               col_scale=None if sc is None else sc.cpu().numpy())
     assert np.array_equal(count.cpu().numpy(), c_ref)
     scale = np.abs(V_ref).max()
     np.testing.assert_allclose(V.cpu().numpy(), V_ref, rtol=1e-12, atol=1e-12 * scale)
@@ -120,7 +122,7 @@ def test_stats_row_reduction_nonfinite(dev, metric):
     assert e.value.code == -6
 
 
-@pytest.mark.parametrize("D,form", [(128, "bf16"), (64, "f32"), (256, "f32")])
+@pytest.mark.parametrize("D,form", [(128, "bf16"), (64, "f32"), (256, "f32"), (128, "fp8")])
 def test_stats_row_reduction_zero_norm(dev, D, form):
     # a zero row in the middle of a batch, and one as the last row of the data
     from paper_2303_14102_amd import _lib
@@ -129,9 +131,9 @@ def test_stats_row_reduction_zero_norm(dev, D, form):
         b = wl.make_small(9_000, D, 6, seed=10)
         X = b.X.clone()
         X[row] = 0.0
-        Xd = storage(X.to(dev), form)[0]
+        Xd, sc, _ = storage(X.to(dev), form)
         with pytest.raises(_lib.SilhouetteError) as e:
-            sil.silhouette(Xd, b.labels.to(dev), 6, "cosine", check_status=True)
+            sil.silhouette(Xd, b.labels.to(dev), 6, "cosine", col_scale=sc, check_status=True)
         assert e.value.code == -5
 
 
