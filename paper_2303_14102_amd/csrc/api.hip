@@ -49,7 +49,9 @@ WsLayout make_layout(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dt
   L.save_b = take(save ? static_cast<size_t>(N) * 4 : 0);
   L.save_n = take(save ? static_cast<size_t>(N) * 4 : 0);
   const size_t KW = static_cast<size_t>(K) * (D + 1);
-  L.gpart = take(save && bwd_fits_lds(K, D) ? static_cast<size_t>(bwd_accum_workgroups(N)) * KW * 8 : 0);
+  L.gpart = take(save && (bwd_fits_lds(K, D) || bwd_fits_slices(K))
+                     ? static_cast<size_t>(bwd_accum_workgroups(N)) * KW * 8
+                     : 0);
   L.gAB = take(save ? KW * 8 : 0);
   L.total = o;
   return L;

@@ -154,6 +154,56 @@ __global__ __launch_bounds__(64 * kBwdWaves) void kb_accum_global(BwdArgs a) {
   }
 }
 
+// Squared Euclidean partials by column slice.  Workgroup b of the grid is row group b % nrg and
+// slice b / nrg: it accumulates columns 64 s .. 64 s + 63 (one per lane) of the rows of its
+// group, and slice 0 also the alphas themselves (A_k, slot 64).  Its LDS holds K x 65 values
+// instead of K x (D + 1), so several workgroups share a CU; every row is still read once in all.
+constexpr int kBwdSlice = 64;
+__global__ __launch_bounds__(64 * kBwdWaves) void kb_accum_slice(BwdArgs a, int nrg) {
+  extern __shared__ double sh[];  // [K * 65]
+  constexpr int SW = kBwdSlice + 1;
+  const int W = a.D + 1;
+  const int64_t KS = static_cast<int64_t>(a.K) * SW;
+  for (int64_t q = threadIdx.x; q < KS; q += blockDim.x) sh[q] = 0.0;
+  __syncthreads();
+  const int rg = static_cast<int>(blockIdx.x) % nrg, sl = static_cast<int>(blockIdx.x) / nrg;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = sl * kBwdSlice + lane;
+  const bool col_ok = c < a.D;
+  const float mv = col_ok ? a.mvec[c] : 0.0f;
+  const double gS = *a.gS;
+  const int64_t nw = static_cast<int64_t>(nrg) * kBwdWaves;
+  for (int64_t i = static_cast<int64_t>(rg) * kBwdWaves + wave; i < a.N; i += nw) {
+    const int32_t o = a.labels[i];
+    const int32_t n = a.save_n[i];
+    if (o < 0 || o >= a.K) continue;
+    double al_o, al_n;
+    alphas(a, i, o, gS, al_o, al_n);
+    if (al_o == 0.0 && al_n == 0.0) continue;
+    const bool has_n = n >= 0 && n < a.K;
+    if (col_ok) {
+      const double v = static_cast<double>(a.X[i * static_cast<int64_t>(a.D) + c] - mv);
+      atomicAdd(&sh[static_cast<int64_t>(o) * SW + lane], al_o * v);
+      if (has_n) atomicAdd(&sh[static_cast<int64_t>(n) * SW + lane], al_n * v);
+    }
+    if (sl == 0 && lane == 0) {
+      atomicAdd(&sh[static_cast<int64_t>(o) * SW + kBwdSlice], al_o);
+      if (has_n) atomicAdd(&sh[static_cast<int64_t>(n) * SW + kBwdSlice], al_n);
+    }
+  }
+  __syncthreads();
+  double* out = a.part + static_cast<int64_t>(rg) * a.K * W;
+  for (int64_t q = threadIdx.x; q < KS; q += blockDim.x) {
+    const int64_t k = q / SW;
+    const int j = static_cast<int>(q % SW);
+    if (j < kBwdSlice) {
+      if (sl * kBwdSlice + j < a.D) out[k * W + sl * kBwdSlice + j] = sh[q];
+    } else if (sl == 0) {
+      out[k * W + a.D] = sh[q];
+    }
+  }
+}
+
 // AB[q] = sum of the workgroup partials in workgroup order.
 __global__ __launch_bounds__(256) void kb_reduce(const double* __restrict__ part, int nwg,
                                                  int64_t KW, double* __restrict__ AB) {
@@ -237,6 +287,11 @@ bool bwd_fits_lds(int32_t K, int32_t D) {
   return static_cast<int64_t>(K) * (D + 1) * 8 <= 160 * 1024;
 }
 
+// The column-slice form (squared Euclidean): K x 65 partials per workgroup.
+bool bwd_fits_slices(int32_t K) {
+  return static_cast<int64_t>(K) * (kBwdSlice + 1) * 8 <= 160 * 1024;
+}
+
 hipError_t launch_backward(const Problem& p, const WsLayout& L, const WsPtrs& w, const double* gS,
                            float* dX, hipStream_t st) {
   BwdArgs a;
@@ -260,7 +315,16 @@ hipError_t launch_backward(const Problem& p, const WsLayout& L, const WsPtrs& w,
   const int64_t KW = static_cast<int64_t>(p.K) * (p.D + 1);
   const int nwg = bwd_accum_workgroups(p.N);
   const bool lds = bwd_fits_lds(p.K, p.D);
-  if (lds) {
+  if (p.metric == SIL_SQEUCLID && bwd_fits_slices(p.K)) {
+    const size_t shm = static_cast<size_t>(p.K) * (kBwdSlice + 1) * 8;
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_accum_slice),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             static_cast<int>(shm));
+    if (e != hipSuccess) return e;
+    const int nsl = static_cast<int>(ceil_div(p.D, kBwdSlice));
+    kb_accum_slice<<<static_cast<unsigned>(nwg * nsl), 64 * kBwdWaves, shm, st>>>(a, nwg);
+    kb_reduce<<<static_cast<unsigned>(ceil_div(KW, 256)), 256, 0, st>>>(w.gpart, nwg, KW, w.gAB);
+  } else if (lds) {
     const size_t shm = static_cast<size_t>(KW) * 8;
     if (p.metric == SIL_SQEUCLID) {
       const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_accum<SIL_SQEUCLID>),

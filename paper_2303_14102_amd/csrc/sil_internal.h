@@ -194,6 +194,7 @@ hipError_t launch_backward(const Problem& p, const WsLayout& L, const WsPtrs& w,
                            float* dX, hipStream_t st);
 int bwd_accum_workgroups(int64_t N);
 bool bwd_fits_lds(int32_t K, int32_t D);
+bool bwd_fits_slices(int32_t K);
 
 // ------------------------------------------------------------------------------------------
 // batched evaluation: many problems (labelings of one or several data sets) per launch

@@ -53,12 +53,15 @@ def test_gradient_vs_oracle(dev, metric, n, d, k, single):
     assert err <= 1e-4
 
 
-@pytest.mark.parametrize("n,d,k", [(6000, 128, 200), (3000, 256, 80)])
-def test_gradient_large_k_global_path(dev, n, d, k):
-    # K (D+1) FP64 values beyond the 160 KB LDS budget: global-atomic accumulation
+# the accumulation forms: squared Euclidean by 64-column slices (K x 65 partials in LDS, here
+# 104 KB and 41.6 KB), and global atomics once neither K x 65 nor K (D+1) FP64 values fit the
+# 160 KB budget (squared Euclidean K = 320, D = 64; cosine K = 80, D = 256)
+@pytest.mark.parametrize("n,d,k,metric", [(6000, 128, 200, "sqeuclid"), (3000, 256, 80, "sqeuclid"),
+                                          (5000, 64, 320, "sqeuclid"), (3000, 256, 80, "cosine")])
+def test_gradient_accumulation_paths(dev, n, d, k, metric):
     b = wl.make_small(n, d, k, seed=41, sigma=1.0)
-    S, g = gpu_grad(dev, b.X, b.labels, k, "sqeuclid")
-    ref = oracle.gradient(b.X.numpy(), b.labels.numpy(), k, "sqeuclid")
+    S, g = gpu_grad(dev, b.X, b.labels, k, metric)
+    ref = oracle.gradient(b.X.numpy(), b.labels.numpy(), k, metric)
     assert rel_l2(g, ref) <= 1e-4
 
 
