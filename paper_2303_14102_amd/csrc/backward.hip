@@ -93,7 +93,8 @@ __global__ __launch_bounds__(64 * kBwdWaves) void kb_accum(BwdArgs a) {
   const int64_t KW = static_cast<int64_t>(a.K) * W;
   for (int64_t q = threadIdx.x; q < KW; q += blockDim.x) sh[q] = 0.0;
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // wave-uniform wave index: the per-row loads (labels, saves, counts) become scalar loads
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const double gS = *a.gS;
   const int64_t nw = static_cast<int64_t>(gridDim.x) * kBwdWaves;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBwdWaves + wave; i < a.N; i += nw) {
@@ -127,7 +128,8 @@ __global__ __launch_bounds__(64 * kBwdWaves) void kb_accum(BwdArgs a) {
 template <int METRIC>
 __global__ __launch_bounds__(64 * kBwdWaves) void kb_accum_global(BwdArgs a) {
   const int W = a.D + 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // wave-uniform wave index: the per-row loads (labels, saves, counts) become scalar loads
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const double gS = *a.gS;
   const int64_t nw = static_cast<int64_t>(gridDim.x) * kBwdWaves;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBwdWaves + wave; i < a.N; i += nw) {
@@ -167,7 +169,8 @@ __global__ __launch_bounds__(64 * kBwdWaves) void kb_accum_slice(BwdArgs a, int 
   for (int64_t q = threadIdx.x; q < KS; q += blockDim.x) sh[q] = 0.0;
   __syncthreads();
   const int rg = static_cast<int>(blockIdx.x) % nrg, sl = static_cast<int>(blockIdx.x) / nrg;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // wave-uniform wave index: the per-row loads (labels, saves, counts) become scalar loads
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c = sl * kBwdSlice + lane;
   const bool col_ok = c < a.D;
   const float mv = col_ok ? a.mvec[c] : 0.0f;
@@ -227,7 +230,9 @@ __global__ __launch_bounds__(256) void kb_dx(BwdArgs a) {
   const double gS = *a.gS;
   const bool bad = a.hdr[0] != 0;
   const int64_t nw = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  // wave-uniform row index: the per-row loads (labels, saves, counts) become scalar loads
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) +
+                   __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
        i < a.N; i += nw) {
     const int64_t base = i * static_cast<int64_t>(a.D);
     const int32_t o = a.labels[i];
