@@ -335,7 +335,7 @@ int silhouette_batched_tune(sil_plan* plan, void* ws, size_t ws_bytes, void* str
 
 /* The chosen configuration into out[0..5] (host): workgroups of the persistent grid, items per
  * queue access, queue order (0 costliest first, 1 problem order), and 32-row blocks per wave
- * for GEMM depths 16, 24, 40.  len must be >= 6. */
+ * for GEMM depths 16, 24, 32 (D up to 16, 17..24, 25..32).  len must be >= 6. */
 int silhouette_batched_config(const sil_plan* plan, int32_t* out, int32_t len);
 
 /* Sets the configuration from cfg[0..5] (host, same layout as silhouette_batched_config), for

@@ -41,8 +41,16 @@ def _check_inputs(X, labels, col_scale):
     if labels.dtype != torch.int32 or labels.shape != (X.shape[0],) or not labels.is_contiguous():
         raise ValueError("labels must be a contiguous int32 [N] tensor")
     if X.dtype == torch.float8_e4m3fn:
-        if col_scale is None or col_scale.dtype != torch.float32 or col_scale.shape != (X.shape[1],):
-            raise ValueError("fp8 X needs a float32 [D] col_scale on the same device")
+        _check_col_scale(col_scale, X.shape[1], X.device)
+
+
+def _check_col_scale(col_scale, D, device):
+    """fp8 storage: the kernels read col_scale as D consecutive float32 values in device memory,
+    so anything else (a host tensor, a strided view, another dtype or length) is refused here,
+    before any launch."""
+    if (col_scale is None or col_scale.dtype != torch.float32 or tuple(col_scale.shape) != (D,)
+            or not col_scale.is_contiguous() or col_scale.device != device):
+        raise ValueError("fp8 X needs a contiguous float32 [D] col_scale on the same device as X")
 
 
 def workspace_bytes(N: int, D: int, K: int, metric: str = "sqeuclid", dtype=torch.float32,
@@ -180,15 +188,17 @@ def silhouette_stream(X_host: torch.Tensor, labels_host: torch.Tensor, K: int, m
     (s float32 [N] in pinned host memory or None, S float64 0-d tensor on the device).  With
     sync=False the call returns after enqueueing: the host tensors must then be kept alive and
     unchanged until the current stream completes."""
-    device = device or torch.device("cuda", torch.cuda.current_device())
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    if device.type == "cuda" and device.index is None:
+        device = torch.device("cuda", torch.cuda.current_device())
     if X_host.device.type != "cpu" or labels_host.device.type != "cpu":
         raise ValueError("X_host and labels_host must be host tensors")
     if X_host.dim() != 2 or not X_host.is_contiguous():
         raise ValueError("X_host must be a contiguous [N, D] tensor")
     if labels_host.dtype != torch.int32 or labels_host.shape != (X_host.shape[0],) or not labels_host.is_contiguous():
         raise ValueError("labels_host must be a contiguous int32 [N] tensor")
-    if X_host.dtype == torch.float8_e4m3fn and (col_scale is None or col_scale.device != device):
-        raise ValueError("fp8 X needs a float32 [D] col_scale on the device")
+    if X_host.dtype == torch.float8_e4m3fn:
+        _check_col_scale(col_scale, X_host.shape[1], device)
     N, D = X_host.shape
     flags = ((0 if centre else L.SIL_FLAG_NO_CENTRE) | (L.SIL_FLAG_EUCLID_APPROX if euclid_approx else 0))
     if workspace is None:
@@ -314,13 +324,13 @@ class BatchedSilhouette:
         out = (ctypes.c_int32 * 6)()
         L.check(L.load().silhouette_batched_config(self._plan, out, 6), "silhouette_batched_config")
         return {"grid": out[0], "grab": out[1], "order": ("cost", "problem")[out[2]],
-                "rows_per_item": {16: 128 * out[3], 24: 128 * out[4], 40: 128 * out[5]}}
+                "rows_per_item": {16: 128 * out[3], 24: 128 * out[4], 32: 128 * out[5]}}
 
     def set_config(self, grid: int, grab: int = 1, order: str = "cost", rows_per_item=None):
-        """Pin the launch configuration (rows_per_item: {16|24|40: 128 or 256})."""
-        rpi = {16: 128, 24: 128, 40: 128, **(rows_per_item or {})}
+        """Pin the launch configuration (rows_per_item: {16|24|32: 128 or 256}, keyed by GEMM depth)."""
+        rpi = {16: 128, 24: 128, 32: 128, **(rows_per_item or {})}
         cfg = (ctypes.c_int32 * 6)(grid, grab, {"cost": 0, "problem": 1}[order], rpi[16] // 128,
-                                   rpi[24] // 128, rpi[40] // 128)
+                                   rpi[24] // 128, rpi[32] // 128)
         L.check(L.load().silhouette_batched_set_config(self._plan, cfg, 6), "silhouette_batched_set_config")
 
     def capture(self, stream: torch.cuda.Stream):

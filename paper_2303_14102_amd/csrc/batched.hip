@@ -303,7 +303,7 @@ int silhouette_batched_tune(sil_plan* plan, void* ws, size_t ws_bytes, void* str
     return SIL_OK;
   };
   // rows per work item, one depth class at a time
-  for (int dpx : {16, 24, 40}) {
+  for (int dpx : kShallowDepths) {
     std::vector<int> idx;
     for (size_t i = 0; i < plan->prob.size(); ++i)
       if (plan->L[i].DPX == dpx) idx.push_back(static_cast<int>(i));
@@ -342,10 +342,9 @@ int silhouette_batched_config(const sil_plan* plan, int32_t* out, int32_t len) {
   out[1] = plan->grab;
   out[2] = plan->order_mode;
   for (int c = 0; c < 3; ++c) out[3 + c] = 1;
-  const int dp[3] = {16, 24, 40};
   for (size_t i = 0; i < plan->prob.size(); ++i)
     for (int c = 0; c < 3; ++c)
-      if (plan->L[i].DPX == dp[c]) out[3 + c] = plan->nb[i];
+      if (plan->L[i].DPX == kShallowDepths[c]) out[3 + c] = plan->nb[i];
   return SIL_OK;
 }
 
@@ -358,11 +357,10 @@ int silhouette_batched_set_config(sil_plan* plan, const int32_t* cfg, int32_t le
   plan->grid = cfg[0];
   plan->grab = cfg[1];
   plan->order_mode = cfg[2];
-  const int dp[3] = {16, 24, 40};
   for (size_t i = 0; i < plan->prob.size(); ++i) {
     plan->nb[i] = 1;
     for (int c = 0; c < 3; ++c)
-      if (plan->L[i].DPX == dp[c]) plan->nb[i] = cfg[3 + c];
+      if (plan->L[i].DPX == kShallowDepths[c]) plan->nb[i] = cfg[3 + c];
   }
   plan->uploaded_ws = nullptr;
   drop_graph(plan);

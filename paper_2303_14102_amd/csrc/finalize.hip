@@ -9,9 +9,10 @@
 //     c_k = ||mu'_k||^2 + sigma_k^2            (uncentred: c_k = Psi_k / N_k, m = 0).
 // Cosine (Eq.18), z = x/||x||, mu_k = Omega_k / N_k:
 //     m(x, k) = 1 - z.mu_k = (1 - ||mu_k||^2 + ||z - mu_k||^2) / 2.
-// The b-path (minimum over the other clusters) uses the GEMM form, with c_k carried in the GEMM
-// depth; the a-path (own cluster) uses the difference form, which has no cancellation.  All
-// table entries are formed in FP64 and rounded once.
+// The b-path (minimum over the other clusters) uses the GEMM form, with c_k held in its own fp32
+// table and added to the cross term in the fused kernel's epilogue; the a-path (own cluster)
+// uses the difference form, which has no cancellation.  All table entries are formed in FP64
+// and rounded once.
 #include "sil_internal.h"
 
 namespace sil {

@@ -14,14 +14,7 @@ static void run_assign(const MainArgs& m, unsigned grid, hipStream_t st) {
 
 template <int DT, int P>
 static void run_assign_dt(const MainArgs& m, int DPX, unsigned grid, hipStream_t st) {
-  switch (DPX) {
-    case 16: run_assign<16, DT, P>(m, grid, st); break;
-    case 32: run_assign<32, DT, P>(m, grid, st); break;
-    case 48: run_assign<48, DT, P>(m, grid, st); break;
-    case 80: run_assign<80, DT, P>(m, grid, st); break;
-    case 128: run_assign<128, DT, P>(m, grid, st); break;
-    default: run_assign<256, DT, P>(m, grid, st); break;
-  }
+  with_depth(DepthsBf16{}, DPX, [&](auto dp) { run_assign<decltype(dp)::value, DT, P>(m, grid, st); });
 }
 
 void launch_main_assign(const MainArgs& m, int DPX, int dtype, int products, unsigned grid,

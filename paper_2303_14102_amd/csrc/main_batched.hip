@@ -102,12 +102,18 @@ __device__ __forceinline__ void batch_body(const MainArgs& a, int DPX, int nb, i
       if (nb == 2) SIL_BODY(24, 2);
       else SIL_BODY(24, 1);
       break;
-    case 40:
-      if (nb == 2) SIL_BODY(40, 2);
-      else SIL_BODY(40, 1);
+    case 32:
+      if (nb == 2) SIL_BODY(32, 2);
+      else SIL_BODY(32, 1);
       break;
-    case 72:
-      SIL_BODY(72, 1);
+    case 48:
+      SIL_BODY(48, 1);
+      break;
+    case 64:
+      SIL_BODY(64, 1);
+      break;
+    case 96:
+      SIL_BODY(96, 1);
       break;
     default:
       SIL_BODY(128, 1);

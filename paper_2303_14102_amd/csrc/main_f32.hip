@@ -13,14 +13,7 @@ static void run_f32(const MainArgs& m, bool save, unsigned grid, hipStream_t st)
 
 template <int METRIC>
 static void run_f32_dp(const MainArgs& m, int DPX, bool save, unsigned grid, hipStream_t st) {
-  switch (DPX) {
-    case 16: run_f32<16, METRIC>(m, save, grid, st); break;
-    case 24: run_f32<24, METRIC>(m, save, grid, st); break;
-    case 40: run_f32<40, METRIC>(m, save, grid, st); break;
-    case 72: run_f32<72, METRIC>(m, save, grid, st); break;
-    case 128: run_f32<128, METRIC>(m, save, grid, st); break;
-    default: run_f32<256, METRIC>(m, save, grid, st); break;
-  }
+  with_depth(DepthsF32{}, DPX, [&](auto dp) { run_f32<decltype(dp)::value, METRIC>(m, save, grid, st); });
 }
 
 template <int DPX>
@@ -35,14 +28,7 @@ void launch_main_f32(const MainArgs& m, int DPX, int metric, bool save, unsigned
   } else if (metric == SIL_COSINE) {
     run_f32_dp<SIL_COSINE>(m, DPX, save, grid, st);
   } else {  // the KL divergence has no backward, so no kernels that keep a_i, b_i
-    switch (DPX) {
-      case 16: run_f32_kl<16>(m, grid, st); break;
-      case 24: run_f32_kl<24>(m, grid, st); break;
-      case 40: run_f32_kl<40>(m, grid, st); break;
-      case 72: run_f32_kl<72>(m, grid, st); break;
-      case 128: run_f32_kl<128>(m, grid, st); break;
-      default: run_f32_kl<256>(m, grid, st); break;
-    }
+    with_depth(DepthsF32{}, DPX, [&](auto dp) { run_f32_kl<decltype(dp)::value>(m, grid, st); });
   }
 }
 

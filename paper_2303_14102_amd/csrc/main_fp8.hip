@@ -22,14 +22,7 @@ static void run_dp(const MainArgs& m, int products, unsigned grid, hipStream_t s
 
 template <int METRIC>
 static void run_metric(const MainArgs& m, int DPX, int products, unsigned grid, hipStream_t st) {
-  switch (DPX) {
-    case 16: run_dp<16, METRIC>(m, products, grid, st); break;
-    case 32: run_dp<32, METRIC>(m, products, grid, st); break;
-    case 48: run_dp<48, METRIC>(m, products, grid, st); break;
-    case 80: run_dp<80, METRIC>(m, products, grid, st); break;
-    case 128: run_dp<128, METRIC>(m, products, grid, st); break;
-    default: run_dp<256, METRIC>(m, products, grid, st); break;
-  }
+  with_depth(DepthsBf16{}, DPX, [&](auto dp) { run_dp<decltype(dp)::value, METRIC>(m, products, grid, st); });
 }
 
 void launch_main_fp8(const MainArgs& m, int DPX, int metric, int products, unsigned grid,

@@ -2,13 +2,14 @@
 // cluster statistics (Eq.11 / Eq.18), a_i, b_i, s_i (Eq.1) and a per-workgroup sum of s_i.
 //
 // The point-to-cluster-mean term over all (i, k) is a dense [N x D] x [D x K] product and runs
-// on MFMA; the [N x K] result never leaves registers.  The per-cluster constant rides in the
-// GEMM depth: the table row of cluster k is [alpha * mu'_k, c_k] and the point carries
-// [x', 1], so the accumulator directly holds
-//     v_ik = c_k + alpha x'_i.mu'_k      (alpha = -2 squared Euclidean, -1 cosine)
-// and the epilogue is a running minimum.  b_i = ||x'_i||^2 + min_{k != own} v_ik (squared
-// Euclidean) or min_{k != own} v_ik (cosine, c_k = 1).  Empty and padding clusters carry a huge
-// finite c_k.  (For bf16 the constant is carried as three bf16 pieces, hi + mid + lo.)
+// on MFMA; the [N x K] result never leaves registers.  The table row of cluster k is
+// alpha * mu'_k (alpha = -2 squared Euclidean, -1 cosine) and the point supplies x', so the
+// accumulator holds alpha x'_i.mu'_k; the epilogue adds the per-cluster constant c_k (one fp32
+// value per lane, since every accumulator of a lane lies in one cluster column) and keeps a
+// running minimum:
+//     v_ik = c_k + alpha x'_i.mu'_k,
+// b_i = ||x'_i||^2 + min_{k != own} v_ik (squared Euclidean) or 1 + min_{k != own} v_ik (cosine,
+// c_k = 0, the 1 added after the minimum).  Empty and padding clusters carry a huge finite c_k.
 //
 // Rows are visited in label-sorted order (the permutation of the statistics pass), so a block
 // of 32 rows almost always belongs to one cluster: its own-cluster column is then excluded by a
@@ -971,9 +972,9 @@ void launch_main_fp8(const MainArgs& m, int DPX, int metric, int products, unsig
 // products (or a deep row) would not fit the register budget of two waves per SIMD.  Two row
 // blocks read each table fragment from LDS once for 64 rows, which halves the LDS traffic per
 // MFMA: at depth 128 with two products it is as large as the MFMA time with one block.  fp8
-// storage stops at depth 80 (its decode would spill at 128).
+// storage stops at depth 64 (its decode would spill at 128).
 constexpr int bf16_nb(int DPX, int P, int DT) {
-  return (P == 3 || DPX > (DT == SIL_BF16 ? 128 : 80)) ? 1 : 2;
+  return (P == 3 || DPX > (DT == SIL_BF16 ? 128 : 64)) ? 1 : 2;
 }
 
 }  // namespace sil

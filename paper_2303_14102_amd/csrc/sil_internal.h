@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/silhouette.h"
 
 namespace sil {
@@ -24,19 +26,29 @@ constexpr int kMainWaves = 4;       // waves per workgroup in the fused GEMM+epi
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
-// GEMM depth of the fused kernels: the D coordinates rounded up to an instantiated depth (the
-// per-cluster constant is added in the epilogue, not carried in the depth).
-constexpr int kDepthsBf16[] = {16, 32, 48, 80, 128, 256};
-constexpr int kDepthsF32[] = {16, 24, 40, 72, 128, 256};
+// GEMM depth of the fused kernels: D rounded up to an instantiated depth class (the
+// per-cluster constant is added in the epilogue, not carried in the depth).  A bf16 k-step is 16
+// deep, an fp32 one 8 (two halves of 4), so every multiple of 16 up to 64 is its own class and D
+// of 16, 32, 64, 128 or 256 runs with no padded columns.
+template <int... Ds>
+struct DepthList {};
+using DepthsBf16 = DepthList<16, 32, 48, 64, 96, 128, 256>;
+using DepthsF32 = DepthList<16, 24, 32, 48, 64, 96, 128, 256>;
+
+template <int... Ds>
+constexpr int first_depth_at_least(DepthList<Ds...>, int D) {
+  int r = 0;
+  (void)((D <= Ds ? (r = Ds, true) : false) || ...);
+  return r;
+}
 inline int gemm_depth(int D, int dtype) {
-  if (dtype == SIL_F32) {
-    for (int v : kDepthsF32)
-      if (D <= v) return v;
-  } else {
-    for (int v : kDepthsBf16)
-      if (D <= v) return v;
-  }
-  return 0;
+  return dtype == SIL_F32 ? first_depth_at_least(DepthsF32{}, D)
+                          : first_depth_at_least(DepthsBf16{}, D);
+}
+// Calls f(std::integral_constant<int, DPX>{}) for the class equal to DPX (host launchers).
+template <int... Ds, typename F>
+inline void with_depth(DepthList<Ds...>, int DPX, F&& f) {
+  (void)((DPX == Ds ? (f(std::integral_constant<int, Ds>{}), true) : false) || ...);
 }
 
 // Row stride of the GEMM table in elements: DPX plus one 16-byte chunk, so that a row spans an
@@ -201,6 +213,9 @@ bool bwd_fits_slices(int32_t K);
 
 constexpr int kBatchMaxProblems = 1024;
 constexpr int kBatchMaxD = 128;  // fp32 storage, GEMM depth <= 128
+// GEMM depths of the persistent kernel that may run two 32-row blocks per wave (the tuner's
+// and silhouette_batched_config's rows-per-item classes, in this order)
+constexpr int kShallowDepths[3] = {16, 24, 32};
 
 // One problem of a batch as the kernels see it (device memory, written by the plan).
 struct BatchProblem {

@@ -198,3 +198,19 @@ def test_batched_plan_host_checks(lib):
     assert lib.silhouette_batched_replay(None, None) == -1
     assert lib.silhouette_batched_set_config(None, None, 6) == -1
     lib.silhouette_batched_free(None)
+
+
+def test_fp8_col_scale_checks_on_the_host():
+    """fp8 storage: col_scale must be a contiguous float32 [D] tensor on X's device; anything
+    else raises before a pointer reaches the C ABI."""
+    import torch
+
+    from paper_2303_14102_amd import binding as sil
+    cpu = torch.device("cpu")
+    good = torch.ones(8, dtype=torch.float32)
+    sil._check_col_scale(good, 8, cpu)
+    bad = [None, good.double(), torch.ones(9), torch.ones(16)[::2], torch.ones(8, 1).squeeze(1)[:7],
+           torch.ones(8, device="meta")]
+    for cs in bad:
+        with pytest.raises(ValueError):
+            sil._check_col_scale(cs, 8, cpu)

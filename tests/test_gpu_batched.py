@@ -25,7 +25,7 @@ def dev():
     return torch.device("cuda:0")
 
 
-# (N, D, K, metric, singletons, seed): every GEMM depth class (16, 24, 40, 72, 136), ragged N,
+# (N, D, K, metric, singletons, seed): every GEMM depth class (16, 24, 32, 48, 64, 96, 128), ragged N,
 # K from 2 to 300, both metrics, singleton clusters, rows fewer than one block
 MIXED = [
     (3_001, 3, 5, "sqeuclid", 1, 31),
@@ -76,9 +76,9 @@ def check_against_oracle(batch, expect, tag):
 
 CONFIGS = [
     dict(grid=512, grab=1, order="cost"),
-    dict(grid=256, grab=4, order="problem", rows_per_item={16: 256, 24: 256, 40: 256}),
+    dict(grid=256, grab=4, order="problem", rows_per_item={16: 256, 24: 256, 32: 256}),
     dict(grid=768, grab=2, order="cost", rows_per_item={24: 256}),
-    dict(grid=7, grab=64, order="problem", rows_per_item={16: 256, 40: 256}),
+    dict(grid=7, grab=64, order="problem", rows_per_item={16: 256, 32: 256}),
 ]
 
 

@@ -342,3 +342,22 @@ def test_device_errors(dev):
     assert sil.status(ws) == 0 and not math.isnan(S.item())
     with pytest.raises((ValueError, _lib.SilhouetteError)):
         sil.silhouette(X, lab, 1)
+
+
+def test_fp8_col_scale_refused_before_launch(dev):
+    # a host, strided, wrong-length or float64 col_scale is refused by the binding (a host pointer
+    # would reach the kernels otherwise); the output buffers are never touched
+    from paper_2303_14102_amd import binding as sil
+    b = wl.make_small(600, 8, 4, seed=77)
+    q, sc = wl.to_fp8_e4m3(b.X.to(dev))
+    lab = b.labels.to(dev)
+    wide = torch.ones(16, dtype=torch.float32, device=dev)
+    for cs in (sc.cpu(), wide[::2], wide[:7], sc.double()):
+        with pytest.raises(ValueError):
+            sil.silhouette(q, lab, 4, col_scale=cs)
+        with pytest.raises(ValueError):
+            sil.cluster_stats(q, lab, 4, col_scale=cs)
+        with pytest.raises(ValueError):
+            sil.silhouette_stream(q.cpu(), b.labels, 4, chunk_rows=256, col_scale=cs, device=dev)
+    s, S = sil.silhouette(q, lab, 4, col_scale=sc, check_status=True)
+    assert not math.isnan(S.item())
