@@ -5,8 +5,9 @@ GEMM+epilogue, reduction of S) over the resident synthetic workload, through the
 
 Default workload: blobs-50m-d128-k1000 (N=50,000,000, D=128, K=1000 Gaussian blobs), squared
 Euclidean, X stored bf16, bf16 MFMA with fp32 accumulation.  The fp32 form (X stored fp32, fp32
-MFMA) is timed beside it on the same points; |dS| between the two and against the FP64 oracle on
-sampled points is reported.  Prints one JSON line.
+MFMA) is timed beside it on the same points; |dS| between the two and against the whole FP64
+oracle (every point, on the host) is reported, with the copy and GEMM rates this GPU reaches on
+plain library work and the small workload's per-call latency.  Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -389,8 +390,13 @@ def parse():
     ap.add_argument("--x3-steps", type=int, default=10, help="steps of the BF16x3 comparison")
     ap.add_argument("--no-x3", action="store_true", help="skip the BF16x3 comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the fp32-form comparison")
-    ap.add_argument("--no-check", action="store_true", help="skip the oracle check on sampled points")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle check")
+    ap.add_argument("--check", default="full", choices=["full", "sampled"],
+                    help="full: every s_i and S against the whole FP64 oracle (about 2 minutes of "
+                         "host time at the default workload); sampled: 256 points")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the measured copy / GEMM peaks and the small workload's latency")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for the traffic counters)")
@@ -427,6 +433,86 @@ def timed_steps(fn, steps, warmup, torch):
     _lib.check(lib.silhouette_profile_end(ms, ctypes.byref(n)), "profile_end")
     total = start.elapsed_time(stop)
     return total / steps, [v / max(1, n.value) for v in ms], wall / steps
+
+
+def measured_peaks(torch, dev):
+    """What this GPU reaches on plain library work, beside the datasheet peaks: a 2 GiB
+    device-to-device copy (bytes read + written per second) and a bf16 8192^3 matrix product
+    (hipBLASLt through torch.matmul).  Measurement references only; the Silhouette path uses
+    neither."""
+    src = torch.empty(1 << 31, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    a = torch.randn(8192, 8192, device=dev).to(torch.bfloat16)
+    b = torch.randn(8192, 8192, device=dev).to(torch.bfloat16)
+
+    def best_ms(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    t_copy = best_ms(lambda: dst.copy_(src))
+    t_mm = best_ms(lambda: torch.matmul(a, b))
+    out = {"hbm_copy_GBps": 2 * src.numel() / (t_copy * 1e-3) / 1e9,
+           "bf16_gemm_TFLOPs": 2 * 8192 ** 3 / (t_mm * 1e-3) / 1e12,
+           "how": "best of 10: 2 GiB device copy (read + write bytes); bf16 8192^3 torch.matmul"}
+    del src, dst, a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def latency_c1(torch, dev):
+    """The small plain-method workload (N = 10,000, D = 8, K = 4, fp32): microseconds per call,
+    launched eagerly through the C ABI, and replayed from a captured graph of the same call."""
+    from paper_2303_14102_amd import binding as sil
+    from paper_2303_14102_amd import workloads as wl
+    spec = wl.WORKLOADS["blobs-10k-d8-k4"]
+    b = wl.make_blobs(spec, dev)
+    res = {"workload": spec.name}
+    for metric in ("sqeuclid", "cosine"):
+        ws = sil.new_workspace(spec.n, spec.d, spec.k, metric, torch.float32, 0, dev)
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            for _ in range(20):
+                sil.silhouette(b.X, b.labels, spec.k, metric, workspace=ws)
+            n = 200
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            side.synchronize()
+            t0 = time.perf_counter()
+            e0.record()
+            for _ in range(n):
+                sil.silhouette(b.X, b.labels, spec.k, metric, workspace=ws)
+            e1.record()
+            side.synchronize()
+            eager_wall = (time.perf_counter() - t0) / n * 1e6
+            eager = e0.elapsed_time(e1) / n * 1e3
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                sil.silhouette(b.X, b.labels, spec.k, metric, workspace=ws)
+            for _ in range(20):
+                g.replay()
+            side.synchronize()
+            e0.record()
+            for _ in range(n):
+                g.replay()
+            e1.record()
+            side.synchronize()
+            graph = e0.elapsed_time(e1) / n * 1e3
+        torch.cuda.current_stream(dev).wait_stream(side)
+        res[metric] = {"eager_us_per_call": eager, "eager_wall_us_per_call": eager_wall,
+                       "graph_replay_us_per_call": graph, "points_per_s_graph": spec.n / (graph * 1e-6)}
+        del g, ws
+    return res
 
 
 def cpu_baseline(spec, X_host_codes, labels_host, metric, col_scale, n_sample):
@@ -717,13 +803,56 @@ def main():
         log(f"fp32 form: {ms32:.3f} ms/step, S={S32.item():.10f}")
         del ws32
 
+    if not args.no_extras:
+        # what this machine reaches on plain library work, and the small workload's call latency
+        log("measured peaks: device copy and a bf16 library GEMM")
+        mp = measured_peaks(torch, dev)
+        out["measured_peaks"] = mp
+        if args.form != "f32":
+            out["roofline"]["frac_vs_measured_gemm"] = out["roofline"]["achieved"] * 1e12 / (
+                mp["bf16_gemm_TFLOPs"] * 1e12)
+        out["stats_pass"]["frac_vs_measured_copy"] = out["stats_pass"]["achieved_GBps"] / mp["hbm_copy_GBps"]
+        log(f"measured peaks: {mp}")
+        log("latency of the small workload: eager and graph-replayed calls")
+        out["latency_small"] = latency_c1(torch, dev)
+        log(f"latency: {out['latency_small']}")
+
     host_codes = None
     if not args.no_check or not args.no_cpu:
         host_codes = wl.host_codes(X)
         labels_host = labels.cpu().numpy()
         cs_host = None if col_scale is None else col_scale.cpu().numpy()
 
-    if not args.no_check:
+    if not args.no_check and args.check == "full":
+        import oracle
+        log(f"oracle check: the whole FP64 oracle over all {spec.n} rows")
+        t0 = time.perf_counter()
+        # the oracle's two passes (orc_silhouette's arithmetic), the second a chunk of rows at a
+        # time so that progress shows; S is the index-order sum of s_i over N, as it forms it
+        stats = oracle.cluster_stats(host_codes, labels_host, spec.k, ref_metric, col_scale=cs_host)
+        s_ref = np.empty(spec.n)
+        for i0 in range(0, spec.n, 5_000_000):
+            idx = np.arange(i0, min(spec.n, i0 + 5_000_000), dtype=np.int64)
+            s_ref[idx] = oracle.scores_at(host_codes, labels_host, spec.k, idx, stats, ref_metric,
+                                          col_scale=cs_host)[0]
+            log(f"oracle rows [{i0}, {idx[-1] + 1}): {time.perf_counter() - t0:.1f} s")
+        S_ref = float(np.cumsum(s_ref)[-1]) / spec.n
+        t_orc = time.perf_counter() - t0
+        s_all = s.cpu().numpy().astype(np.float64)
+        out["check"] = {"points": int(spec.n), "oracle": "whole FP64 oracle on the same stored input",
+                        "S_oracle": S_ref, "dS_vs_oracle": abs(S_form - S_ref),
+                        "max_abs_ds": float(np.abs(s_all - s_ref).max()),
+                        "S_vs_sum_of_s": abs(S_form - s_all.sum() / spec.n),
+                        "oracle_s": t_orc}
+        del s_all
+        if s3 is not None:
+            s3_all = s3.cpu().numpy().astype(np.float64)
+            out["bf16x3_form"]["dS_vs_oracle"] = abs(out["bf16x3_form"]["S"] - S_ref)
+            out["bf16x3_form"]["max_abs_ds"] = float(np.abs(s3_all - s_ref).max())
+            del s3_all
+        del s_ref
+        log(f"check: {out['check']}")
+    elif not args.no_check:
         import oracle
         log("oracle check on sampled points (FP64 statistics over the full data)")
         t0 = time.perf_counter()

@@ -76,6 +76,44 @@ def bound_from_stats(form, products, metric, centre, rows, stats, a, b, root=Fal
     return 2 * (da + db) / np.maximum(np.maximum(a, b), 1e-30) + 4 * U32
 
 
+def sqeuclid_bounds_all_rows(form, products_list, codes, cs, stats, a, b, chunk=1 << 21):
+    """bound_from_stats for the centred squared Euclidean forms over every row of a large data
+    set, for several product counts at once: the two row norms it needs (|x - m| and |x|) are
+    formed a chunk at a time with torch on the host, in binary64."""
+    count, V, psi = stats
+    cnt = np.asarray(count, np.float64)
+    ne = cnt > 0
+    mu = V[ne] / cnt[ne, None]
+    m = V.sum(0) / cnt.sum()
+    mup = mu - m
+    var = psi[ne] / cnt[ne] - (mu * mu).sum(1)
+    cmax0 = ((mup * mup).sum(1) + var).max()
+    mupmax = np.linalg.norm(mup, axis=1).max()
+    D = V.shape[1]
+    N = len(a)
+    nx = np.empty(N)
+    nxc = np.empty(N)
+    mt = torch.from_numpy(m)
+    for i0 in range(0, N, chunk):
+        i1 = min(N, i0 + chunk)
+        rows = torch.from_numpy(np.ascontiguousarray(dequantised(codes[i0:i1], cs))).double()
+        nxc[i0:i1] = torch.linalg.vector_norm(rows, dim=1).numpy()
+        nx[i0:i1] = torch.linalg.vector_norm(rows - mt, dim=1).numpy()
+    a = np.asarray(a)
+    b = np.asarray(b)
+    da = 4 * U32 * (D + 8) * (a + np.abs(a))
+    den = np.maximum(np.maximum(a, b), 1e-30)
+    out = {}
+    for products in products_list:
+        eps = cross_term_eps(form, products, "sqeuclid", True, D)
+        folded = form in ("bf16", "fp8") and products == 2
+        ng = nxc if folded else nx  # norm of the GEMM operand
+        cmax = cmax0 + (2 * np.abs(mup @ m).max() if folded else 0.0)
+        db = 2 * eps * ng * mupmax + 4 * U32 * (nx ** 2 + ng ** 2 + cmax)
+        out[products] = 2 * (da + db) / den + 4 * U32
+    return out
+
+
 def plain_stats(X, labels, K, metric):
     metric = "sqeuclid" if metric == "euclid_approx" else metric
     """count, V, psi of a small data set with numpy (for the bound only)."""

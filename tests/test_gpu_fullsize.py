@@ -6,11 +6,15 @@ configuration the benchmark times.
     few sampled points;
   - blobs-50m-d128-k1000 (N = 5e7, D = 128, K = 1000): bf16 (two products on the exact x, as the
     benchmark runs it, and BF16x3), fp8 e4m3 and fp32 storage.
-    The whole oracle is too slow here, so: cluster statistics over all rows against the oracle's,
-    s_i on 256 sampled points against the oracle's linear form (FP64 statistics of all rows),
-    s_i on 4 of them against the quadratic definition over all 5e7 rows, and S against the
-    FP64 mean of the returned s_i (a property that holds at any size).
+    Squared Euclidean on the bf16 codes (both forms) and on the fp32 values: every s_i and S
+    against the whole FP64 oracle over all 5e7 rows (about two minutes of host time per input).
+    Every form: cluster statistics over all rows against the oracle's, s_i on 256 sampled
+    points against the oracle's linear form (FP64 statistics of all rows), s_i on 4 of them
+    against the quadratic definition over all 5e7 rows, and S against the FP64 mean of the
+    returned s_i (a property that holds at any size).
 """
+
+import time
 
 import numpy as np
 import pytest
@@ -18,7 +22,8 @@ import torch
 
 import oracle
 from paper_2303_14102_amd import workloads as wl
-from parity_helpers import TOL_S_MEAN, bound_from_stats, dequantised, per_point_bound
+from parity_helpers import (TOL_S_MEAN, bound_from_stats, dequantised, per_point_bound,
+                            sqeuclid_bounds_all_rows)
 
 pytestmark = pytest.mark.gpu
 
@@ -138,3 +143,47 @@ def test_precision_forms_at_scale(dev, big, metric, form, products):
         print(f"  |S - S(fp32 form)|={abs(S.item() - S32):.2e}", flush=True)
         if form == "bf16":
             assert abs(S.item() - S32) <= TOL_S_MEAN[form]
+
+
+@pytest.mark.timeout(1500)
+@pytest.mark.parametrize("form", ["bf16", "f32"])
+def test_headline_every_point_against_whole_oracle(dev, big, form):
+    """Squared Euclidean at N = 5e7, D = 128, K = 1000: the GPU's s_i and S (bf16 codes with two
+    products on the exact x and with BF16x3; fp32 values with fp32 MFMA) against the whole FP64
+    oracle on the same stored input.  S within 1e-4 (bf16) / 1e-6 (fp32) of the oracle's S, every
+    s_i within its bound."""
+    from paper_2303_14102_amd import binding as sil
+    spec, b = big
+    Xd = wl.to_bf16(b.X) if form == "bf16" else b.X
+    runs = {}
+    for products in ((2, 3) if form == "bf16" else (0,)):
+        print(f"[full] {spec.name} whole oracle: form={form} products={products}", flush=True)
+        s, S = sil.silhouette(Xd, b.labels, spec.k, "sqeuclid", products=products, check_status=True)
+        runs[products] = (s.cpu().numpy().astype(np.float64), S.item())
+        del s
+    codes = wl.host_codes(Xd)
+    if Xd is not b.X:
+        del Xd
+    lab_h = b.labels.cpu().numpy()
+    # the oracle's two passes, the second a chunk of rows at a time (orc_silhouette does the same
+    # over all rows at once; S is its index-order sum of s_i over N)
+    t0 = time.perf_counter()
+    stats = oracle.cluster_stats(codes, lab_h, spec.k, "sqeuclid")
+    s_ref, a, bb = np.empty(spec.n), np.empty(spec.n), np.empty(spec.n)
+    step = 5_000_000
+    for i0 in range(0, spec.n, step):
+        idx = np.arange(i0, min(spec.n, i0 + step), dtype=np.int64)
+        s_ref[idx], a[idx], bb[idx], _ = oracle.scores_at(codes, lab_h, spec.k, idx, stats, "sqeuclid")
+        print(f"  oracle rows [{i0}, {idx[-1] + 1}): {time.perf_counter() - t0:.1f} s", flush=True)
+    S_ref = float(np.cumsum(s_ref)[-1]) / spec.n
+    print(f"  oracle over {spec.n} rows: {time.perf_counter() - t0:.1f} s on {oracle.num_threads()} threads",
+          flush=True)
+    bounds = sqeuclid_bounds_all_rows(form, list(runs), codes, None, stats, a, bb)
+    for products, (s, S) in runs.items():
+        bound = bounds[products]
+        ds = np.abs(s - s_ref)
+        print(f"  form={form} products={products}: S={S:.12f} oracle={S_ref:.12f} |dS|={abs(S - S_ref):.2e} "
+              f"max|ds|={ds.max():.2e} mean|ds|={ds.mean():.2e} max(|ds|/bound)={(ds / bound).max():.4f}",
+              flush=True)
+        assert np.all(ds <= bound), f"point {int((ds / bound).argmax())} exceeds its bound"
+        assert abs(S - S_ref) <= TOL_S_MEAN[form]

@@ -361,3 +361,52 @@ def test_fp8_col_scale_refused_before_launch(dev):
             sil.silhouette_stream(q.cpu(), b.labels, 4, chunk_rows=256, col_scale=cs, device=dev)
     s, S = sil.silhouette(q, lab, 4, col_scale=sc, check_status=True)
     assert not math.isnan(S.item())
+
+
+@pytest.mark.parametrize("form,products", [("f32", 0), ("bf16", 2)])
+def test_single_call_graph_replay(dev, form, products):
+    """One silhouette_sqeuclid call captured into a graph (it launches kernels only) and replayed:
+    every replay matches the oracle, with eager library work and a change of X's contents
+    between replays (the graph reads X where it lies, so a replay after the change gives the
+    Silhouette of the new points)."""
+    from paper_2303_14102_amd import binding as sil
+    n, d, k = 20_011, 48, 37
+    b1 = wl.make_small(n, d, k, seed=91, singletons=2)
+    b2 = wl.make_small(n, d, k, seed=92, singletons=1)
+    lab = b1.labels.to(dev)
+    X1, _, codes1 = storage(b1.X.to(dev), form)
+    X2, _, codes2 = storage(b2.X.to(dev), form)
+    lab_h = b1.labels.numpy()
+    refs = []
+    for codes in (codes1, codes2):
+        s_ref, S_ref, a, bb, _ = oracle.silhouette(codes, lab_h, k, "sqeuclid", details=True)
+        refs.append((s_ref, S_ref, per_point_bound(form, products, "sqeuclid", True,
+                                                   dequantised(codes, None), lab_h, k, a, bb)))
+    X = X1.clone()
+    ws = sil.new_workspace(n, d, k, "sqeuclid", X.dtype, 0, dev)
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        sil.silhouette(X, lab, k, products=products, workspace=ws)  # eager warm-up
+    side.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        s_g, S_g = sil.silhouette(X, lab, k, products=products, workspace=ws)
+    torch.cuda.current_stream(dev).wait_stream(side)
+    ws_other = sil.new_workspace(n, d, k, "cosine", X.dtype, 0, dev)
+    for rep, which in enumerate((0, 0, 1, 1, 0)):
+        X.copy_(X1 if which == 0 else X2)
+        s_g.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert sil.status(ws) == 0
+        s_ref, S_ref, bound = refs[which]
+        s = s_g.cpu().numpy().astype(np.float64)
+        ds = np.abs(s - s_ref)
+        print(f"  replay {rep} (X{which + 1}): S={S_g.item():.10f} ref={S_ref:.10f} max|ds|={ds.max():.2e}",
+              flush=True)
+        assert np.all(ds <= bound), f"replay {rep}: point {int((ds / bound).argmax())}"
+        assert abs(S_g.item() - S_ref) <= TOL_S_MEAN[form]
+        # eager library work between replays, on another workspace
+        sil.silhouette(X2, lab, k, "cosine", products=products, workspace=ws_other, check_status=True)
