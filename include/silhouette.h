@@ -47,7 +47,8 @@ typedef enum {
   SIL_E_NONFINITE = -6,    /* (device) NaN or infinity in X */
   SIL_E_WORKSPACE = -7,    /* workspace NULL, misaligned or smaller than required */
   SIL_E_HIP = -8,          /* a HIP runtime call failed */
-  SIL_E_DOMAIN = -9        /* (device) an entry outside the distance's domain (KL: not > 0) */
+  SIL_E_DOMAIN = -9,       /* (device) an entry outside the distance's domain (KL: not > 0) */
+  SIL_E_SCRATCH = -10      /* the problem's workspace exceeds SIL_NOALLOC_SCRATCH_BYTES */
 } sil_status;
 
 /* Storage of X.  SIL_BF16: bfloat16 values.  SIL_FP8_E4M3: OCP e4m3fn codes, element (i,l)
@@ -116,6 +117,29 @@ int silhouette_sqeuclid(const void* X, int32_t dtype, const float* col_scale,
 int silhouette_cosine(const void* X, int32_t dtype, const float* col_scale, const int32_t* labels,
                       int64_t N, int32_t D, int32_t K, int32_t products, int32_t flags, float* s,
                       double* S, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * For callers that cannot allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): silhouette_sqeuclid without a caller workspace.  The
+ * library keeps a static device array of SIL_NOALLOC_SCRATCH_BYTES bytes on every GPU it runs
+ * on (held until the process ends) and uses it as the workspace; this call allocates and frees
+ * nothing.
+ *   status   device, int32 [1], or NULL: receives the first device-detected error (SIL_OK if
+ *            none), as silhouette_status would report it for a workspace call
+ * Other arguments, results and errors as silhouette_sqeuclid.  A problem whose workspace
+ * (silhouette_workspace_bytes with the same arguments) exceeds SIL_NOALLOC_SCRATCH_BYTES returns
+ * SIL_E_SCRATCH at once and launches nothing; SIL_FLAG_SAVE_FOR_GRAD returns SIL_E_ARG (the
+ * backward needs the forward's workspace).  Every call on one GPU shares that GPU's scratch:
+ * calls that overlap on one GPU (different streams, or host threads) race and must be
+ * serialised by the caller; calls in one stream are ordered.  Each call clears the parts of the
+ * scratch that must start at zero.  The first call on a device looks up that device's scratch
+ * address (a host-side query, no allocation): make it outside graph capture.
+ */
+#define SIL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int silhouette_sqeuclid_noalloc(const void* X, int32_t dtype, const float* col_scale,
+                                const int32_t* labels, int64_t N, int32_t D, int32_t K,
+                                int32_t products, int32_t flags, float* s, double* S,
+                                int32_t* status, void* stream);
 
 /*
  * Gradient dS/dX of the squared-Euclidean Silhouette with the labels held fixed (not in the

@@ -17,8 +17,9 @@ SIL_OK = 0
 STATUS = {
     0: "SIL_OK", -1: "SIL_E_ARG", -2: "SIL_E_DTYPE", -3: "SIL_E_LABEL", -4: "SIL_E_FEW_CLUSTERS",
     -5: "SIL_E_ZERO_NORM", -6: "SIL_E_NONFINITE", -7: "SIL_E_WORKSPACE", -8: "SIL_E_HIP",
-    -9: "SIL_E_DOMAIN",
+    -9: "SIL_E_DOMAIN", -10: "SIL_E_SCRATCH",
 }
+SIL_NOALLOC_SCRATCH_BYTES = 64 << 20
 SIL_F32, SIL_BF16, SIL_FP8_E4M3 = 0, 1, 2
 SIL_SQEUCLID, SIL_COSINE, SIL_KL = 0, 1, 2
 SIL_FLAG_NO_CENTRE = 1 << 0
@@ -30,6 +31,7 @@ _P, _I32, _I64, _SZ, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctype
 SIGNATURES = {
     "silhouette_workspace_bytes": (_SZ, [_I64, _I32, _I32, _I32, _I32, _I32]),
     "silhouette_sqeuclid": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "silhouette_sqeuclid_noalloc": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
     "silhouette_cosine": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "silhouette_kl": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "silhouette_cluster_stats": (ctypes.c_int, [_P, _I32, _P, _P, _I64, _I32, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),

@@ -100,6 +100,30 @@ def silhouette(X: torch.Tensor, labels: torch.Tensor, K: int, metric: str = "sqe
     return s, S
 
 
+def sqeuclid_noalloc(X: torch.Tensor, labels: torch.Tensor, K: int, *, products: int = 0,
+                     centre: bool = True, col_scale: Optional[torch.Tensor] = None,
+                     s: Optional[torch.Tensor] = None, S: Optional[torch.Tensor] = None,
+                     status: Optional[torch.Tensor] = None):
+    """silhouette_sqeuclid_noalloc: the squared Euclidean Silhouette with the library's static
+    per-GPU scratch as the workspace.  s (float32 [N] or None), S (float64 0-d) and status (int32
+    [1] or None) are written in place when given (allocated here otherwise), so that a caller that
+    must not allocate passes all three."""
+    _check_inputs(X, labels, col_scale)
+    N, D = X.shape
+    if S is None:
+        S = torch.empty((), dtype=torch.float64, device=X.device)
+    for t, dt, shape in ((s, torch.float32, (N,)), (S, torch.float64, ()), (status, torch.int32, (1,))):
+        if t is not None and (t.dtype != dt or tuple(t.shape) != shape or t.device != X.device
+                              or not t.is_contiguous()):
+            raise ValueError(f"output must be a contiguous {dt} tensor of shape {shape} on X's device")
+    flags = 0 if centre else L.SIL_FLAG_NO_CENTRE
+    rc = L.load().silhouette_sqeuclid_noalloc(_ptr(X), _dtype_code(X), _ptr(col_scale), _ptr(labels), N, D,
+                                              int(K), int(products), flags, _ptr(s), _ptr(S), _ptr(status),
+                                              _stream(X.device))
+    L.check(rc, "silhouette_sqeuclid_noalloc")
+    return s, S, status
+
+
 def cluster_stats(X: torch.Tensor, labels: torch.Tensor, K: int, metric: str = "sqeuclid", *,
                   col_scale: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None):
     """(count int32 [K], V float64 [K, D], psi float64 [K]) from one pass over X."""

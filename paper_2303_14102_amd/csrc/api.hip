@@ -117,9 +117,9 @@ static void prof_record(int call, int point, hipStream_t st) {
   if (g_prof.on && call >= 0) (void)hipEventRecord(g_prof.ev[call * 5 + point], st);
 }
 
-static int forward(int32_t metric, const void* X, int32_t dtype, const float* col_scale,
-                   const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t products,
-                   int32_t flags, float* s, double* S, void* ws, size_t ws_bytes, void* stream) {
+int run_forward(int32_t metric, const void* X, int32_t dtype, const float* col_scale,
+                const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t products,
+                int32_t flags, float* s, double* S, void* ws, size_t ws_bytes, void* stream) {
   WsLayout L;
   int rc = check_common(X, dtype, col_scale, labels, N, D, K, metric, ws, ws_bytes, flags, &L);
   if (rc) return rc;
@@ -247,21 +247,21 @@ int silhouette_sqeuclid(const void* X, int32_t dtype, const float* col_scale,
                         const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t products,
                         int32_t flags, float* s, double* S, void* ws, size_t ws_bytes,
                         void* stream) {
-  return forward(SIL_SQEUCLID, X, dtype, col_scale, labels, N, D, K, products, flags, s, S, ws,
+  return run_forward(SIL_SQEUCLID, X, dtype, col_scale, labels, N, D, K, products, flags, s, S, ws,
                  ws_bytes, stream);
 }
 
 int silhouette_kl(const void* X, int32_t dtype, const float* col_scale, const int32_t* labels,
                   int64_t N, int32_t D, int32_t K, int32_t products, int32_t flags, float* s,
                   double* S, void* ws, size_t ws_bytes, void* stream) {
-  return forward(SIL_KL, X, dtype, col_scale, labels, N, D, K, products,
+  return run_forward(SIL_KL, X, dtype, col_scale, labels, N, D, K, products,
                  flags & ~SIL_FLAG_NO_CENTRE, s, S, ws, ws_bytes, stream);
 }
 
 int silhouette_cosine(const void* X, int32_t dtype, const float* col_scale, const int32_t* labels,
                       int64_t N, int32_t D, int32_t K, int32_t products, int32_t flags, float* s,
                       double* S, void* ws, size_t ws_bytes, void* stream) {
-  return forward(SIL_COSINE, X, dtype, col_scale, labels, N, D, K, products,
+  return run_forward(SIL_COSINE, X, dtype, col_scale, labels, N, D, K, products,
                  flags & ~SIL_FLAG_NO_CENTRE, s, S, ws, ws_bytes, stream);
 }
 
@@ -359,6 +359,7 @@ const char* silhouette_strerror(int status) {
     case SIL_E_WORKSPACE: return "workspace missing, misaligned or too small";
     case SIL_E_HIP: return "a HIP runtime call failed";
     case SIL_E_DOMAIN: return "an entry lies outside the distance's domain (KL needs positive entries)";
+    case SIL_E_SCRATCH: return "problem needs more than the static scratch of the no-allocation entry point";
     default: return "unknown status";
   }
 }

@@ -164,6 +164,12 @@ hipError_t launch_reduce(const Problem& p, const WsLayout& L, const WsPtrs& w, h
 hipError_t launch_copy_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, int32_t* count,
                              double* V, double* psi, hipStream_t st);
 
+// The forward entry points' common body: argument checks against the workspace, then the four
+// phases (statistics, tables, fused GEMM + epilogue, reduction) on `stream`.
+int run_forward(int32_t metric, const void* X, int32_t dtype, const float* col_scale,
+                const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t products,
+                int32_t flags, float* s, double* S, void* ws, size_t ws_bytes, void* stream);
+
 // rows per workgroup of the fused kernel for this problem (host and workspace sizing)
 int main_rows_per_block(int dtype, int DPX, int products);
 

@@ -156,7 +156,7 @@ def test_kl_host_checks(lib):
 
 
 def test_strerror(lib):
-    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, 99):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, 99):
         assert isinstance(lib.silhouette_strerror(code), bytes)
 
 
