@@ -72,7 +72,10 @@ enum {
    * not the exact Euclidean Silhouette (by Jensen's inequality each root is at least the mean
    * Euclidean distance; they agree when all of a point's distances to a cluster are equal).
    * SIL_E_ARG with the cosine entry point or with SIL_FLAG_SAVE_FOR_GRAD. */
-  SIL_FLAG_EUCLID_APPROX = 1 << 2
+  SIL_FLAG_EUCLID_APPROX = 1 << 2,
+  /* Squared Euclidean with bf16 storage and two products: run the plain two-product sweep for
+   * every point instead of the one-product screen (see silhouette_sqeuclid). */
+  SIL_FLAG_NO_SCREEN = 1 << 3
 };
 
 /*
@@ -98,6 +101,15 @@ size_t silhouette_workspace_bytes(int64_t N, int32_t D, int32_t K, int32_t metri
  *              mean.  That matches 3 while |m| is small against the data's spread, at two
  *              thirds of the MFMA work.  For the uncentred squared Euclidean distance and for
  *              KL, 3 runs as 2: x has no low half, so the results are the same.
+ *              Squared Euclidean with bf16 storage and 2 (D <= 128): a one-product screen finds
+ *              each point's closest other cluster first.  x is exact in fp16 and the cluster-side
+ *              table is rounded to fp16, so an fp16 MFMA sweep gives every point-to-cluster
+ *              value with a known per-point error bound; when the best value is ahead of the
+ *              second by more than twice that bound, the closest cluster is known exactly and
+ *              b_i is scored for it alone in fp32; every other point (and every point whose
+ *              values fp16 cannot hold exactly) gets the two-product sweep above.  The results
+ *              stay within the two-product form's accuracy at about half its MFMA work.
+ *              SIL_FLAG_NO_SCREEN runs the two-product sweep for every point.
  *   flags      SIL_FLAG_* bits
  *   s          device, float32 [N], or NULL
  *   S          device, float64 [1]

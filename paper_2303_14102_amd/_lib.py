@@ -25,6 +25,7 @@ SIL_SQEUCLID, SIL_COSINE, SIL_KL = 0, 1, 2
 SIL_FLAG_NO_CENTRE = 1 << 0
 SIL_FLAG_SAVE_FOR_GRAD = 1 << 1
 SIL_FLAG_EUCLID_APPROX = 1 << 2
+SIL_FLAG_NO_SCREEN = 1 << 3
 
 # every symbol include/silhouette.h declares, with its ctypes signature
 _P, _I32, _I64, _SZ, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double

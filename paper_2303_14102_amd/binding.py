@@ -242,6 +242,12 @@ def silhouette_stream(X_host: torch.Tensor, labels_host: torch.Tensor, K: int, m
     return s, S
 
 
+def fallback_rows(workspace: torch.Tensor) -> int:
+    """Rows the one-product screen of the last call on `workspace` left to the two-product
+    kernel (header word 40; 0 for calls without the screen).  Synchronises the device."""
+    return int(workspace[160:164].view(torch.int32).item())
+
+
 def status(workspace: torch.Tensor) -> int:
     """First device-detected error of the last call on this workspace (waits for the stream)."""
     return L.load().silhouette_status(_ptr(workspace), _stream(workspace.device))

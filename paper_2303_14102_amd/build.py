@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsilhouette.so")
 SOURCES = ["main_batched.hip", "main_f32.hip", "main_bf16.hip", "main_fp8.hip", "main_assign.hip",
            "api.hip", "stats.hip", "finalize.hip", "main.hip", "backward.hip", "batched.hip",
-           "stream.hip", "mahalanobis.hip", "noalloc.hip"]
+           "stream.hip", "mahalanobis.hip", "noalloc.hip", "screen.hip",
+           "main_screen.hip"]
 ARCH = os.environ.get("SIL_OFFLOAD_ARCH", "gfx950")
 
 

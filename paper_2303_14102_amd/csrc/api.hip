@@ -53,6 +53,14 @@ WsLayout make_layout(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dt
                      ? static_cast<size_t>(bwd_accum_workgroups(N)) * KW * 8
                      : 0);
   L.gAB = take(save ? KW * 8 : 0);
+  // the one-product screen's regions whenever a call with this shape may take it
+  const bool scr = screen_applies(metric, dtype, L.DPX, 2, flags);
+  L.nsblk = scr ? ceil_div(N, screen_rows_per_block()) : 0;
+  L.stab = take(scr ? static_cast<size_t>(L.Kpad) * screen_stride(L.DPX) * 2 : 0);
+  L.c64 = take(scr ? static_cast<size_t>(L.Kpad) * 8 : 0);
+  L.fblist = take(scr ? static_cast<size_t>(N) * 4 : 0);
+  // fallback workgroups take at least 128 list entries each
+  L.fbpart = take(scr ? static_cast<size_t>(ceil_div(N, kMainWaves * 32)) * 8 : 0);
   L.total = o;
   return L;
 }
@@ -83,6 +91,10 @@ WsPtrs carve(const WsLayout& L, void* ws) {
   w.save_n = reinterpret_cast<int32_t*>(b + L.save_n);
   w.gpart = reinterpret_cast<double*>(b + L.gpart);
   w.gAB = reinterpret_cast<double*>(b + L.gAB);
+  w.stab = b + L.stab;
+  w.c64 = reinterpret_cast<double*>(b + L.c64);
+  w.fblist = reinterpret_cast<int32_t*>(b + L.fblist);
+  w.fbpart = reinterpret_cast<double*>(b + L.fbpart);
   return w;
 }
 
@@ -136,9 +148,12 @@ int run_forward(int32_t metric, const void* X, int32_t dtype, const float* col_s
   const WsPtrs w = carve(L, ws);
   if ((flags & SIL_FLAG_SAVE_FOR_GRAD) && dtype != SIL_F32) return SIL_E_DTYPE;
   products = run_products(metric, dtype, flags, products);
-  const int64_t nblocks = ceil_div(N, main_rows_per_block(dtype, L.DPX, products));
+  const int screen = screen_applies(metric, dtype, L.DPX, products, flags) ? 1 : 0;
+  const int64_t nblocks =
+      screen ? L.nsblk : ceil_div(N, main_rows_per_block(dtype, L.DPX, products));
   Problem p{X, col_scale, labels, N, D, L.DPX, K, L.Kpad, dtype, metric, products, flags, s, S,
             nblocks};
+  p.screen = screen;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int call = g_prof.on && g_prof.used < g_prof.cap ? g_prof.used++ : -1;
   prof_record(call, 0, st);

@@ -82,7 +82,8 @@ __device__ __forceinline__ void finalize_body(
     const double* __restrict__ psi, const double* __restrict__ gmean, int32_t K, int32_t Kpad,
     int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ ctab,
     float* __restrict__ atab, float* __restrict__ avec, float* __restrict__ ascale, int with_var,
-    const float* __restrict__ mvec, int fold, const float* __restrict__ tscale, int64_t bid) {
+    const float* __restrict__ mvec, int fold, const float* __restrict__ tscale,
+    double* __restrict__ c64, double* __restrict__ smax, int64_t bid) {
   constexpr double ALPHA = METRIC == SIL_SQEUCLID ? -2.0 : -1.0;
   const int lane = threadIdx.x & 63;
   const int32_t k = static_cast<int32_t>(bid) * 4 + (threadIdx.x >> 6);
@@ -95,7 +96,7 @@ __device__ __forceinline__ void finalize_body(
   const int64_t arow = static_cast<int64_t>(k) * DPX; // a-path row
   const int32_t n = k < K ? count[k] : 0;
   const double dn = static_cast<double>(n);
-  double mu2 = 0.0, muc2 = 0.0, mdot = 0.0;
+  double mu2 = 0.0, muc2 = 0.0, mdot = 0.0, gmax = 0.0;
   for (int r = 0; r < nrep; ++r) {
     const int l = lane + 64 * r;
     if (l >= RS) break;
@@ -109,6 +110,7 @@ __device__ __forceinline__ void finalize_body(
     if (fold && l < D) mdot = fma(static_cast<double>(mvec[l]), muc, mdot);
     double g = ALPHA * muc;  // exact scaling
     if (tscale && l < D) g *= static_cast<double>(tscale[l]);
+    gmax = fmax(gmax, fabs(g));
     if (BF16TAB) {
       const uint16_t hi = f32_to_bf16_rne(static_cast<float>(g));
       bthi[brow + l] = hi;
@@ -121,6 +123,8 @@ __device__ __forceinline__ void finalize_body(
   mu2 = wave_sum(mu2);
   muc2 = wave_sum(muc2);
   if (fold) mdot = wave_sum(mdot);
+  if (smax)
+    for (int off = 1; off < 64; off <<= 1) gmax = fmax(gmax, __shfl_xor(gmax, off, 64));
   if (lane == 0) {
     double c = kEmptyC, av = 0.0;
     if (n > 0) {
@@ -142,6 +146,11 @@ __device__ __forceinline__ void finalize_body(
       }
     }
     ctab[k] = static_cast<float>(c);
+    if (c64) c64[k] = c;
+    if (smax) {  // the screen table's scale: largest entry and constant (see screen.hip)
+      smax[0] = n > 0 ? gmax : 0.0;
+      smax[1] = n > 0 ? fabs(c) : 0.0;
+    }
     if (k < K) {
       avec[k] = static_cast<float>(av);
       ascale[k] = n >= 2 ? static_cast<float>(dn / (dn - 1.0)) : 0.0f;
@@ -155,9 +164,29 @@ __global__ __launch_bounds__(256) void k_finalize(
     const double* __restrict__ psi, const double* __restrict__ gmean, int32_t K, int32_t Kpad,
     int32_t D, int32_t DPX, int32_t RS, void* __restrict__ btab, float* __restrict__ ctab,
     float* __restrict__ atab, float* __restrict__ avec, float* __restrict__ ascale, int with_var,
-    const float* __restrict__ mvec, int fold, const float* __restrict__ tscale) {
+    const float* __restrict__ mvec, int fold, const float* __restrict__ tscale,
+    int32_t* __restrict__ shdr, double* __restrict__ c64) {
+  // shdr (the one-product screen): the workgroup's largest table entry and constant raise the
+  // header's slots (one atomic each per workgroup)
+  __shared__ double red[4][2];
+  const int wave = threadIdx.x >> 6;
+  red[wave][0] = 0.0;
+  red[wave][1] = 0.0;
   finalize_body<METRIC, BF16TAB>(count, V, psi, gmean, K, Kpad, D, DPX, RS, btab, ctab, atab,
-                                 avec, ascale, with_var, mvec, fold, tscale, blockIdx.x);
+                                 avec, ascale, with_var, mvec, fold, tscale, c64,
+                                 shdr ? red[wave] : nullptr, blockIdx.x);
+  if (!shdr) return;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0, c = 0.0;
+    for (int w = 0; w < 4; ++w) {
+      t = fmax(t, red[w][0]);
+      c = fmax(c, red[w][1]);
+    }
+    unsigned long long* slot = reinterpret_cast<unsigned long long*>(shdr + kHdrScreenWord);
+    atomicMax(slot + SC_TMAX, static_cast<unsigned long long>(__double_as_longlong(t)));
+    atomicMax(slot + SC_CMAX, static_cast<unsigned long long>(__double_as_longlong(c)));
+  }
 }
 
 hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
@@ -174,7 +203,8 @@ hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w,
 #define SIL_FIN(MT, BF)                                                                        \
   k_finalize<MT, BF><<<nb, 256, 0, st>>>(w.count, w.V, w.psi, w.gmean, p.K, p.Kpad, p.D, p.DPX, \
                                          table_stride(p.DPX, p.dtype), w.btab, w.ctab, w.atab,  \
-                                         w.avec, w.ascale, p.assign ? 0 : 1, w.mvec, fold, tscale)
+                                         w.avec, w.ascale, p.assign ? 0 : 1, w.mvec, fold, tscale, \
+                                         p.screen ? w.hdr : nullptr, p.screen ? w.c64 : nullptr)
   if (p.metric == SIL_SQEUCLID) {
     if (bf) SIL_FIN(SIL_SQEUCLID, true);
     else SIL_FIN(SIL_SQEUCLID, false);
@@ -186,7 +216,7 @@ hipError_t launch_finalize(const Problem& p, const WsLayout& L, const WsPtrs& w,
     else SIL_FIN(SIL_COSINE, false);
   }
 #undef SIL_FIN
-  (void)L;
+  if (p.screen) return launch_screen_table(p, L, w, st);
   return hipGetLastError();
 }
 
@@ -217,11 +247,11 @@ __global__ __launch_bounds__(256) void kb_fin(BatchDev b) {
   if (q.metric == SIL_SQEUCLID)
     finalize_body<SIL_SQEUCLID, false>(q.count, q.V, q.psi, q.gmean, q.K, q.Kpad, q.D, q.DPX, RS,
                                        q.btab, q.ctab, q.atab, q.avec, q.ascale, 1, nullptr, 0,
-                                       nullptr, it);
+                                       nullptr, nullptr, nullptr, it);
   else
     finalize_body<SIL_COSINE, false>(q.count, q.V, q.psi, q.gmean, q.K, q.Kpad, q.D, q.DPX, RS,
                                      q.btab, q.ctab, q.atab, q.avec, q.ascale, 1, nullptr, 0,
-                                     nullptr, it);
+                                     nullptr, nullptr, nullptr, it);
 }
 
 hipError_t launch_finalize_batched(const BatchLaunch& b, hipStream_t st) {

@@ -34,20 +34,25 @@ __global__ __launch_bounds__(1024) void k_reduce1(const double* __restrict__ bpa
 }
 
 // mean: S = sum / N (the Silhouette); otherwise the sum itself (the K-means inertia)
+// extra (may be NULL): one more partial sum, added last (the screen's fallback rows)
 __device__ __forceinline__ void reduce2_body(const double* __restrict__ part, int n, int64_t N,
                                              const int32_t* __restrict__ hdr,
-                                             double* __restrict__ S, int mean) {
+                                             double* __restrict__ S, int mean,
+                                             const double* __restrict__ extra = nullptr) {
   __shared__ double sh[1024];
   const double v = static_cast<int>(threadIdx.x) < n ? part[threadIdx.x] : 0.0;
-  const double tot = block_sum_1024(v, sh);
-  if (threadIdx.x == 0)
+  double tot = block_sum_1024(v, sh);
+  if (threadIdx.x == 0) {
+    if (extra) tot += *extra;
     *S = hdr[0] != 0 ? __builtin_nan("") : (mean ? tot / static_cast<double>(N) : tot);
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_reduce2(const double* __restrict__ part, int n,
                                                   int64_t N, const int32_t* __restrict__ hdr,
-                                                  double* __restrict__ S, int mean) {
-  reduce2_body(part, n, N, hdr, S, mean);
+                                                  double* __restrict__ S, int mean,
+                                                  const double* __restrict__ extra) {
+  reduce2_body(part, n, N, hdr, S, mean, extra);
 }
 
 __device__ __forceinline__ void poison_body(const int32_t* __restrict__ hdr, float* __restrict__ s,
@@ -77,7 +82,7 @@ int main_rows_per_block(int dtype, int DPX, int products) {
 }
 
 hipError_t launch_main(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
-  (void)L;
+  if (p.screen) return launch_screen_main(p, L, w, st);
   MainArgs m;
   m.X = p.X;
   m.col_scale = p.col_scale;
@@ -130,7 +135,10 @@ hipError_t launch_reduce(const Problem& p, const WsLayout& L, const WsPtrs& w, h
   int32_t n1;
   reduce_split(p.nblocks, &chunk, &n1);
   k_reduce1<<<static_cast<unsigned>(n1), 1024, 0, st>>>(w.bpart, p.nblocks, chunk, w.bpart2);
-  k_reduce2<<<1, 1024, 0, st>>>(w.bpart2, n1, p.N, w.hdr, p.S, (p.assign || p.reduce_sum) ? 0 : 1);
+  const double* extra =
+      p.screen ? reinterpret_cast<const double*>(w.hdr + kHdrFallbackSumWord) : nullptr;
+  k_reduce2<<<1, 1024, 0, st>>>(w.bpart2, n1, p.N, w.hdr, p.S, (p.assign || p.reduce_sum) ? 0 : 1,
+                                extra);
   if (p.s) k_poison<<<1024, 256, 0, st>>>(w.hdr, p.s, p.N);
   if (p.labels_out) k_poison_labels<<<1024, 256, 0, st>>>(w.hdr, p.labels_out, p.N);
   return hipGetLastError();

@@ -70,6 +70,9 @@ struct MainArgs {
   // mean's id goes to labels_out[row] and the squared distance to it into the block sum
   int32_t* labels_out = nullptr;
   int32_t assign = 0;
+  // rows of X when the positions (N) index a list of them rather than the sorted order (the
+  // screen's fallback); 0: N
+  int64_t nrows = 0;
 };
 
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
@@ -202,7 +205,7 @@ __device__ __forceinline__ void make_blocks(const MainArgs& a, const RowPre<NB>&
     const int64_t pos = p0 + nb * 32 + r;
     B.ok[nb] = pos < a.N;
     const int32_t rw = pre.row[nb];
-    B.row[nb] = (rw >= 0 && rw < a.N) ? rw : 0;
+    B.row[nb] = (rw >= 0 && rw < (a.nrows ? a.nrows : a.N)) ? rw : 0;
     int32_t o = B.ok[nb] ? pre.lab[nb] : -1;
     if (o < 0 || o >= a.K) o = -1;
     B.lab[nb] = o;

@@ -1,0 +1,460 @@
+// Fused pass 2 with a one-product screen (squared Euclidean, X stored bf16, Eq.11).
+//
+// The two-product kernel spends half its MFMA work on the low half of the cluster means, which
+// only matters for the few clusters that can be a row's closest other cluster.  Here one fp16
+// product finds that cluster and the epilogue scores it exactly:
+//   1. screen: x in fp16 (exact for bf16 values of magnitude 2^-14 .. 65504, off by less than
+//      2^-24 below that; rows with larger values go to the fallback) times the fp16 table
+//      T16_k ~ -2 mu'_k, plus the constant c_k in three fp16 pieces carried in one more k-step
+//      (so the epilogue has no add); every value is known to within the row's bound E (see
+//      screen.hip).  Each lane keeps, per row, the smallest and second smallest value over its
+//      columns (v_med3 + v_min); the 32-cluster block index rides in the low mantissa bits of
+//      the smallest, so that the lane and those bits name the cluster.
+//   2. the finish takes both minima across the 32 lanes of a row.  When the second exceeds the
+//      first by more than 2 E (plus the perturbation of the index bits), the smallest names the
+//      row's closest other cluster n exactly, and b_i = ||x'||^2 + c_n - 2 x . mu'_n is formed
+//      for n alone in fp32 (x exact, mu'_n and c_n as the two-product form rounds them).
+//   3. the other rows are appended to a list (one atomic per workgroup reserves its entries), and
+//      the two-product kernel runs over that list (fallback), adding its own partial sums of
+//      s_i.  S = (sum over screened rows + sum over fallback rows) / N; the fallback's sums follow
+//      the list's order, which depends on the schedule (as the order of rows within a cluster
+//      does in the statistics pass), so S is reproducible to binary64 rounding, not bitwise.
+// Rows are visited in label-sorted order as in the other fused kernels; 4 waves, two 32-row
+// blocks per wave, 64-cluster tiles through the same LDS ring.
+#include "main_kernels.h"
+
+namespace sil {
+
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+
+struct ScreenArgs {
+  const void* stab;     // fp16 screen table [Kpad][screen_stride(DPX)]
+  int64_t stab_bytes;   // its size
+  int32_t* hdr;         // header: the screen's bound slots, the fallback count
+  int32_t* fblist;      // [N] sorted positions of the rows left to the fallback
+  int32_t ibits;        // bits of the 32-cluster block index packed into the screen values
+};
+
+constexpr uint32_t kExcluded = 0x7f7fffffu;  // FLT_MAX: a column that never competes
+
+__device__ __forceinline__ float slot_f(const int32_t* hdr, int slot) {
+  const unsigned long long* p =
+      reinterpret_cast<const unsigned long long*>(hdr + kHdrScreenWord) + slot;
+  // rounded up, so that the bound stays a bound in fp32
+  return static_cast<float>(__longlong_as_double(static_cast<long long>(*p)) * (1.0 + 0x1p-20));
+}
+
+// Running smallest (m1, with the block index in its low bits) and second smallest (m2) over one
+// 32-cluster block of the accumulators of a row block.  keep / tag: AND and OR applied to each
+// value's bits (keep = 0, tag = kExcluded for a column that does not compete).
+__device__ __forceinline__ void screen_min(const f32x16_t& acc, float (&m1)[16], float (&m2)[16],
+                                           uint32_t keep, uint32_t tag) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const float v = __uint_as_float((__float_as_uint(acc[j]) & keep) | tag);
+    m2[j] = __builtin_amdgcn_fmed3f(v, m1[j], m2[j]);
+    m1[j] = fminf(m1[j], v);
+  }
+}
+
+// The same for a block that straddles a cluster boundary: the own column is excluded per row.
+__device__ __forceinline__ void screen_min_mixed(const f32x16_t& acc, float (&m1)[16],
+                                                 float (&m2)[16], uint32_t keep, uint32_t tag,
+                                                 int32_t k, const int32_t* lab_block, int h) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const i32x4_t l4 = *reinterpret_cast<const i32x4_t*>(lab_block + 8 * q + 4 * h);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = 4 * q + e;
+      const uint32_t bits = (__float_as_uint(acc[j]) & keep) | tag;
+      const float v = __uint_as_float(l4[e] == k ? kExcluded : bits);
+      m2[j] = __builtin_amdgcn_fmed3f(v, m1[j], m2[j]);
+      m1[j] = fminf(m1[j], v);
+    }
+  }
+}
+
+// TC: clusters per table tile (64 or 128; a tile is one barrier and one ring stage).  NB: 32-row
+// blocks per wave: 2 (two workgroups per CU, one accumulator set) or 1 (three workgroups per CU,
+// two accumulator sets alternating between the tile's two 32-cluster blocks, TC = 64).
+template <int DPX, int TC, int NB>
+__global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a, ScreenArgs sa) {
+  static_assert(NB == 2 || (NB == 1 && TC == 64), "screen configurations");
+  constexpr int S = DPX / 16;  // k-steps over the coordinates; step S carries the constant
+  constexpr int RSS = screen_stride(DPX);
+  constexpr int BPT = TC / 32;  // 32-cluster blocks per tile
+  using R = Ring<1, RSS * 2, TC == 64 ? 3 : 2, TC>;
+  constexpr int64_t ROWS = kMainWaves * NB * 32;
+  // the ring's stages (separate arrays, so that the compiler tells the stage being read from the
+  // stages being filled); after the sweep the first stage holds the row minima (3 x 1 KB)
+  __shared__ __attribute__((aligned(16))) uint8_t ring0[R::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t ring1[R::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t ring2[R::NSTAGE == 3 ? R::STAGE_BYTES : 16];
+  static_assert(R::STAGE_BYTES >= 3 * kMainWaves * NB * 32 * 4, "minima fit one stage");
+  float* lds_m1 = reinterpret_cast<float*>(ring0);
+  float* lds_m2 = lds_m1 + kMainWaves * NB * 32;
+  int32_t* lds_win = reinterpret_cast<int32_t*>(lds_m2 + kMainWaves * NB * 32);
+  __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves * NB * 32];
+  __shared__ double lds_bsum[kMainWaves];
+  __shared__ int32_t lds_cnt[kMainWaves + 1];
+
+  const int64_t wb = blockIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int col = lane & 31, h = lane >> 5;
+  const char* tab = static_cast<const char*>(sa.stab);
+  const int64_t piece_bytes = sa.stab_bytes;
+  const int ntiles = static_cast<int>(ceil_div(a.K, TC));  // tiles holding real clusters
+  issue_first<R>(tab, piece_bytes, ntiles, ring0, ring1, wave, lane);
+  const RowPre<NB> pre = fetch_rows<NB>(a, wb * ROWS + wave * NB * 32, lane);
+  int32_t* lab_w = lds_lab + wave * NB * 32;
+  Blocks<NB> B;
+  make_blocks<NB>(a, pre, wb * ROWS + wave * NB * 32, lane, B, lab_w);
+
+  // Prologue: the row term ||x'||^2 and the a-path as in the other kernels; the raw x goes into
+  // fp16 fragments (round toward zero: exact for bf16 values of magnitude 2^-14 .. 65504, within
+  // 2^-24 below), with the row's largest magnitude (rows at or above 65504 are not screened).
+  u32x4_t xf[NB][S];
+  float nrow[NB], arow[NB], amax[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) amax[nb] = 0.0f;
+  prologue<SIL_BF16, 8, S, NB, SIL_SQEUCLID, true>(
+      a, B, lane, nrow, arow, [&](int nb, int q, const float* v) __attribute__((always_inline)) {
+        uint32_t w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          w[e] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(v[2 * e], v[2 * e + 1]));
+          amax[nb] = fmaxf(amax[nb], fmaxf(fabsf(v[2 * e]), fabsf(v[2 * e + 1])));
+        }
+        xf[nb][q] = u32x4_t{w[0], w[1], w[2], w[3]};
+      });
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) amax[nb] = fmaxf(amax[nb], __shfl_xor(amax[nb], 32, 64));
+  // A-side of the constant's k-step: fp16 ones against c1, c2, c3 (lanes of half 0)
+  const u32x4_t onef = h == 0 ? u32x4_t{0x3c003c00u, 0x00003c00u, 0u, 0u} : u32x4_t{0u, 0u, 0u, 0u};
+
+  float m1[NB][16], m2[NB][16];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      m1[nb][j] = __builtin_inff();
+      m2[nb][j] = __builtin_inff();
+    }
+
+  auto bfrag = [&](const uint8_t* st, int cb, int s) __attribute__((always_inline)) {
+    const int off = ((cb * 32 + col) * RSS + 16 * s + 8 * h) * 2;
+    return __builtin_bit_cast(f16x8_t, *reinterpret_cast<const u32x4_t*>(st + off));
+  };
+  constexpr int LA = 2;  // k-steps of table fragments read ahead
+  auto gemm = [&](const uint8_t* st, int cb, f32x16_t (&acc)[NB], auto&& after_first_read)
+      __attribute__((always_inline)) {
+    f16x8_t f[LA + 1];
+    f[0] = bfrag(st, cb, 0);
+    after_first_read();
+#pragma unroll
+    for (int s = 1; s < LA; ++s) f[s] = bfrag(st, cb, s);
+#pragma unroll
+    for (int s = 0; s <= S; ++s) {
+      if (s + LA <= S) f[(s + LA) % (LA + 1)] = bfrag(st, cb, s + LA);
+      __builtin_amdgcn_sched_barrier(0);
+      const f16x8_t g = f[s % (LA + 1)];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const f16x8_t x = __builtin_bit_cast(f16x8_t, s < S ? xf[nb][s < S ? s : 0] : onef);
+        if (s == 0)
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x, g, f32x16_t{}, 0, 0, 0);
+        else
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x, g, acc[nb], 0, 0, 0);
+      }
+    }
+  };
+  const uint32_t keep_in = ~((1u << sa.ibits) - 1u);
+  // minima over 32-cluster block blk; cv = c_k of the lane's column (1e30: empty or padding)
+  auto epi = [&](const f32x16_t (&acc)[NB], int blk, float cv) __attribute__((always_inline)) {
+    const bool empty = cv >= 1.0e29f;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const bool out = empty || (!B.mixed[nb] && blk == B.town[nb] && col == B.cown[nb]);
+      const uint32_t keep = out ? 0u : keep_in;
+      const uint32_t tag = out ? kExcluded : static_cast<uint32_t>(blk);
+      if (B.mixed[nb])
+        screen_min_mixed(acc[nb], m1[nb], m2[nb], keep, tag, 32 * blk + col, lab_w + nb * 32, h);
+      else
+        screen_min(acc[nb], m1[nb], m2[nb], keep, tag);
+    }
+  };
+
+  // One accumulator set (two would not fit the registers of two workgroups per CU beside the
+  // second minimum): the other waves on the SIMD fill each block's minimum with their MFMAs.
+  // Blocks past the last real cluster (padding only) are skipped; table rows past Kpad read as
+  // zeros (the buffer resource ends at the table).
+  const int nblk = static_cast<int>(ceil_div(a.K, 32));
+  if constexpr (NB == 2) {
+    f32x16_t acc[NB];
+    sweep<R>(tab, piece_bytes, ntiles, ring0, ring1, ring2, wave, lane,
+             [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
+      float cv[BPT];
+#pragma unroll
+      for (int cb = 0; cb < BPT; ++cb)
+        cv[cb] = BPT * t + cb < nblk ? a.ctab[TC * t + 32 * cb + col] : 0.0f;
+      gemm(st, 0, acc, prefetch);
+      epi(acc, BPT * t, cv[0]);
+#pragma unroll
+      for (int cb = 1; cb < BPT; ++cb) {
+        if (BPT * t + cb < nblk) {
+          gemm(st, cb, acc, [] {});
+          epi(acc, BPT * t + cb, cv[cb]);
+        }
+      }
+    });
+  } else {
+    // block 0's MFMAs, the previous tile's block 1 minimum under them, block 1's MFMAs, block 0's
+    // minimum under them
+    f32x16_t acc0[NB], acc1[NB];
+    float c1p = 0.0f;
+    const bool last_b1 = 2 * (ntiles - 1) + 1 < nblk;
+    sweep<R>(tab, piece_bytes, ntiles, ring0, ring1, ring2, wave, lane,
+             [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
+      const float c0 = a.ctab[64 * t + col];
+      const float c1 = 2 * t + 1 < nblk ? a.ctab[64 * t + 32 + col] : 0.0f;
+      gemm(st, 0, acc0, prefetch);
+      if (t > 0) epi(acc1, 2 * t - 1, c1p);
+      if (t + 1 < ntiles || last_b1) gemm(st, 1, acc1, [] {});
+      epi(acc0, 2 * t, c0);
+      c1p = c1;
+    });
+    if (last_b1) epi(acc1, 2 * ntiles - 1, c1p);
+  }
+  __syncthreads();
+
+  // ---- finish: both minima across the row's 32 lanes
+  float* lm1 = lds_m1 + wave * NB * 32;
+  float* lm2 = lds_m2 + wave * NB * 32;
+  int32_t* lwin = lds_win + wave * NB * 32;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const float v1 = m1[nb][j];
+      const float g1 = min_over_half(v1);
+      const uint64_t bal = __ballot(v1 == g1);
+      const uint32_t hb = h ? static_cast<uint32_t>(bal >> 32) : static_cast<uint32_t>(bal);
+      const int win = __builtin_ctz(hb);  // lowest lane of the half holding the smallest
+      const float g2 = min_over_half(col == win ? m2[nb][j] : v1);
+      if (col == 0) {
+        lm1[nb * 32 + out_row(j, h)] = g1;
+        lm2[nb * 32 + out_row(j, h)] = g2;
+        lwin[nb * 32 + out_row(j, h)] = win;
+      }
+    }
+  __syncthreads();
+
+  const float inv_scale = ldexpf(1.0f, -screen_exponent(
+      fmax(__longlong_as_double(static_cast<long long>(
+               reinterpret_cast<const unsigned long long*>(sa.hdr + kHdrScreenWord)[SC_TMAX])),
+           __longlong_as_double(static_cast<long long>(
+               reinterpret_cast<const unsigned long long*>(sa.hdr + kHdrScreenWord)[SC_CMAX])))));
+  const float L1 = slot_f(sa.hdr, SC_L1), L2 = slot_f(sa.hdr, SC_L2);
+  const float L3 = slot_f(sa.hdr, SC_L3), EC = slot_f(sa.hdr, SC_EC);
+  const float MN = slot_f(sa.hdr, SC_MNORM);
+  constexpr float acc_eps = (DPX + 16) * 0x1p-23f;
+  // ||x - x16|| < sqrt(DPX) 2^-24 (values below fp16's normal range), times ||T16_k|| <= L2
+  const float xq_err = sqrtf(static_cast<float>(DPX)) * 0x1p-24f * L2;
+  const float tiny_row = sqrtf(static_cast<float>(DPX)) * 0x1p-8f;
+  const float pert = ldexpf(1.0f, sa.ibits - 21);
+  const uint32_t idx_mask = (1u << sa.ibits) - 1u;
+  const int r = lane & 31;
+  double bsum = 0.0;
+  uint64_t fmask[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const float g1 = lm1[nb * 32 + r], g2 = lm2[nb * 32 + r];
+    const int32_t n = static_cast<int32_t>(__float_as_uint(g1) & idx_mask) * 32 + lwin[nb * 32 + r];
+    const int32_t o = B.lab[nb];
+    const bool valid = B.ok[nb] && o >= 0;
+    const bool single = valid && !(a.ascale[o] > 0.0f);
+    // ||x|| <= ||x'|| + ||m|| (x' = x - m), so the bound needs no norm of the raw row
+    const float nx = sqrtf(fmaxf(nrow[nb], 0.0f)) + MN;
+    const float E = (nx * L1 + EC + acc_eps * (nx * L2 + L3) + xq_err) * inv_scale * 1.001f;
+    const float P = pert * (fabsf(g1) + fabsf(g2)) + 1.0e-30f;
+    // rows beyond fp16's range, and rows so small (max |x| < sqrt(DPX) 2^-8, hence ||x|| too)
+    // that the fp16 rounding of their smallest values could reach the two-product form's error
+    // in the exact score, are not screened
+    const bool fits = amax[nb] < 65504.0f && amax[nb] >= tiny_row;
+    const bool unique = valid && !single && fits && n < a.K && (g2 - g1) > 2.0f * E + P;
+    const bool flag = valid && !single && !unique;
+    // the exact score of cluster n: this lane's half of x . mu'_n (x from its fp16 fragments)
+    float dot = 0.0f;
+    if (unique) {
+      const float* mu = a.atab + static_cast<int64_t>(n) * DPX + 8 * h;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        float mv[8];
+        load_f32w<8>(mu + 16 * s, mv);
+        const f16x8_t xv = __builtin_bit_cast(f16x8_t, xf[nb][s]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dot = fmaf(static_cast<float>(xv[e]), mv[e], dot);
+      }
+    }
+    dot += __shfl_xor(dot, 32, 64);
+    const bool owner = h == (nb & 1);
+    if (owner && valid && !flag) {
+      float s_i = 0.0f;
+      if (!single) {
+        float b = fmaxf(nrow[nb] + a.ctab[n] - 2.0f * dot, 0.0f);
+        float av = fmaxf(arow[nb], 0.0f);
+        if (a.root) {
+          b = sqrtf(b);
+          av = sqrtf(av);
+        }
+        const float mx = fmaxf(av, b);
+        s_i = mx > 0.0f ? (b - av) / mx : 0.0f;
+      }
+      if (a.s) a.s[B.row[nb]] = s_i;
+      bsum += static_cast<double>(s_i);
+    }
+    fmask[nb] = __ballot(owner && flag);
+  }
+  int nflag = 0;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) nflag += __popcll(fmask[nb]);
+  for (int off = 1; off < 64; off <<= 1) bsum += __shfl_xor(bsum, off, 64);
+  if (lane == 0) {
+    lds_bsum[wave] = bsum;
+    lds_cnt[wave] = nflag;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    int c = 0;
+    for (int w = 0; w < kMainWaves; ++w) {
+      t += lds_bsum[w];
+      const int cw = lds_cnt[w];
+      lds_cnt[w] = c;  // the wave's offset within the workgroup's entries
+      c += cw;
+    }
+    a.bpart[wb] = t;
+    lds_cnt[kMainWaves] = c > 0 ? atomicAdd(sa.hdr + kHdrFallbackWord, c) : 0;
+  }
+  __syncthreads();
+  if (nflag > 0) {  // wave-uniform: the wave's marked rows, in position order
+    int at = lds_cnt[kMainWaves] + lds_cnt[wave];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const uint64_t m = fmask[nb];
+      if ((m >> lane) & 1u) {
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        sa.fblist[at + before] = static_cast<int32_t>(wb * ROWS + wave * NB * 32 + nb * 32 + r);
+      }
+      at += __popcll(m);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Fallback: the two-product kernel over the listed rows (a persistent grid; each workgroup takes
+// 256 list entries at a time until the list is exhausted).
+
+template <int DPX>
+__global__ __launch_bounds__(256, 2) void k_main_fallback(MainArgs a, const int32_t* fblist,
+                                                          const int32_t* hdr) {
+  constexpr int NB = bf16_nb(DPX, 2, SIL_BF16);
+  constexpr int RS = table_stride(DPX, SIL_BF16);
+  using R = Ring<2, RS * 2, 3, kColTile>;
+  constexpr int64_t ROWS = kMainWaves * NB * 32;
+  __shared__ __attribute__((aligned(16))) uint8_t ring0[R::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t ring1[R::STAGE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t ring2[R::NSTAGE == 3 ? R::STAGE_BYTES : 16];
+  __shared__ float lds_min[kMainWaves * NB * 32];
+  __shared__ int32_t lds_arg[kMainWaves];
+  __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves * NB * 32];
+  __shared__ double lds_bsum[kMainWaves];
+
+  const int32_t total = hdr[kHdrFallbackWord];
+  MainArgs b = a;
+  b.nrows = a.N;
+  b.N = total;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  for (int64_t lb = blockIdx.x; lb * ROWS < total; lb += gridDim.x) {
+    issue_first<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, wave, lane);
+    RowPre<NB> pre;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int64_t p = lb * ROWS + wave * NB * 32 + nb * 32 + (lane & 31);
+      pre.row[nb] = 0;
+      pre.lab[nb] = -1;
+      if (p < total) {
+        int64_t pos = fblist[p];
+        pos = pos < 0 ? 0 : (pos >= a.N ? a.N - 1 : pos);
+        pre.row[nb] = a.perm[pos];
+        pre.lab[nb] = a.lsorted[pos];
+      }
+    }
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));  // keep the body's lane addresses inside the loop
+    main_bf16_body<DPX, NB, 2, SIL_BF16, SIL_SQEUCLID, false, kColTile>(
+        b, lb, pre, ring0, ring1, ring2, lds_min, lds_arg, lds_lab, lds_bsum, tid);
+  }
+}
+
+hipError_t launch_fb_sum(const WsPtrs& w, int rows_per_wg, hipStream_t st);
+
+constexpr int kScreenTile = 64;
+constexpr int kScreenNB = 2;
+int screen_rows_per_block() { return kMainWaves * kScreenNB * 32; }
+
+template <int DPX>
+static void run_screen(const MainArgs& m, const ScreenArgs& sa, const WsLayout& L,
+                       const WsPtrs& w, hipStream_t st) {
+  k_main_screen<DPX, kScreenTile, kScreenNB><<<static_cast<unsigned>(L.nsblk), 256, 0, st>>>(m, sa);
+  MainArgs f = m;
+  f.bpart = w.fbpart;
+  const int64_t flb = ceil_div(m.N, kMainWaves * bf16_nb(DPX, 2, SIL_BF16) * 32);
+  const unsigned fgrid = static_cast<unsigned>(flb < 512 ? flb : 512);
+  k_main_fallback<DPX><<<fgrid, 256, 0, st>>>(f, w.fblist, w.hdr);
+  constexpr int rows = kMainWaves * bf16_nb(DPX, 2, SIL_BF16) * 32;
+  (void)launch_fb_sum(w, rows, st);
+}
+
+hipError_t launch_screen_main(const Problem& p, const WsLayout& L, const WsPtrs& w,
+                              hipStream_t st) {
+  MainArgs m;
+  m.X = p.X;
+  m.col_scale = p.col_scale;
+  m.perm = w.perm;
+  m.lsorted = w.lsorted;
+  m.hdr = w.hdr;
+  m.N = p.N;
+  m.D = p.D;
+  m.K = p.K;
+  m.btab = w.btab;
+  m.piece = static_cast<int64_t>(p.Kpad) * table_stride(p.DPX, p.dtype);
+  m.ctab = w.ctab;
+  m.atab = w.atab;
+  m.avec = w.avec;
+  m.ascale = w.ascale;
+  m.mvec = w.mvec;
+  m.ntiles = p.Kpad / kColTile;
+  m.root = (p.flags & SIL_FLAG_EUCLID_APPROX) ? 1 : 0;
+  m.s = p.s;
+  m.bpart = w.bpart;
+  m.save_a = nullptr;
+  m.save_b = nullptr;
+  m.save_n = nullptr;
+  ScreenArgs sa;
+  sa.stab = w.stab;
+  sa.stab_bytes = static_cast<int64_t>(p.Kpad) * screen_stride(p.DPX) * 2;
+  sa.hdr = w.hdr;
+  sa.fblist = w.fblist;
+  int bits = 1;
+  while ((1 << bits) < p.Kpad / 32) ++bits;
+  sa.ibits = bits;
+  with_depth(DepthsBf16{}, p.DPX, [&](auto dp) {
+    constexpr int D_ = decltype(dp)::value;
+    if constexpr (D_ <= kScreenMaxDPX) run_screen<D_>(m, sa, L, w, st);
+  });
+  return hipGetLastError();
+}
+
+}  // namespace sil

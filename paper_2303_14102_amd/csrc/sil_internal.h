@@ -51,6 +51,38 @@ inline void with_depth(DepthList<Ds...>, int DPX, F&& f) {
   (void)((DPX == Ds ? (f(std::integral_constant<int, Ds>{}), true) : false) || ...);
 }
 
+// One-product screen (squared Euclidean, bf16 storage, two-product request): an fp16 MFMA sweep
+// finds each row's nearest other cluster, which the epilogue then scores exactly; rows whose two
+// best screened values are too close for the screen's error bound go to the two-product kernel.
+// Its table row: the fp16 table entries (DPX), one k-step holding the per-cluster constant as
+// three fp16 pieces (16), and one 16-byte chunk of padding (the odd chunk count of table_stride).
+constexpr int screen_stride(int DPX) { return DPX + 24; }
+constexpr int kScreenMaxDPX = 128;
+// Header slots of the screen: 64-bit words from int32 word 16, each the bit pattern of a
+// non-negative double raised with integer atomicMax (for such patterns the largest pattern is
+// that of the largest value, whatever the order of the updates).
+enum ScreenSlot {
+  SC_TMAX = 0,  // max |table entry|
+  SC_CMAX,      // max |c_k|
+  SC_L1,        // max_k || fp16 table row - exact table row ||
+  SC_L2,        // max_k || fp16 table row ||
+  SC_L3,        // max_k (|c1| + |c2| + |c3|), the constant's pieces
+  SC_EC,        // max_k |c1 + c2 + c3 - c_k|
+  SC_MNORM,     // || centring vector (fp32, as the kernels use it) ||
+  SC_COUNT
+};
+constexpr int kHdrScreenWord = 16;
+constexpr int kHdrFallbackWord = 40;  // rows the screen left to the fallback (int32)
+constexpr int kHdrFallbackSumWord = 48;  // sum of their s_i (double)
+// fp16 scale exponent of the screen table: entries are stored times 2^-f so that the largest lies
+// in (2^13, 2^14] (f = 0 for an all-zero table)
+__host__ __device__ inline int screen_exponent(double amax) {
+  if (!(amax > 0.0)) return 0;
+  int e = 0;
+  (void)frexp(amax, &e);  // amax = m 2^e, m in [0.5, 1)
+  return e - 14;
+}
+
 // Row stride of the GEMM table in elements: DPX plus one 16-byte chunk, so that a row spans an
 // odd number of 16-byte chunks and the 16 lanes of one LDS read phase hit 16 different bank
 // groups.  (Every instantiated DPX spans an even number of chunks.)
@@ -84,11 +116,17 @@ struct WsLayout {
   size_t save_n;   // int32[N]       neighbouring cluster id
   size_t gpart;    // f64[nwg*K*(D+1)] backward: per-workgroup partial A_k, B_k
   size_t gAB;      // f64[K*(D+1)]   backward: A_k (column D) and B_k
+  // one-product screen (squared Euclidean with bf16 storage; empty otherwise)
+  size_t stab;     // f16[Kpad*screen_stride(DPX)]  screen table
+  size_t c64;      // f64[Kpad]      c_k in binary64
+  size_t fblist;   // i32[N]         sorted positions of the rows left to the fallback
+  size_t fbpart;   // f64[N/128]     per-workgroup sums of s_i of the fallback rows
   size_t total;
   // shape
   int64_t N;
   int32_t D, DPX, K, Kpad;
   int64_t nseg, nblocks;
+  int64_t nsblk;   // screen workgroups; 0 without a screen region
   int dtype, metric, flags;
 };
 
@@ -120,6 +158,10 @@ struct WsPtrs {
   int32_t* save_n;
   double* gpart;
   double* gAB;
+  void* stab;
+  double* c64;
+  int32_t* fblist;
+  double* fbpart;
 };
 
 WsPtrs carve(const WsLayout& L, void* ws);
@@ -149,6 +191,9 @@ struct Problem {
   int min_nonempty = 2;
   // the reduction returns the sum of the block partials rather than their mean
   int reduce_sum = 0;
+  // squared Euclidean, bf16 storage, two products: the one-product screen with exact rescoring
+  // and the two-product kernel for the rows it leaves (run_forward sets it)
+  int screen = 0;
 };
 
 // zero the small workspace regions; histogram, scan, scatter, segmented reduction, combine
@@ -172,6 +217,14 @@ int run_forward(int32_t metric, const void* X, int32_t dtype, const float* col_s
 
 // rows per workgroup of the fused kernel for this problem (host and workspace sizing)
 int main_rows_per_block(int dtype, int DPX, int products);
+// whether a forward call takes the one-product screen
+bool screen_applies(int metric, int dtype, int DPX, int products, int flags);
+// rows per workgroup of the screen kernel (its workgroups and per-workgroup sums)
+int screen_rows_per_block();
+// screen tables and bounds after launch_finalize; the screen kernel, the fallback list, the
+// two-product kernel over it (launch_main with p.screen); the reduction adds the fallback sums
+hipError_t launch_screen_table(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st);
+hipError_t launch_screen_main(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st);
 
 // Folded centring.  The two-product bf16 kernels for the squared Euclidean distance take x
 // itself (exact in bf16 storage) into the GEMM rather than x' = x - m, and the constant carries

@@ -51,8 +51,12 @@ def test_workspace_bytes_host_logic(lib):
     b = f(10_000, 8, 4, 0, _lib.SIL_F32, _lib.SIL_FLAG_SAVE_FOR_GRAD)
     assert a > 0 and b >= a + 3 * 4 * 10_000
     # grows linearly in N (sorted row ids and labels: 8 bytes a point), plus tables independent of N
-    big = f(50_000_000, 128, 1000, 0, _lib.SIL_BF16, 0)
+    big = f(50_000_000, 128, 1000, 0, _lib.SIL_F32, 0)
     assert 50_000_000 * 8 < big < 50_000_000 * 8 + 64 * 2**20
+    # squared Euclidean with bf16 storage adds the one-product screen's list of fallback rows
+    big = f(50_000_000, 128, 1000, 0, _lib.SIL_BF16, 0)
+    assert 50_000_000 * 12 < big < 50_000_000 * 12 + 64 * 2**20
+    assert f(50_000_000, 128, 1000, 0, _lib.SIL_BF16, _lib.SIL_FLAG_NO_SCREEN) < 50_000_000 * 8 + 64 * 2**20
     assert f(2**31 - 1, 1, 2, 0, 0, 0) > 0
     assert f(2**31, 1, 2, 0, 0, 0) == 0
 
