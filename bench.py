@@ -25,7 +25,8 @@ sys.path.insert(0, ROOT)
 PEAK = {"bf16": 2.5e15, "fp32": 157.3e12, "hbm": 8.0e12}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ["paper_2303_14102_amd/csrc/main_kernels.h", "paper_2303_14102_amd/csrc/main_bf16.hip",
-                  "paper_2303_14102_amd/csrc/main_f32.hip", "paper_2303_14102_amd/csrc/stats.hip"]
+                  "paper_2303_14102_amd/csrc/main_f32.hip", "paper_2303_14102_amd/csrc/stats.hip",
+                  "paper_2303_14102_amd/csrc/main_screen.hip", "paper_2303_14102_amd/csrc/screen.hip"]
 
 
 def kernel_source_hash():
@@ -395,6 +396,8 @@ def parse():
                     help="full: every s_i and S against the whole FP64 oracle (about 2 minutes of "
                          "host time at the default workload); sampled: 256 points")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--no-screen", action="store_true",
+                    help="squared Euclidean, bf16, two products: the plain two-product sweep for every row")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the measured copy / GEMM peaks and the small workload's latency")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
@@ -679,7 +682,8 @@ def main():
             "kl": lib.silhouette_kl}[args.metric]
     if args.euclid_approx and args.metric != "sqeuclid":
         sys.exit("--euclid-approx applies to the squared Euclidean entry point")
-    flags = _lib.SIL_FLAG_EUCLID_APPROX if args.euclid_approx else 0
+    flags = (_lib.SIL_FLAG_EUCLID_APPROX if args.euclid_approx else 0) | (
+        _lib.SIL_FLAG_NO_SCREEN if args.no_screen else 0)
     ref_metric = "euclid_approx" if args.euclid_approx else args.metric
     dcode = sil._dtype_code(X)
     stream = sil._stream(dev)
@@ -736,13 +740,29 @@ def main():
     peak = PEAK["fp32"] if args.form == "f32" else PEAK["bf16"]
     prods = 1 if args.form == "f32" else args.products
     kname = "k_main_bf16" if args.form != "f32" else "k_main_f32"
+    screened = (args.form == "bf16" and args.metric == "sqeuclid" and args.products == 2
+                and spec.d <= 128 and not args.no_screen)
+    issued = useful * prods
+    note = ("achieved = 2*N*D*K useful flops / mean duration of the fused kernel; "
+            "issued_frac counts every split product")
+    if screened:
+        fb = sil.fallback_rows(ws)
+        # the screen: one fp16 product over D coordinates plus the constant's k-step (16 deep) for
+        # every row; the two-product kernel over the listed rows
+        depth = -(-spec.d // 16) * 16
+        issued = 2.0 * spec.n * spec.k * (depth + 16) + 2.0 * 2.0 * fb * spec.k * depth
+        kname = "k_main_screen"
+        note = ("achieved = 2*N*D*K useful flops / mean duration of the fused phase (the fp16 screen "
+                "kernel, then the two-product kernel over the rows it leaves); issued_frac counts the "
+                "screen's constant k-step and the fallback's two products")
+        out["screen"] = {"fallback_rows": fb, "fallback_frac": fb / spec.n,
+                         "kernels": ["k_main_screen", "k_main_fallback", "k_fb_sum"]}
     out["roofline"] = {"bound": "mfma", "achieved": useful / t_main / 1e12, "peak": peak / 1e12,
                        "unit": "TFLOP/s", "frac": useful / t_main / peak,
                        "traffic": measured_traffic(kname, spec.name),
                        "kernel": kname,
-                       "issued_frac": useful * prods / t_main / peak,
-                       "note": "achieved = 2*N*D*K useful flops / mean duration of the fused kernel; "
-                               "issued_frac counts every split product"}
+                       "issued_frac": issued / t_main / peak,
+                       "note": note}
     stats_bytes = spec.n * spec.d * X.element_size() + 4 * spec.n
     out["stats_pass"] = {"bound": "hbm", "algorithmic_bytes": stats_bytes,
                          "achieved_GBps": stats_bytes / (phases[0] * 1e-3) / 1e9,

@@ -247,7 +247,8 @@ int silhouette_mahalanobis(const void* X, int32_t dtype, const float* col_scale,
  * two device chunk buffers of `chunk_rows` rows, twice: pass 1 accumulates every chunk's
  * statistics into FP64 global sums (in chunk order), pass 2 scores every chunk against the
  * tables of the whole data set.  The result equals silhouette_sqeuclid / silhouette_cosine on
- * the same data up to the order of the FP64 cluster sums.
+ * the same data up to the order of the FP64 cluster sums (with bf16 storage and two products,
+ * the chunks run the plain two-product sweep: SIL_FLAG_NO_SCREEN's result).
  *   metric       SIL_SQEUCLID or SIL_COSINE
  *   X_host       host, [N, D] in `dtype`; pinned (hipHostMalloc) for the uploads to overlap the
  *                kernels, pageable memory works but serialises them

@@ -71,21 +71,23 @@ def new_workspace(N: int, D: int, K: int, metric: str, dtype, flags: int, device
 def silhouette(X: torch.Tensor, labels: torch.Tensor, K: int, metric: str = "sqeuclid", *,
                products: int = 0, centre: bool = True, col_scale: Optional[torch.Tensor] = None,
                want_s: bool = True, save_for_grad: bool = False, euclid_approx: bool = False,
-               workspace: Optional[torch.Tensor] = None, check_status: bool = False):
+               screen: bool = True, workspace: Optional[torch.Tensor] = None,
+               check_status: bool = False):
     """Per-point s_i (float32 [N] or None) and the mean S (float64 0-d tensor on the device).
 
     metric: "sqeuclid", "cosine" or "kl" (the generalized Kullback-Leibler divergence of positive
     vectors, fp32 or bf16 storage).  products: bf16/fp8 cross-term products (1, 2, 3; 0 = library
     default).  centre: subtract the global mean first (squared Euclidean only).  euclid_approx:
     the approximate Euclidean form (square roots of the point-to-cluster mean squared distances;
-    squared Euclidean only).
+    squared Euclidean only).  screen: the one-product screen of the squared Euclidean bf16
+    two-product form (False: the plain two-product sweep for every point).
     workspace: a uint8 device tensor of at least workspace_bytes(...) bytes, reused across
     calls; allocated here when None.
     """
     _check_inputs(X, labels, col_scale)
     N, D = X.shape
     flags = ((0 if centre else L.SIL_FLAG_NO_CENTRE) | (L.SIL_FLAG_SAVE_FOR_GRAD if save_for_grad else 0)
-             | (L.SIL_FLAG_EUCLID_APPROX if euclid_approx else 0))
+             | (L.SIL_FLAG_EUCLID_APPROX if euclid_approx else 0) | (0 if screen else L.SIL_FLAG_NO_SCREEN))
     if workspace is None:
         workspace = new_workspace(N, D, K, metric, X.dtype, flags, X.device)
     s = torch.empty(N, dtype=torch.float32, device=X.device) if want_s else None

@@ -53,8 +53,9 @@ def test_stream_equals_in_memory(dev, case):
     Xd, sc, codes = storage(b.X.to(dev), form)
     lab_d = b.labels.to(dev)
     print(f"[stream] {case}", flush=True)
+    # the streamed chunks run the two-product sweep itself (not the in-memory form's screen)
     s_mem, S_mem = sil.silhouette(Xd, lab_d, k, metric, products=products, col_scale=sc,
-                                  euclid_approx=approx, check_status=True)
+                                  euclid_approx=approx, screen=False, check_status=True)
     s_st, S_st = sil.silhouette_stream(host_copy(Xd), b.labels.contiguous().pin_memory(), k, metric,
                                        chunk_rows=chunk, products=products, col_scale=sc,
                                        euclid_approx=approx, device=dev, check_status=True)
