@@ -740,8 +740,8 @@ def main():
     peak = PEAK["fp32"] if args.form == "f32" else PEAK["bf16"]
     prods = 1 if args.form == "f32" else args.products
     kname = "k_main_bf16" if args.form != "f32" else "k_main_f32"
-    screened = (args.form == "bf16" and args.metric == "sqeuclid" and args.products == 2
-                and spec.d <= 128 and not args.no_screen)
+    screened = (args.form in ("bf16", "fp8") and args.metric == "sqeuclid" and args.products == 2
+                and spec.d <= 128 and (args.form == "bf16" or spec.d % 8 == 0) and not args.no_screen)
     issued = useful * prods
     note = ("achieved = 2*N*D*K useful flops / mean duration of the fused kernel; "
             "issued_frac counts every split product")

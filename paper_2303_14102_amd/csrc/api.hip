@@ -58,6 +58,7 @@ WsLayout make_layout(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dt
   L.nsblk = scr ? ceil_div(N, screen_rows_per_block()) : 0;
   L.stab = take(scr ? static_cast<size_t>(L.Kpad) * screen_stride(L.DPX) * 2 : 0);
   L.c64 = take(scr ? static_cast<size_t>(L.Kpad) * 8 : 0);
+  L.rtab = take(scr && dtype == SIL_FP8_E4M3 ? static_cast<size_t>(K) * L.DPX * 4 : 0);
   L.fblist = take(scr ? static_cast<size_t>(N) * 4 : 0);
   // fallback workgroups take at least 128 list entries each
   L.fbpart = take(scr ? static_cast<size_t>(ceil_div(N, kMainWaves * 32)) * 8 : 0);
@@ -93,6 +94,7 @@ WsPtrs carve(const WsLayout& L, void* ws) {
   w.gAB = reinterpret_cast<double*>(b + L.gAB);
   w.stab = b + L.stab;
   w.c64 = reinterpret_cast<double*>(b + L.c64);
+  w.rtab = reinterpret_cast<float*>(b + L.rtab);
   w.fblist = reinterpret_cast<int32_t*>(b + L.fblist);
   w.fbpart = reinterpret_cast<double*>(b + L.fbpart);
   return w;
@@ -148,7 +150,10 @@ int run_forward(int32_t metric, const void* X, int32_t dtype, const float* col_s
   const WsPtrs w = carve(L, ws);
   if ((flags & SIL_FLAG_SAVE_FOR_GRAD) && dtype != SIL_F32) return SIL_E_DTYPE;
   products = run_products(metric, dtype, flags, products);
-  const int screen = screen_applies(metric, dtype, L.DPX, products, flags) ? 1 : 0;
+  // fp8: the screen's prologue reads whole 8-code chunks and 16-byte aligned column scales
+  const bool fp8_vec = dtype != SIL_FP8_E4M3 ||
+                       (D % 8 == 0 && (reinterpret_cast<uintptr_t>(col_scale) & 15u) == 0);
+  const int screen = screen_applies(metric, dtype, L.DPX, products, flags) && fp8_vec ? 1 : 0;
   const int64_t nblocks =
       screen ? L.nsblk : ceil_div(N, main_rows_per_block(dtype, L.DPX, products));
   Problem p{X, col_scale, labels, N, D, L.DPX, K, L.Kpad, dtype, metric, products, flags, s, S,

@@ -82,16 +82,20 @@ __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
 }
 __device__ __forceinline__ float bf16_bits_f32(uint32_t h) { return __uint_as_float(h << 16); }
 
+// OCP FP8 E4M3 codes by the hardware conversion (gfx950's v_cvt_[pk_]f32_fp8 decode the OCP
+// encoding exactly, NaN codes included)
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float e4m3_f32(uint32_t q) {
-  const uint32_t sign = (q & 0x80u) << 24;
-  const uint32_t e = (q >> 3) & 15u;
-  const uint32_t m = q & 7u;
-  if (e == 15u && m == 7u) return __uint_as_float(0x7fc00000u);
-  if (e == 0u) {
-    const float v = static_cast<float>(m) * 0.001953125f;
-    return sign ? -v : v;
-  }
-  return __uint_as_float(sign | ((e + 120u) << 23) | (m << 20));
+  return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(q & 0xffu), 0);
+}
+// the four codes of a 32-bit word, lowest byte first
+__device__ __forceinline__ void e4m3x4_f32(uint32_t w, float* out) {
+  const f32x2_t lo = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w), false);
+  const f32x2_t hi = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w), true);
+  out[0] = lo[0];
+  out[1] = lo[1];
+  out[2] = hi[0];
+  out[3] = hi[1];
 }
 
 // W consecutive stored elements of row `row` starting at column c0, decoded to fp32; zero
@@ -136,11 +140,8 @@ __device__ __forceinline__ void load_chunk(const void* __restrict__ X,
     const uint8_t* p = static_cast<const uint8_t*>(X) + base;
     if (vec) {
       const u32x2_t v = *reinterpret_cast<const u32x2_t*>(p);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        out[e] = e4m3_f32((v[0] >> (8 * e)) & 0xffu);
-        out[4 + e] = e4m3_f32((v[1] >> (8 * e)) & 0xffu);
-      }
+      e4m3x4_f32(v[0], out);
+      e4m3x4_f32(v[1], out + 4);
     } else {
 #pragma unroll
       for (int e = 0; e < W; ++e) out[e] = (c0 + e < D) ? e4m3_f32(p[e]) : 0.0f;
@@ -268,11 +269,8 @@ __device__ __forceinline__ void decode_raw(typename RawChunk<DT>::T raw,
       out[2 * e + 1] = bf16_bits_f32(raw[e] >> 16);
     }
   } else {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      out[e] = e4m3_f32((raw[0] >> (8 * e)) & 0xffu);
-      out[4 + e] = e4m3_f32((raw[1] >> (8 * e)) & 0xffu);
-    }
+    e4m3x4_f32(raw[0], out);
+    e4m3x4_f32(raw[1], out + 4);
     if constexpr (SCALE) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) out[e] *= col_scale[c0 + e];
@@ -295,17 +293,32 @@ __device__ __forceinline__ void load_f32w(const float* __restrict__ p, float* ou
   }
 }
 
-template <int DT, int W, int NQ, int NB, int METRIC, bool RAW, typename Emit>
+// VEC_ONLY: the caller guarantees D % W == 0 and 16-byte aligned column scales, so only the
+// whole-vector paths are compiled.
+template <int DT, int W, int NQ, int NB, int METRIC, bool RAW, bool VEC_ONLY = false, typename Emit>
 __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B, int lane,
                                          float (&nrow)[NB], float (&arow)[NB], Emit&& emit) {
   constexpr int DPX = 2 * NQ * W;
   constexpr bool CODES = RAW && DT == SIL_FP8_E4M3;  // xv holds unscaled fp8 codes
   const int h = lane >> 5;
-  const bool vec = (a.D % W) == 0;  // wave-uniform
-  // the column scales of chunk c0 (fp8 codes), zero past D
+  const bool vec = VEC_ONLY || (a.D % W) == 0;  // wave-uniform
+  // the column scales of chunk c0 (fp8 codes), zero past D: whole-vector loads when every chunk
+  // lies inside the row and the scales are 16-byte aligned
+  const bool svec =
+      VEC_ONLY || (vec && (reinterpret_cast<uintptr_t>(a.col_scale) & 15u) == 0);
+  const float* colsc = a.col_scale;
   auto scales = [&](int c0, float* sc) __attribute__((always_inline)) {
+    if (svec) {
+      if (c0 < a.D) {
+        load_f32w<W>(colsc + c0, sc);
+      } else {
 #pragma unroll
-    for (int e = 0; e < W; ++e) sc[e] = c0 + e < a.D ? a.col_scale[c0 + e] : 0.0f;
+        for (int e = 0; e < W; ++e) sc[e] = 0.0f;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < W; ++e) sc[e] = c0 + e < a.D ? colsc[c0 + e] : 0.0f;
+    }
   };
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {

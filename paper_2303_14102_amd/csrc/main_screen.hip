@@ -32,6 +32,7 @@ struct ScreenArgs {
   int64_t stab_bytes;   // its size
   int32_t* hdr;         // header: the screen's bound slots, the fallback count
   int32_t* fblist;      // [N] sorted positions of the rows left to the fallback
+  const float* rtab;    // fp8: [K][DPX] column scales times mu'_k
   int32_t ibits;        // bits of the 32-cluster block index packed into the screen values
 };
 
@@ -78,9 +79,13 @@ __device__ __forceinline__ void screen_min_mixed(const f32x16_t& acc, float (&m1
 // TC: clusters per table tile (64 or 128; a tile is one barrier and one ring stage).  NB: 32-row
 // blocks per wave: 2 (two workgroups per CU, one accumulator set) or 1 (three workgroups per CU,
 // two accumulator sets alternating between the tile's two 32-cluster blocks, TC = 64).
-template <int DPX, int TC, int NB>
+// DT: X stored bf16 (x itself in the GEMM) or fp8 e4m3 (its codes in the GEMM, the column scales
+// in the table); both are exact in fp16 (fp8 always, bf16 for magnitudes 2^-14 .. 65504).
+template <int DPX, int TC, int NB, int DT>
 __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a, ScreenArgs sa) {
   static_assert(NB == 2 || (NB == 1 && TC == 64), "screen configurations");
+  static_assert(DT == SIL_BF16 || DT == SIL_FP8_E4M3, "bf16 or fp8 storage");
+  constexpr bool CODES = DT == SIL_FP8_E4M3;
   constexpr int S = DPX / 16;  // k-steps over the coordinates; step S carries the constant
   constexpr int RSS = screen_stride(DPX);
   constexpr int BPT = TC / 32;  // 32-cluster blocks per tile
@@ -111,25 +116,38 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
   Blocks<NB> B;
   make_blocks<NB>(a, pre, wb * ROWS + wave * NB * 32, lane, B, lab_w);
 
-  // Prologue: the row term ||x'||^2 and the a-path as in the other kernels; the raw x goes into
-  // fp16 fragments (round toward zero: exact for bf16 values of magnitude 2^-14 .. 65504, within
-  // 2^-24 below), with the row's largest magnitude (rows at or above 65504 are not screened).
+  // Prologue: the row term ||x'||^2 and the a-path as in the other kernels; the GEMM operand (x,
+  // or the fp8 codes) goes into fp16 fragments (round toward zero: exact for bf16 values of
+  // magnitude 2^-14 .. 65504, within 2^-24 below; exact for every e4m3 code), with the row's
+  // largest magnitude (bf16 rows at or above 65504 are not screened) and, for fp8, the squared
+  // norm of the codes.
   u32x4_t xf[NB][S];
-  float nrow[NB], arow[NB], amax[NB];
+  float nrow[NB], arow[NB], amax[NB], ncode[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) amax[nb] = 0.0f;
-  prologue<SIL_BF16, 8, S, NB, SIL_SQEUCLID, true>(
+  for (int nb = 0; nb < NB; ++nb) {
+    amax[nb] = 0.0f;
+    ncode[nb] = 0.0f;
+  }
+  prologue<DT, 8, S, NB, SIL_SQEUCLID, true, CODES>(
       a, B, lane, nrow, arow, [&](int nb, int q, const float* v) __attribute__((always_inline)) {
         uint32_t w[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           w[e] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(v[2 * e], v[2 * e + 1]));
-          amax[nb] = fmaxf(amax[nb], fmaxf(fabsf(v[2 * e]), fabsf(v[2 * e + 1])));
+          if constexpr (CODES) {
+            ncode[nb] = fmaf(v[2 * e], v[2 * e], ncode[nb]);
+            ncode[nb] = fmaf(v[2 * e + 1], v[2 * e + 1], ncode[nb]);
+          } else {
+            amax[nb] = fmaxf(amax[nb], fmaxf(fabsf(v[2 * e]), fabsf(v[2 * e + 1])));
+          }
         }
         xf[nb][q] = u32x4_t{w[0], w[1], w[2], w[3]};
       });
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) amax[nb] = fmaxf(amax[nb], __shfl_xor(amax[nb], 32, 64));
+  for (int nb = 0; nb < NB; ++nb) {
+    amax[nb] = fmaxf(amax[nb], __shfl_xor(amax[nb], 32, 64));
+    ncode[nb] += __shfl_xor(ncode[nb], 32, 64);
+  }
   // A-side of the constant's k-step: fp16 ones against c1, c2, c3 (lanes of half 0)
   const u32x4_t onef = h == 0 ? u32x4_t{0x3c003c00u, 0x00003c00u, 0u, 0u} : u32x4_t{0u, 0u, 0u, 0u};
 
@@ -274,20 +292,21 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
     const int32_t o = B.lab[nb];
     const bool valid = B.ok[nb] && o >= 0;
     const bool single = valid && !(a.ascale[o] > 0.0f);
-    // ||x|| <= ||x'|| + ||m|| (x' = x - m), so the bound needs no norm of the raw row
-    const float nx = sqrtf(fmaxf(nrow[nb], 0.0f)) + MN;
+    // the GEMM operand's norm: ||x|| <= ||x'|| + ||m|| (x' = x - m) for bf16, the codes' for fp8
+    const float nx = CODES ? sqrtf(ncode[nb]) : sqrtf(fmaxf(nrow[nb], 0.0f)) + MN;
     const float E = (nx * L1 + EC + acc_eps * (nx * L2 + L3) + xq_err) * inv_scale * 1.001f;
     const float P = pert * (fabsf(g1) + fabsf(g2)) + 1.0e-30f;
     // rows beyond fp16's range, and rows so small (max |x| < sqrt(DPX) 2^-8, hence ||x|| too)
     // that the fp16 rounding of their smallest values could reach the two-product form's error
     // in the exact score, are not screened
-    const bool fits = amax[nb] < 65504.0f && amax[nb] >= tiny_row;
+    const bool fits = CODES || (amax[nb] < 65504.0f && amax[nb] >= tiny_row);
     const bool unique = valid && !single && fits && n < a.K && (g2 - g1) > 2.0f * E + P;
     const bool flag = valid && !single && !unique;
-    // the exact score of cluster n: this lane's half of x . mu'_n (x from its fp16 fragments)
+    // the exact score of cluster n: this lane's half of x . mu'_n (x from its fp16 fragments;
+    // fp8: the codes against the column scales times mu'_n)
     float dot = 0.0f;
     if (unique) {
-      const float* mu = a.atab + static_cast<int64_t>(n) * DPX + 8 * h;
+      const float* mu = (CODES ? sa.rtab : a.atab) + static_cast<int64_t>(n) * DPX + 8 * h;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         float mv[8];
@@ -356,10 +375,10 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
 // Fallback: the two-product kernel over the listed rows (a persistent grid; each workgroup takes
 // 256 list entries at a time until the list is exhausted).
 
-template <int DPX>
+template <int DPX, int DT>
 __global__ __launch_bounds__(256, 2) void k_main_fallback(MainArgs a, const int32_t* fblist,
                                                           const int32_t* hdr) {
-  constexpr int NB = bf16_nb(DPX, 2, SIL_BF16);
+  constexpr int NB = bf16_nb(DPX, 2, DT);
   constexpr int RS = table_stride(DPX, SIL_BF16);
   using R = Ring<2, RS * 2, 3, kColTile>;
   constexpr int64_t ROWS = kMainWaves * NB * 32;
@@ -393,7 +412,7 @@ __global__ __launch_bounds__(256, 2) void k_main_fallback(MainArgs a, const int3
     }
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));  // keep the body's lane addresses inside the loop
-    main_bf16_body<DPX, NB, 2, SIL_BF16, SIL_SQEUCLID, false, kColTile>(
+    main_bf16_body<DPX, NB, 2, DT, SIL_SQEUCLID, false, kColTile>(
         b, lb, pre, ring0, ring1, ring2, lds_min, lds_arg, lds_lab, lds_bsum, tid);
   }
 }
@@ -404,16 +423,16 @@ constexpr int kScreenTile = 64;
 constexpr int kScreenNB = 2;
 int screen_rows_per_block() { return kMainWaves * kScreenNB * 32; }
 
-template <int DPX>
+template <int DPX, int DT>
 static void run_screen(const MainArgs& m, const ScreenArgs& sa, const WsLayout& L,
                        const WsPtrs& w, hipStream_t st) {
-  k_main_screen<DPX, kScreenTile, kScreenNB><<<static_cast<unsigned>(L.nsblk), 256, 0, st>>>(m, sa);
+  k_main_screen<DPX, kScreenTile, kScreenNB, DT><<<static_cast<unsigned>(L.nsblk), 256, 0, st>>>(m, sa);
   MainArgs f = m;
   f.bpart = w.fbpart;
-  const int64_t flb = ceil_div(m.N, kMainWaves * bf16_nb(DPX, 2, SIL_BF16) * 32);
+  constexpr int rows = kMainWaves * bf16_nb(DPX, 2, DT) * 32;
+  const int64_t flb = ceil_div(m.N, rows);
   const unsigned fgrid = static_cast<unsigned>(flb < 512 ? flb : 512);
-  k_main_fallback<DPX><<<fgrid, 256, 0, st>>>(f, w.fblist, w.hdr);
-  constexpr int rows = kMainWaves * bf16_nb(DPX, 2, SIL_BF16) * 32;
+  k_main_fallback<DPX, DT><<<fgrid, 256, 0, st>>>(f, w.fblist, w.hdr);
   (void)launch_fb_sum(w, rows, st);
 }
 
@@ -447,12 +466,18 @@ hipError_t launch_screen_main(const Problem& p, const WsLayout& L, const WsPtrs&
   sa.stab_bytes = static_cast<int64_t>(p.Kpad) * screen_stride(p.DPX) * 2;
   sa.hdr = w.hdr;
   sa.fblist = w.fblist;
+  sa.rtab = w.rtab;
   int bits = 1;
   while ((1 << bits) < p.Kpad / 32) ++bits;
   sa.ibits = bits;
   with_depth(DepthsBf16{}, p.DPX, [&](auto dp) {
     constexpr int D_ = decltype(dp)::value;
-    if constexpr (D_ <= kScreenMaxDPX) run_screen<D_>(m, sa, L, w, st);
+    if constexpr (D_ <= kScreenMaxDPX) {
+      if (p.dtype == SIL_FP8_E4M3)
+        run_screen<D_, SIL_FP8_E4M3>(m, sa, L, w, st);
+      else
+        run_screen<D_, SIL_BF16>(m, sa, L, w, st);
+    }
   });
   return hipGetLastError();
 }

@@ -41,8 +41,9 @@ constexpr int kTableClustersPerWave = 4;
 __global__ __launch_bounds__(256) void k_screen_table(
     const int32_t* __restrict__ count, const double* __restrict__ V,
     const double* __restrict__ gmean, const float* __restrict__ mvec,
-    const double* __restrict__ c64, int32_t K, int32_t Kpad, int32_t D, int32_t DPX,
-    _Float16* __restrict__ stab, int32_t* __restrict__ hdr) {
+    const float* __restrict__ tscale, const double* __restrict__ c64, int32_t K, int32_t Kpad,
+    int32_t D, int32_t DPX, _Float16* __restrict__ stab, float* __restrict__ rtab,
+    int32_t* __restrict__ hdr) {
   __shared__ double red[4][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int f = screen_exponent(fmax(read_slot(hdr, SC_TMAX), read_slot(hdr, SC_CMAX)));
@@ -62,9 +63,12 @@ __global__ __launch_bounds__(256) void k_screen_table(
       if (n > 0 && l < D) {  // the same binary64 operations as the two-product table
         const double mu = V[static_cast<int64_t>(k) * D + l] / dn;
         g = -2.0 * (mu - gmean[l]);
+        if (tscale) g *= static_cast<double>(tscale[l]);  // fp8: the codes enter the GEMM
       }
       const _Float16 t = static_cast<_Float16>(static_cast<float>(g * sc));
       row[l] = t;
+      // fp8: s_l mu'_kl in fp32 for the exact score of the codes (-g / 2, exact scaling)
+      if (rtab && k < K && l < DPX) rtab[static_cast<int64_t>(k) * DPX + l] = static_cast<float>(-0.5 * g);
       const double back = static_cast<double>(t) * usc;
       err2 += (back - g) * (back - g);
       nrm2 += back * back;
@@ -135,7 +139,8 @@ __global__ __launch_bounds__(1024) void k_fb_sum(const double* __restrict__ part
 }  // namespace
 
 bool screen_applies(int metric, int dtype, int DPX, int products, int flags) {
-  return metric == SIL_SQEUCLID && dtype == SIL_BF16 && products == 2 && DPX <= kScreenMaxDPX &&
+  return metric == SIL_SQEUCLID && (dtype == SIL_BF16 || dtype == SIL_FP8_E4M3) && products == 2 &&
+         DPX <= kScreenMaxDPX &&
          !(flags & (SIL_FLAG_NO_SCREEN | SIL_FLAG_SAVE_FOR_GRAD));
 }
 
@@ -143,8 +148,10 @@ hipError_t launch_screen_table(const Problem& p, const WsLayout& L, const WsPtrs
                                hipStream_t st) {
   (void)L;
   const unsigned nb = static_cast<unsigned>(ceil_div(p.Kpad, 4 * kTableClustersPerWave));
-  k_screen_table<<<nb, 256, 0, st>>>(w.count, w.V, w.gmean, w.mvec, w.c64, p.K, p.Kpad, p.D,
-                                     p.DPX, static_cast<_Float16*>(w.stab), w.hdr);
+  const float* tscale = p.dtype == SIL_FP8_E4M3 ? p.col_scale : nullptr;
+  k_screen_table<<<nb, 256, 0, st>>>(w.count, w.V, w.gmean, w.mvec, tscale, w.c64, p.K, p.Kpad,
+                                     p.D, p.DPX, static_cast<_Float16*>(w.stab),
+                                     tscale ? w.rtab : nullptr, w.hdr);
   return hipGetLastError();
 }
 

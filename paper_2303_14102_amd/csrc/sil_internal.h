@@ -119,6 +119,7 @@ struct WsLayout {
   // one-product screen (squared Euclidean with bf16 storage; empty otherwise)
   size_t stab;     // f16[Kpad*screen_stride(DPX)]  screen table
   size_t c64;      // f64[Kpad]      c_k in binary64
+  size_t rtab;     // f32[K*DPX]     fp8: the column scales times mu'_k (the exact score's table)
   size_t fblist;   // i32[N]         sorted positions of the rows left to the fallback
   size_t fbpart;   // f64[N/128]     per-workgroup sums of s_i of the fallback rows
   size_t total;
@@ -160,6 +161,7 @@ struct WsPtrs {
   double* gAB;
   void* stab;
   double* c64;
+  float* rtab;
   int32_t* fblist;
   double* fbpart;
 };

@@ -33,17 +33,22 @@ __device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) {
   return __uint_as_float(static_cast<uint32_t>(h) << 16);
 }
 
-// OCP FP8 E4M3 ("fn"): bias 7, no infinities, S.1111.111 is NaN, exponent 0 is subnormal.
+// OCP FP8 E4M3 ("fn": bias 7, no infinities, S.1111.111 is NaN, exponent 0 is subnormal), by
+// the hardware conversion: gfx950's v_cvt_[pk_]f32_fp8 read the OCP encoding, and decode all 256
+// codes to the values the format defines (checked bit for bit on the device, NaN codes and the
+// zero's sign included).
+typedef float f32x2_s __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float e4m3_to_f32(uint8_t q) {
-  const uint32_t sign = static_cast<uint32_t>(q & 0x80) << 24;
-  const uint32_t e = (q >> 3) & 15u;
-  const uint32_t m = q & 7u;
-  if (e == 15u && m == 7u) return __uint_as_float(0x7fc00000u);
-  if (e == 0u) {
-    const float v = static_cast<float>(m) * 0.001953125f;  // m/8 * 2^-6
-    return sign ? -v : v;
-  }
-  return __uint_as_float(sign | ((e + 120u) << 23) | (m << 20));
+  return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(q), 0);
+}
+// the four codes of a 32-bit word, lowest byte first
+__device__ __forceinline__ void e4m3x4_to_f32(uint32_t w, float* out) {
+  const f32x2_s lo = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w), false);
+  const f32x2_s hi = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w), true);
+  out[0] = lo[0];
+  out[1] = lo[1];
+  out[2] = hi[0];
+  out[3] = hi[1];
 }
 
 // Stored element as double; the fp8 code times its column scale is exact in binary64.
@@ -452,9 +457,13 @@ __device__ __forceinline__ void decode16(u32x4_s raw, const float* __restrict__ 
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < 16; ++e)
-      x[e] = static_cast<double>(e4m3_to_f32(static_cast<uint8_t>(raw[e >> 2] >> (8 * (e & 3))))) *
-             static_cast<double>(col_scale[c0 + e]);
+    for (int w = 0; w < 4; ++w) {
+      float f[4];
+      e4m3x4_to_f32(raw[w], f);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        x[4 * w + i] = static_cast<double>(f[i]) * static_cast<double>(col_scale[c0 + 4 * w + i]);
+    }
   }
 }
 
@@ -670,10 +679,10 @@ __device__ __forceinline__ void segreduce_row_body(
 
   auto decode = [&](chunk_t raw, double* x) __attribute__((always_inline)) {
     if constexpr (DT == SIL_FP8_E4M3) {
+      float f[4];
+      e4m3x4_to_f32(raw[0], f);
 #pragma unroll
-      for (int e = 0; e < E; ++e)
-        x[e] = static_cast<double>(e4m3_to_f32(static_cast<uint8_t>(raw[0] >> (8 * e)))) *
-               static_cast<double>(sc[e]);
+      for (int e = 0; e < E; ++e) x[e] = static_cast<double>(f[e]) * static_cast<double>(sc[e]);
       return;
     }
 #pragma unroll

@@ -410,3 +410,33 @@ def test_single_call_graph_replay(dev, form, products):
         assert abs(S_g.item() - S_ref) <= TOL_S_MEAN[form]
         # eager library work between replays, on another workspace
         sil.silhouette(X2, lab, k, "cosine", products=products, workspace=ws_other, check_status=True)
+
+
+def test_fp8_every_finite_code(dev):
+    """Every finite e4m3fn code (all 256 but the two NaN codes) passes through the library's
+    hardware decode: the cluster statistics match the oracle's (which decodes each code by the
+    format's definition) to binary64 rounding, and every s_i is within its bound."""
+    from paper_2303_14102_amd import binding as sil
+    codes_all = np.array([c for c in range(256) if c not in (0x7F, 0xFF)], dtype=np.uint8)
+    n, d, k = 2_032, 8, 5  # 254 codes x 8 columns, each code in every column
+    rng = np.random.default_rng(131)
+    Xc = np.empty((n, d), np.uint8)
+    for l in range(d):
+        Xc[:, l] = np.tile(np.roll(codes_all, 31 * l), n // len(codes_all))
+    labels = rng.integers(0, k, n).astype(np.int32)
+    cs = np.ldexp(1.0, rng.integers(-6, 4, d)).astype(np.float32)
+    q = torch.from_numpy(Xc).view(torch.float8_e4m3fn).to(dev)
+    sc = torch.from_numpy(cs).to(dev)
+    lab = torch.from_numpy(labels).to(dev)
+    count_g, V_g, psi_g = sil.cluster_stats(q, lab, k, col_scale=sc)
+    count, V, psi = oracle.cluster_stats(Xc, labels, k, col_scale=cs)
+    assert np.array_equal(count_g.cpu().numpy(), count)
+    u = 2.0 ** -53
+    tol = 2 * u * count.astype(np.float64)[:, None] ** 2 * np.abs(dequantised(Xc, cs)).max()
+    assert np.all(np.abs(V_g.cpu().numpy() - V) <= tol)
+    for products in (2, 3):
+        s, S = sil.silhouette(q, lab, k, products=products, col_scale=sc, check_status=True)
+        s_ref, S_ref, a, bb, _ = oracle.silhouette(Xc, labels, k, col_scale=cs, details=True)
+        bound = per_point_bound("fp8", products, "sqeuclid", True, dequantised(Xc, cs), labels, k, a, bb)
+        ds = np.abs(s.cpu().numpy().astype(np.float64) - s_ref)
+        assert np.all(ds <= bound) and abs(S.item() - S_ref) <= TOL_S_MEAN["fp8"]

@@ -1,5 +1,5 @@
-"""The one-product screen (squared Euclidean, bf16 storage, two products): every s_i within the
-two-product form's bound of the FP64 oracle and S within 1e-4, next to the plain two-product
+"""The one-product screen (squared Euclidean, bf16 or fp8 storage, two products): every s_i within
+the two-product form's bound of the FP64 oracle and S within 1e-4, next to the plain two-product
 sweep (SIL_FLAG_NO_SCREEN) on the same inputs.  Cases cover every screen depth class, K from 2
 (one 32-cluster block) to past a thousand, ragged N, singletons and blocks straddling clusters,
 and inputs built to send rows to the two-product fallback: exactly tied clusters (duplicated
@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from paper_2303_14102_amd import workloads as wl
-from parity_helpers import TOL_S_MEAN, per_point_bound
+from parity_helpers import TOL_S_MEAN, dequantised, per_point_bound, storage
 
 pytestmark = pytest.mark.gpu
 
@@ -26,27 +26,28 @@ def dev():
     return torch.device("cuda:0")
 
 
-def run_both(dev, X32, labels, K, euclid_approx=False, tag=""):
-    """Screen and plain two-product calls on bf16(X32); both checked against the oracle."""
+def run_both(dev, X32, labels, K, euclid_approx=False, tag="", form="bf16"):
+    """Screen and plain two-product calls on X32 stored bf16 (or fp8 e4m3 with column scales);
+    both checked against the oracle."""
     from paper_2303_14102_amd import _lib
     from paper_2303_14102_amd import binding as sil
-    Xq = wl.to_bf16(X32.to(dev))
+    Xq, sc, codes = storage(X32.to(dev), form)
     lab = labels.to(dev)
-    codes = wl.host_codes(Xq)
     lab_h = labels.numpy()
+    cs = None if sc is None else sc.cpu().numpy()
     metric = "euclid_approx" if euclid_approx else "sqeuclid"
-    s_ref, S_ref, a, bb, _ = oracle.silhouette(codes, lab_h, K, metric, details=True)
-    deq = (codes.astype(np.uint32) << 16).view(np.float32)
-    bound = per_point_bound("bf16", 2, metric, True, deq, lab_h, K, a, bb)
+    s_ref, S_ref, a, bb, _ = oracle.silhouette(codes, lab_h, K, metric, col_scale=cs, details=True)
+    bound = per_point_bound(form, 2, metric, True, dequantised(codes, cs), lab_h, K, a, bb)
     n, d = Xq.shape
     out = {}
     for screen in (True, False):
         flags = (_lib.SIL_FLAG_EUCLID_APPROX if euclid_approx else 0) | (0 if screen else _lib.SIL_FLAG_NO_SCREEN)
-        ws = sil.new_workspace(n, d, K, "sqeuclid", torch.bfloat16, flags, dev)
+        ws = sil.new_workspace(n, d, K, "sqeuclid", Xq.dtype, flags, dev)
         s = torch.full((n,), float("nan"), dtype=torch.float32, device=dev)
         S = torch.empty((), dtype=torch.float64, device=dev)
-        rc = _lib.load().silhouette_sqeuclid(sil._ptr(Xq), _lib.SIL_BF16, None, sil._ptr(lab), n, d, K, 2, flags,
-                                             sil._ptr(s), sil._ptr(S), sil._ptr(ws), ws.numel(), sil._stream(dev))
+        rc = _lib.load().silhouette_sqeuclid(sil._ptr(Xq), sil._dtype_code(Xq), sil._ptr(sc), sil._ptr(lab), n, d,
+                                             K, 2, flags, sil._ptr(s), sil._ptr(S), sil._ptr(ws), ws.numel(),
+                                             sil._stream(dev))
         _lib.check(rc, "silhouette_sqeuclid")
         torch.cuda.synchronize()
         assert sil.status(ws) == 0
@@ -56,7 +57,7 @@ def run_both(dev, X32, labels, K, euclid_approx=False, tag=""):
         print(f"  {tag} screen={screen}: S={S.item():.12f} ref={S_ref:.12f} |dS|={abs(S.item() - S_ref):.2e} "
               f"max|ds|={ds.max():.2e} max(|ds|/bound)={(ds / bound).max():.4f} fallback={fb}", flush=True)
         assert np.all(ds <= bound), f"{tag} screen={screen}: point {int((ds / bound).argmax())}"
-        assert abs(S.item() - S_ref) <= TOL_S_MEAN["bf16"]
+        assert abs(S.item() - S_ref) <= TOL_S_MEAN[form]
         out[screen] = (sv, S.item(), fb)
     return out
 
@@ -140,3 +141,28 @@ def test_screen_offset_data(dev):
     print("[screen] offset data", flush=True)
     out = run_both(dev, b.X + 300.0, b.labels, 60, tag="offset")
     print(f"  fallback rows: {out[True][2]}", flush=True)
+
+
+FP8_CASES = [
+    (9_999, 16, 40, 1, 121),
+    (20_011, 64, 100, 0, 122),
+    (30_007, 96, 257, 2, 123),
+    (40_009, 128, 1000, 1, 124),
+]
+
+
+@pytest.mark.parametrize("case", FP8_CASES, ids=lambda c: f"N{c[0]}-D{c[1]}-K{c[2]}")
+def test_screen_fp8_parity(dev, case):
+    # fp8 e4m3 storage: the codes enter the screen (exact in fp16), the table carries the scales
+    n, d, k, single, seed = case
+    print(f"[screen fp8] N={n} D={d} K={k}", flush=True)
+    b = wl.make_small(n, d, k, seed=seed, singletons=single)
+    out = run_both(dev, b.X, b.labels, k, tag=f"fp8-N{n}-D{d}-K{k}", form="fp8")
+    assert out[True][2] < n // 4
+
+
+def test_screen_fp8_unscreened_shapes(dev):
+    # D not a multiple of 8: the fp8 call runs the two-product sweep (no rows are listed)
+    b = wl.make_small(8_000, 20, 30, seed=125)
+    out = run_both(dev, b.X, b.labels, 30, tag="fp8-D20", form="fp8")
+    assert out[True][2] == 0
