@@ -257,7 +257,7 @@ def bench_backward(args, spec, X32, labels, dev):
         "S": S.item(),
         "roofline": {"bound": "hbm", "achieved": alg / (bwd_ms * 1e-3) / 1e9, "peak": PEAK["hbm"] / 1e9,
                      "unit": "GB/s", "frac": alg / (bwd_ms * 1e-3) / PEAK["hbm"], "traffic": None,
-                     "kernel": "kb_accum + kb_reduce + kb_dx",
+                     "kernel": "kb_alpha + kb_accum(_slice) + kb_reduce + kb_gtab + kb_dx(4)",
                      "algorithmic_bytes": alg,
                      "note": "per point: X read twice, dX written (12 D bytes), saves and label (16 B)"},
         "dX_norm": float(dX.double().norm()),

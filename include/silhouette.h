@@ -11,8 +11,9 @@
  *
  * Conventions for every entry point
  *  - Pointers named "device" are HIP device pointers; host pointers are marked "host".
- *  - X is row-major [N, D] in the storage given by `dtype` (sil_dtype).  labels is int32 [N]
- *    with values in [0, K) (0-based cluster ids; ids may be unused).
+ *  - X is row-major [N, D] in the storage given by `dtype` (sil_dtype), at a 16-byte aligned
+ *    device address (rows are read as 16-byte vectors; SIL_E_ARG otherwise).  labels is int32
+ *    [N] with values in [0, K) (0-based cluster ids; ids may be unused).
  *  - s (optional, may be NULL) receives s_i as float32 [N]; S receives the mean as one float64.
  *  - The caller owns every buffer, including the workspace `ws` (device, at least
  *    silhouette_workspace_bytes(...) bytes, 256-byte aligned).  The library never allocates or

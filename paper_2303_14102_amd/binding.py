@@ -38,6 +38,8 @@ def _check_inputs(X, labels, col_scale):
         raise ValueError("X and labels must be on the same GPU")
     if X.dim() != 2 or not X.is_contiguous():
         raise ValueError("X must be a contiguous [N, D] tensor")
+    if X.data_ptr() % 16:
+        raise ValueError("X must start at a 16-byte aligned address (a fresh tensor or X.clone())")
     if labels.dtype != torch.int32 or labels.shape != (X.shape[0],) or not labels.is_contiguous():
         raise ValueError("labels must be a contiguous int32 [N] tensor")
     if X.dtype == torch.float8_e4m3fn:

@@ -53,6 +53,8 @@ WsLayout make_layout(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dt
                      ? static_cast<size_t>(bwd_accum_workgroups(N)) * KW * 8
                      : 0);
   L.gAB = take(save ? KW * 8 : 0);
+  L.galpha = take(save ? static_cast<size_t>(N) * 16 : 0);
+  L.gtab = take(save ? (static_cast<size_t>(K) * L.DPX + K) * 4 : 0);
   // the one-product screen's regions whenever a call with this shape may take it
   const bool scr = screen_applies(metric, dtype, L.DPX, 2, flags);
   L.nsblk = scr ? ceil_div(N, screen_rows_per_block()) : 0;
@@ -92,6 +94,8 @@ WsPtrs carve(const WsLayout& L, void* ws) {
   w.save_n = reinterpret_cast<int32_t*>(b + L.save_n);
   w.gpart = reinterpret_cast<double*>(b + L.gpart);
   w.gAB = reinterpret_cast<double*>(b + L.gAB);
+  w.galpha = b + L.galpha;
+  w.gtab = reinterpret_cast<float*>(b + L.gtab);
   w.stab = b + L.stab;
   w.c64 = reinterpret_cast<double*>(b + L.c64);
   w.rtab = reinterpret_cast<float*>(b + L.rtab);
@@ -108,6 +112,7 @@ static int check_common(const void* X, int32_t dtype, const float* col_scale,
                         const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t metric,
                         const void* ws, size_t ws_bytes, int32_t flags, WsLayout* L) {
   if (!shape_ok(N, D, K) || !X || !labels) return SIL_E_ARG;
+  if (reinterpret_cast<uintptr_t>(X) & 15u) return SIL_E_ARG;  // rows are read as 16-byte vectors
   if (metric != SIL_SQEUCLID && metric != SIL_COSINE && metric != SIL_KL) return SIL_E_ARG;
   if (dtype != SIL_F32 && dtype != SIL_BF16 && dtype != SIL_FP8_E4M3) return SIL_E_DTYPE;
   if (dtype == SIL_FP8_E4M3 && !col_scale) return SIL_E_DTYPE;

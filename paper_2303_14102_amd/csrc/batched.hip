@@ -215,7 +215,7 @@ int silhouette_batched_plan(const sil_problem* problems, int32_t count, int32_t 
   if (flags & ~(SIL_FLAG_NO_CENTRE | SIL_FLAG_EUCLID_APPROX)) return SIL_E_ARG;
   for (int i = 0; i < count; ++i) {
     const sil_problem& u = problems[i];
-    if (!u.X || !u.labels || !u.S) return SIL_E_ARG;
+    if (!u.X || !u.labels || !u.S || (reinterpret_cast<uintptr_t>(u.X) & 15u)) return SIL_E_ARG;
     if (u.N < 1 || u.N > INT32_MAX || u.D < 1 || u.D > kBatchMaxD || u.K < 2 ||
         u.K > kLdsHistMaxK)
       return SIL_E_ARG;

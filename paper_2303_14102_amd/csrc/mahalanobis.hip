@@ -126,6 +126,7 @@ int silhouette_mahalanobis(const void* X, int32_t dtype, const float* col_scale,
                            const int32_t* labels, int64_t N, int32_t D, int32_t K, int32_t flags,
                            float* s, double* S, void* ws, size_t ws_bytes, void* stream) {
   if (!shape_ok(N, D, K) || !X || !L || !labels || !S) return SIL_E_ARG;
+  if (reinterpret_cast<uintptr_t>(X) & 15u) return SIL_E_ARG;
   if (flags & ~SIL_FLAG_NO_CENTRE) return SIL_E_ARG;
   if (dtype != SIL_F32 && dtype != SIL_BF16 && dtype != SIL_FP8_E4M3) return SIL_E_DTYPE;
   if (dtype == SIL_FP8_E4M3 && !col_scale) return SIL_E_DTYPE;

@@ -116,6 +116,8 @@ struct WsLayout {
   size_t save_n;   // int32[N]       neighbouring cluster id
   size_t gpart;    // f64[nwg*K*(D+1)] backward: per-workgroup partial A_k, B_k
   size_t gAB;      // f64[K*(D+1)]   backward: A_k (column D) and B_k
+  size_t galpha;   // 16 B [N]       backward: per row {own, neighbour, alpha_own, alpha_nbr}
+  size_t gtab;     // f32[K*DPX + K] backward: per-cluster terms of dX
   // one-product screen (squared Euclidean with bf16 storage; empty otherwise)
   size_t stab;     // f16[Kpad*screen_stride(DPX)]  screen table
   size_t c64;      // f64[Kpad]      c_k in binary64
@@ -159,6 +161,8 @@ struct WsPtrs {
   int32_t* save_n;
   double* gpart;
   double* gAB;
+  void* galpha;
+  float* gtab;
   void* stab;
   double* c64;
   float* rtab;

@@ -82,6 +82,9 @@ def test_host_argument_errors_launch_nothing(lib):
         # the approximate Euclidean form has no backward
         approx_save = _lib.SIL_FLAG_EUCLID_APPROX | _lib.SIL_FLAG_SAVE_FOR_GRAD
         assert fn(fake, 0, None, fake, 10, 4, 2, 0, approx_save, None, fake, ws, 1 << 30, None) == -1
+        # X at an address that is not 16-byte aligned
+        odd = ctypes.c_void_p(0x1004)
+        assert fn(odd, 0, None, fake, 10, 4, 2, 0, 0, None, fake, ws, 1 << 30, None) == -1
     # ... and is a squared Euclidean form
     assert lib.silhouette_cosine(fake, 0, None, fake, 10, 4, 2, 0, _lib.SIL_FLAG_EUCLID_APPROX, None, fake, ws,
                                  1 << 30, None) == -1
@@ -141,6 +144,7 @@ def test_mahalanobis_host_checks(lib):
     assert f(fake, 0, None, fake, fake, 10, 4, 2, 0, None, None, ws, 1 << 30, None) == -1   # S
     assert f(fake, 2, None, fake, fake, 10, 4, 2, 0, None, fake, ws, 1 << 30, None) == -2   # fp8 scale
     assert f(fake, 0, None, fake, fake, 10, 4, 2, 0, None, fake, ws, 64, None) == -7        # workspace
+    assert f(ctypes.c_void_p(0x1004), 0, None, fake, fake, 10, 4, 2, 0, None, fake, ws, 1 << 30, None) == -1
     sz = lib.silhouette_mahalanobis_workspace_bytes
     assert sz(1000, 8, 4, 0) >= 1000 * 8 * 4 + lib.silhouette_workspace_bytes(1000, 8, 4, 0, 0, 0)
     assert sz(0, 8, 4, 0) == 0
@@ -191,6 +195,7 @@ def test_batched_plan_host_checks(lib):
     assert plan([P(N=2**31)]) == -1
     assert plan([P(metric=2)]) == -1
     assert plan([P(X=0)]) == -1
+    assert plan([P(X=fake + 4)]) == -1                      # X not 16-byte aligned
     assert plan([P(labels=0)]) == -1
     assert plan([P(S=0)]) == -1
     assert plan([P(), P(dtype=_lib.SIL_BF16)]) == -2        # fp32 storage only

@@ -65,6 +65,40 @@ def test_gradient_accumulation_paths(dev, n, d, k, metric):
     assert rel_l2(g, ref) <= 1e-4
 
 
+# the two dX kernels: four columns per lane (D % 4 == 0, D > 128; at D = 132 lanes 33..63 idle)
+# and one column per lane (D = 201; and D = 256 when dX is only 4-byte aligned)
+@pytest.mark.parametrize("metric", ["sqeuclid", "cosine"])
+@pytest.mark.parametrize("n,d,k,offset", [(2500, 132, 9, 0), (2500, 201, 9, 0), (2500, 256, 9, 1)])
+def test_gradient_dx_forms(dev, metric, n, d, k, offset):
+    from paper_2303_14102_amd import _lib
+    from paper_2303_14102_amd import binding as sil
+    b = wl.make_small(n, d, k, seed=53 + d, singletons=1, sigma=1.2)
+    print(f"[bwd-dx] metric={metric} N={n} D={d} K={k} offset={offset}", flush=True)
+    lib = _lib.load()
+    flags = _lib.SIL_FLAG_SAVE_FOR_GRAD
+    m = 0 if metric == "sqeuclid" else 1
+    # dX at a 4-byte offset into its buffer when offset = 1 (X itself must be 16-byte aligned)
+    X = b.X.to(dev).contiguous()
+    gbuf = torch.zeros(n * d + offset, dtype=torch.float32, device=dev)
+    dX = gbuf[offset:].view(n, d)
+    lab = b.labels.to(dev)
+    ws = sil.new_workspace(n, d, k, metric, torch.float32, flags, dev)
+    S = torch.empty((), dtype=torch.float64, device=dev)
+    gS = torch.ones((), dtype=torch.float64, device=dev)
+    st = sil._stream(dev)
+    fwd = lib.silhouette_sqeuclid if m == 0 else lib.silhouette_cosine
+    bwd = lib.silhouette_sqeuclid_backward if m == 0 else lib.silhouette_cosine_backward
+    _lib.check(fwd(sil._ptr(X), 0, None, sil._ptr(lab), n, d, k, 0, flags, None, sil._ptr(S),
+                   sil._ptr(ws), ws.numel(), st), "forward")
+    _lib.check(bwd(sil._ptr(X), 0, None, sil._ptr(lab), n, d, k, flags, sil._ptr(gS), sil._ptr(dX),
+                   sil._ptr(ws), ws.numel(), st), "backward")
+    torch.cuda.synchronize()
+    ref = oracle.gradient(b.X.numpy(), b.labels.numpy(), k, metric)
+    err = rel_l2(dX.cpu().numpy().astype(np.float64), ref)
+    print(f"  rel_l2(dX)={err:.2e}", flush=True)
+    assert err <= 1e-4
+
+
 @pytest.mark.parametrize("metric", ["sqeuclid", "cosine"])
 def test_gradient_vs_finite_differences(dev, metric):
     # central differences (h = 1e-3) of the FP64 oracle's S on 64 sampled coordinates away from
@@ -116,4 +150,43 @@ def test_gradient_full_size_workload(dev):
     ref = oracle.gradient(Xh, b.labels.cpu().numpy(), spec.k, "sqeuclid")
     err = rel_l2(g, ref)
     print(f"  rel_l2(dX)={err:.2e}", flush=True)
+    assert err <= 1e-4
+
+
+def test_gradient_full_size_finite_differences(dev):
+    # the differentiation workload at its full size (N = 1e6, D = 256, K = 64) against central
+    # differences (h = 1e-3) of the FP64 oracle's S along 8 directions, each touching 8 sampled
+    # coordinates (distinct rows away from kinks, |a - b| > 0.2 max(a, b)) with signs +-1.
+    # Each difference of S is summed from the per-point differences s_j(X + hU) - s_j(X - hU),
+    # so the rounding of the two S values (sums of 1e6 terms) does not enter it.
+    from paper_2303_14102_amd import binding as sil
+    spec = wl.WORKLOADS["blobs-1m-d256-k64"]
+    b = wl.make_blobs(spec, dev)
+    print(f"[bwd-fd-full] {spec.name}", flush=True)
+    Xd = b.X.requires_grad_(True)
+    S = sil.SilhouetteFn.apply(Xd, b.labels, spec.k, "sqeuclid")
+    S.backward()
+    torch.cuda.synchronize()
+    g = Xd.grad.cpu().numpy().astype(np.float64)
+    X = b.X.detach().cpu().numpy().astype(np.float64)
+    lab = b.labels.cpu().numpy()
+    _, _, a, bb, _ = oracle.silhouette(X, lab, spec.k, details=True)
+    ok = np.flatnonzero(np.abs(a - bb) > 0.2 * np.maximum(a, bb))
+    rng = np.random.default_rng(17)
+    rows = rng.choice(ok, size=64, replace=False).reshape(8, 8)
+    cols = rng.integers(0, X.shape[1], size=(8, 8))
+    sign = rng.choice([-1.0, 1.0], size=(8, 8))
+    h = 1e-3
+    fd, pred = np.empty(8), np.empty(8)
+    for t in range(8):
+        Xp, Xm = X.copy(), X.copy()
+        Xp[rows[t], cols[t]] += h * sign[t]
+        Xm[rows[t], cols[t]] -= h * sign[t]
+        sp, _ = oracle.silhouette(Xp, lab, spec.k)
+        sm, _ = oracle.silhouette(Xm, lab, spec.k)
+        fd[t] = np.sum(sp - sm) / X.shape[0] / (2 * h)
+        pred[t] = np.sum(sign[t] * g[rows[t], cols[t]])
+        print(f"  direction {t}: fd={fd[t]:.6e} grad={pred[t]:.6e}", flush=True)
+    err = rel_l2(pred, fd)
+    print(f"  FD rel_l2={err:.2e}", flush=True)
     assert err <= 1e-4
