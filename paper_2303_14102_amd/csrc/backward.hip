@@ -20,7 +20,7 @@
 
 namespace sil {
 
-constexpr int kBwdWaves = 8;  // waves per workgroup of the accumulation kernel
+constexpr int kBwdWaves = 16;  // waves per workgroup of the accumulation kernels
 
 struct BwdArgs {
   const float* X;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void kb_accum_global(BwdArgs a) {
 // Squared Euclidean partials by column slice.  Workgroup b of the grid is row group b % nrg and
 // slice b / nrg: it accumulates columns 64 s .. 64 s + 63 (one per lane) of the rows of its
 // group, and slice 0 also the alphas themselves (A_k, slot 64).  Its LDS holds K x 65 values
-// instead of K x (D + 1), so several workgroups share a CU; every row is still read once in all.
+// instead of K x (D + 1): the form for K (D + 1) FP64 values beyond the LDS of one CU.
 constexpr int kBwdSlice = 64;
 __global__ __launch_bounds__(64 * kBwdWaves) void kb_accum_slice(BwdArgs a, int nrg) {
   extern __shared__ double sh[];  // [K * 65]
@@ -517,7 +517,9 @@ hipError_t launch_backward(const Problem& p, const WsLayout& L, const WsPtrs& w,
   const int64_t KW = static_cast<int64_t>(p.K) * (p.D + 1);
   const int nwg = bwd_accum_workgroups(p.N);
   const bool lds = bwd_fits_lds(p.K, p.D);
-  if (p.metric == SIL_SQEUCLID && bwd_fits_slices(p.K)) {
+  // whole rows per wave where the K (D + 1) partials fit in LDS; else 64-column slices (squared
+  // Euclidean) or global atomics
+  if (p.metric == SIL_SQEUCLID && !lds && bwd_fits_slices(p.K)) {
     const size_t shm = static_cast<size_t>(p.K) * (kBwdSlice + 1) * 8;
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_accum_slice),
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
