@@ -11,7 +11,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsilhouette.so")
+# SIL_LIBRARY names another build of the same library (the AddressSanitizer host build, for one)
+LIB_PATH = os.environ.get("SIL_LIBRARY") or os.path.join(HERE, "libsilhouette.so")
 
 SIL_OK = 0
 STATUS = {

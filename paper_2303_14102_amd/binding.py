@@ -6,6 +6,7 @@ torch supplies device memory and the current HIP stream; the library does all th
 from __future__ import annotations
 
 import ctypes
+import os
 from typing import Optional
 
 import torch
@@ -333,6 +334,8 @@ class BatchedSilhouette:
         plan = ctypes.c_void_p()
         lib = L.load()
         flags = (0 if centre else L.SIL_FLAG_NO_CENTRE) | (L.SIL_FLAG_EUCLID_APPROX if euclid_approx else 0)
+        self.flags = flags
+        self.tuned_from_cache = False
         L.check(lib.silhouette_batched_plan(arr, len(problems), flags, ctypes.byref(plan)),
                 "silhouette_batched_plan")
         self._plan = plan
@@ -347,11 +350,37 @@ class BatchedSilhouette:
         L.check(L.load().silhouette_batched_run(self._plan, *self._ws(), st), "silhouette_batched_run")
         return self.S
 
-    def tune(self) -> float:
-        """Autotune the persistent launch on these problems; returns its time in ms."""
+    def tune_key(self):
+        """(key, shape) of this plan in the tuner's cache (see tune_cache.plan_key)."""
+        from .tune_cache import plan_key
+        props = torch.cuda.get_device_properties(self.device)
+        return plan_key(props.gcnArchName, props.multi_processor_count, "f32", self.flags,
+                        [(m, X.shape[0], X.shape[1], K) for X, _, K, m in self.problems])
+
+    def tune(self, cache=None) -> float:
+        """Autotune the persistent launch on these problems; returns its time in ms.
+
+        cache (a path or a tune_cache.TuneCache): a plan whose signature is in the cache takes the
+        stored configuration without timing any launch (``self.tuned_from_cache`` is then True and
+        the stored time is returned); otherwise the tuner's choice is stored there."""
+        from .tune_cache import TuneCache
+        if isinstance(cache, (str, os.PathLike)):
+            cache = TuneCache(os.fspath(cache))
+        key = shape = None
+        if cache is not None:
+            key, shape = self.tune_key()
+            hit = cache.get(key)
+            if hit is not None:
+                self.set_config(**hit["config"])
+                self.run()  # as after tuning: statistics, tables and results in the workspace
+                self.tuned_from_cache = True
+                return hit["ms"]
         ms = ctypes.c_float()
         L.check(L.load().silhouette_batched_tune(self._plan, *self._ws(), _stream(self.device),
                                                  ctypes.byref(ms)), "silhouette_batched_tune")
+        self.tuned_from_cache = False
+        if cache is not None:
+            cache.put(key, self.config(), ms.value, shape)
         return ms.value
 
     def config(self) -> dict:

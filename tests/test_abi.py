@@ -202,6 +202,17 @@ def test_batched_plan_host_checks(lib):
     assert plan([P()], flags=_lib.SIL_FLAG_SAVE_FOR_GRAD) == -1
     assert plan([P()], flags=1 << 3) == -1                  # unknown flag bit
     assert lib.silhouette_batched_plan(None, 1, 0, ctypes.byref(ctypes.c_void_p())) == -1
+    # valid descriptors: without a GPU the plan fails at its device query (SIL_E_HIP) and frees
+    # what it built; with one it is created (nothing is launched) and freed here
+    arr = (_lib.SilProblem * 3)(P(), P(D=64, K=300), P(D=128, K=2, metric=1))
+    out = ctypes.c_void_p()
+    rc = lib.silhouette_batched_plan(arr, 3, 0, ctypes.byref(out))
+    assert rc in (0, -8)
+    if rc == 0:
+        assert lib.silhouette_batched_workspace_bytes(out) > 0
+        lib.silhouette_batched_free(out)
+    else:
+        assert out.value is None
     assert lib.silhouette_batched_workspace_bytes(None) == 0
     assert lib.silhouette_batched_run(None, ctypes.c_void_p(fake), 1, None) == -1
     assert lib.silhouette_batched_replay(None, None) == -1

@@ -27,6 +27,26 @@ def rel_l2(g, ref):
     return float(np.linalg.norm(g - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
+def kink_rows(X, labels, K, metric, rel=1e-4):
+    """Rows whose two nearest other clusters are within `rel` (relative) of each other in binary64
+    (mean distances from the oracle's cluster statistics, Eq.11 / Eq.18).  There s_i is a minimum
+    of two nearly equal terms: the fp32 forward may take either as the neighbour (its error in b
+    is below 1e-6 relative on these workloads), and dS/dx_i is a different one-sided derivative
+    for each, so such rows have no unique gradient to compare."""
+    count, V, psi = oracle.cluster_stats(X, labels, K, metric)
+    Xd = X.astype(np.float64)
+    nk = np.maximum(count, 1).astype(np.float64)
+    if metric == "cosine":
+        Z = Xd / np.linalg.norm(Xd, axis=1)[:, None]
+        d = 1.0 - Z @ (V / nk[:, None]).T
+    else:
+        d = (Xd * Xd).sum(1)[:, None] - 2.0 * Xd @ (V / nk[:, None]).T + (psi / nk)[None, :]
+    d[:, count == 0] = np.inf
+    d[np.arange(len(labels)), labels] = np.inf
+    two = np.partition(d, 1, axis=1)[:, :2]
+    return (two[:, 1] - two[:, 0]) <= rel * np.abs(two[:, 0])
+
+
 def gpu_grad(dev, X, labels, K, metric):
     from paper_2303_14102_amd import binding as sil
     Xd = X.to(dev).requires_grad_(True)
@@ -135,21 +155,26 @@ def test_gradient_flows_through_autograd(dev):
     assert rel_l2(Xd.grad.cpu().numpy().astype(np.float64), 3.0 * ref) <= 1e-4
 
 
-def test_gradient_full_size_workload(dev):
+@pytest.mark.parametrize("metric", ["sqeuclid", "cosine"])
+def test_gradient_full_size_workload(dev, metric):
     # the differentiation workload at its full size: N = 1e6 points, D = 256, K = 64
     from paper_2303_14102_amd import binding as sil
     spec = wl.WORKLOADS["blobs-1m-d256-k64"]
     b = wl.make_blobs(spec, dev)
-    print(f"[bwd-full] {spec.name}", flush=True)
+    print(f"[bwd-full] {spec.name} {metric}", flush=True)
     Xd = b.X.requires_grad_(True)
-    S = sil.SilhouetteFn.apply(Xd, b.labels, spec.k, "sqeuclid")
+    S = sil.SilhouetteFn.apply(Xd, b.labels, spec.k, metric)
     S.backward()
     torch.cuda.synchronize()
     g = Xd.grad.cpu().numpy().astype(np.float64)
     Xh = b.X.detach().cpu().numpy()
-    ref = oracle.gradient(Xh, b.labels.cpu().numpy(), spec.k, "sqeuclid")
-    err = rel_l2(g, ref)
-    print(f"  rel_l2(dX)={err:.2e}", flush=True)
+    lab = b.labels.cpu().numpy()
+    ref = oracle.gradient(Xh, lab, spec.k, metric)
+    kink = kink_rows(Xh, lab, spec.k, metric)
+    err_all, err = rel_l2(g, ref), rel_l2(g[~kink], ref[~kink])
+    print(f"  rel_l2(dX)={err:.2e} over {int((~kink).sum())} rows ({err_all:.2e} with the "
+          f"{int(kink.sum())} rows at a kink)", flush=True)
+    assert kink.mean() < 0.005
     assert err <= 1e-4
 
 

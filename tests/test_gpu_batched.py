@@ -124,6 +124,24 @@ def test_autotuner_choice(dev, mixed):
     check_against_oracle(batch, expect, "tuned, run")
 
 
+def test_tune_cache(dev, mixed, tmp_path):
+    # the first plan is tuned and its choice stored; a second plan of the same shape takes it from
+    # the cache without timing launches, and its results still match the oracle
+    from paper_2303_14102_amd import BatchedSilhouette
+    probs, _, expect = mixed
+    path = str(tmp_path / "tune.json")
+    first = BatchedSilhouette(probs)
+    ms = first.tune(cache=path)
+    assert not first.tuned_from_cache and ms > 0
+    cfg = first.config()
+    first.close()
+    second = BatchedSilhouette(probs)
+    assert second.tune(cache=path) == ms
+    assert second.tuned_from_cache and second.config() == cfg
+    check_against_oracle(second, expect, f"cached {cfg}")
+    second.close()
+
+
 def test_graph_capture_and_replay(dev, mixed):
     from paper_2303_14102_amd import BatchedSilhouette
     from paper_2303_14102_amd import binding as sil
