@@ -38,15 +38,16 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, variant):
     """HBM bytes per launch of `kernel` on `workload` from the committed counter summary, or None
-    when it is missing or the kernel sources changed since the counters were taken."""
+    when it is missing, was taken on another form (variant: storage/metric/products, e.g.
+    "bf16/sqeuclid/p2") or the kernel sources changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != kernel_source_hash():
+    if t.get("source_hash") != kernel_source_hash() or t.get("variant") != variant:
         return None
     e = t.get("kernels", {}).get(f"{kernel}@{workload}")
     return None if e is None else e.get("hbm_bytes_per_launch")
@@ -743,6 +744,7 @@ def main():
     screened = (args.form in ("bf16", "fp8") and args.metric == "sqeuclid" and args.products == 2
                 and spec.d <= 128 and (args.form == "bf16" or spec.d % 8 == 0) and not args.no_screen)
     issued = useful * prods
+    variant = f"{args.form}/{args.metric}/p{args.products}" + ("/noscreen" if args.no_screen else "")
     note = ("achieved = 2*N*D*K useful flops / mean duration of the fused kernel; "
             "issued_frac counts every split product")
     if screened:
@@ -759,7 +761,7 @@ def main():
                          "kernels": ["k_main_screen", "k_main_fallback", "k_fb_sum"]}
     out["roofline"] = {"bound": "mfma", "achieved": useful / t_main / 1e12, "peak": peak / 1e12,
                        "unit": "TFLOP/s", "frac": useful / t_main / peak,
-                       "traffic": measured_traffic(kname, spec.name),
+                       "traffic": measured_traffic(kname, spec.name, variant),
                        "kernel": kname,
                        "issued_frac": issued / t_main / peak,
                        "note": note}
@@ -767,7 +769,7 @@ def main():
     out["stats_pass"] = {"bound": "hbm", "algorithmic_bytes": stats_bytes,
                          "achieved_GBps": stats_bytes / (phases[0] * 1e-3) / 1e9,
                          "frac": stats_bytes / (phases[0] * 1e-3) / PEAK["hbm"],
-                         "traffic": measured_traffic(stats_kernel(args, spec), spec.name)}
+                         "traffic": measured_traffic(stats_kernel(args, spec), spec.name, variant)}
 
     if args.calibrate:
         # a plain device copy of known size: the reference for the FETCH_SIZE / WRITE_SIZE counters
