@@ -340,9 +340,10 @@ typedef struct sil_plan sil_plan;
 /*
  * Validates `count` problem descriptors (host array, copied) and creates a plan on the current
  * device.  flags: SIL_FLAG_NO_CENTRE and SIL_FLAG_EUCLID_APPROX bits (both apply to the squared
- * Euclidean problems only).  On
- * success *plan is set (free it with silhouette_batched_free); otherwise *plan is NULL and a
- * sil_status is returned.
+ * Euclidean problems only).  Problems with the same X pointer, N, D and metric (the labelings of
+ * one data set) are evaluated together by default: the fused kernel reads each block of rows
+ * once for all of them, and they share the first one's centring vector.  On success *plan is set
+ * (free it with silhouette_batched_free); otherwise *plan is NULL and a sil_status is returned.
  */
 int silhouette_batched_plan(const sil_problem* problems, int32_t count, int32_t flags,
                             sil_plan** plan);
@@ -363,8 +364,9 @@ int silhouette_batched_run(sil_plan* plan, void* ws, size_t ws_bytes, void* stre
  * Autotuner: runs the batch once, then times the persistent launch (events on `stream`, which it
  * synchronises) over the plan's own problems while it varies, one at a time, the rows per work
  * item of the shallow GEMM depths (128 or 256), the persistent grid (1, 2 or 3 workgroups per
- * CU), the items taken per queue access (1, 2, 4) and the queue order (costliest first, or
- * problem order), keeping each change that is faster.  Ends with a run in the chosen
+ * CU), the items taken per queue access (1, 2, 4), the queue order (costliest first, or
+ * problem order) and whether problems sharing X read their rows together, keeping each change
+ * that is faster.  Ends with a run in the chosen
  * configuration; *best_ms (host, may be NULL) receives the persistent launch's time.  Drops a
  * captured graph.
  */
@@ -373,13 +375,16 @@ int silhouette_batched_tune(sil_plan* plan, void* ws, size_t ws_bytes, void* str
 
 /* The chosen configuration into out[0..5] (host): workgroups of the persistent grid, items per
  * queue access, queue order (0 costliest first, 1 problem order), and 32-row blocks per wave
- * for GEMM depths 16, 24, 32 (D up to 16, 17..24, 25..32).  len must be >= 6. */
+ * for GEMM depths 16, 24, 32 (D up to 16, 17..24, 25..32); with len >= 7 also out[6], 1 when
+ * problems that share their X (same pointer, N, D and metric: the labelings of one data set) are
+ * evaluated together, reading the rows once for all of them (the default), 0 when each problem
+ * reads its own.  len must be >= 6. */
 int silhouette_batched_config(const sil_plan* plan, int32_t* out, int32_t len);
 
-/* Sets the configuration from cfg[0..5] (host, same layout as silhouette_batched_config), for
- * instance one saved from an earlier tuning: grid 1..65536, items per access 1..64, order 0 or 1,
- * blocks per wave 1 or 2.  SIL_E_ARG for values out of range.  Drops a captured graph; the next
- * run uploads the descriptors again. */
+/* Sets the configuration from cfg[0..5] (and cfg[6] when len >= 7; host, same layout as
+ * silhouette_batched_config), for instance one saved from an earlier tuning: grid 1..65536,
+ * items per access 1..64, order 0 or 1, blocks per wave 1 or 2, shared rows 0 or 1.  SIL_E_ARG
+ * for values out of range.  Drops a captured graph; the next run uploads the descriptors again. */
 int silhouette_batched_set_config(sil_plan* plan, const int32_t* cfg, int32_t len);
 
 /*

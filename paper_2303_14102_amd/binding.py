@@ -384,17 +384,20 @@ class BatchedSilhouette:
         return ms.value
 
     def config(self) -> dict:
-        out = (ctypes.c_int32 * 6)()
-        L.check(L.load().silhouette_batched_config(self._plan, out, 6), "silhouette_batched_config")
+        out = (ctypes.c_int32 * 7)()
+        L.check(L.load().silhouette_batched_config(self._plan, out, 7), "silhouette_batched_config")
         return {"grid": out[0], "grab": out[1], "order": ("cost", "problem")[out[2]],
-                "rows_per_item": {16: 128 * out[3], 24: 128 * out[4], 32: 128 * out[5]}}
+                "rows_per_item": {16: 128 * out[3], 24: 128 * out[4], 32: 128 * out[5]},
+                "share_x": bool(out[6])}
 
-    def set_config(self, grid: int, grab: int = 1, order: str = "cost", rows_per_item=None):
-        """Pin the launch configuration (rows_per_item: {16|24|32: 128 or 256}, keyed by GEMM depth)."""
+    def set_config(self, grid: int, grab: int = 1, order: str = "cost", rows_per_item=None,
+                   share_x: bool = True):
+        """Pin the launch configuration (rows_per_item: {16|24|32: 128 or 256}, keyed by GEMM depth;
+        share_x: problems with the same X, D and metric read their rows once for all of them)."""
         rpi = {16: 128, 24: 128, 32: 128, **(rows_per_item or {})}
-        cfg = (ctypes.c_int32 * 6)(grid, grab, {"cost": 0, "problem": 1}[order], rpi[16] // 128,
-                                   rpi[24] // 128, rpi[32] // 128)
-        L.check(L.load().silhouette_batched_set_config(self._plan, cfg, 6), "silhouette_batched_set_config")
+        cfg = (ctypes.c_int32 * 7)(grid, grab, {"cost": 0, "problem": 1}[order], rpi[16] // 128,
+                                   rpi[24] // 128, rpi[32] // 128, int(bool(share_x)))
+        L.check(L.load().silhouette_batched_set_config(self._plan, cfg, 7), "silhouette_batched_set_config")
 
     def capture(self, stream: torch.cuda.Stream):
         """Capture one run into a hipGraph on `stream` (a non-default stream)."""

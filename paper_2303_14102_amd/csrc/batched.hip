@@ -29,6 +29,7 @@ struct sil_plan {
   std::vector<int32_t> nb;      // 32-row blocks per wave in the fused kernel, per problem
   int32_t flags = 0;
   int32_t grid = 0, grab = 1, order_mode = 0;
+  int32_t share_x = 1;          // group problems that share X (see BatchProblem::grp_n)
   int32_t cus = 0;
   size_t hdr_bytes = 0, total = 0;
   // batch header layout (offsets from the workspace base)
@@ -50,10 +51,32 @@ double item_cost(const WsLayout& L, int nb) {
   return static_cast<double>(L.Kpad) * static_cast<double>(L.DPX) * nb;
 }
 
+// Group leader of every problem: the first problem with the same X, N, D, metric, flags and row
+// blocks per wave when X is shared, else the problem itself.
+std::vector<int> group_leaders(const sil_plan* P) {
+  const int n = static_cast<int>(P->prob.size());
+  std::vector<int> lead(n);
+  for (int i = 0; i < n; ++i) {
+    lead[i] = i;
+    if (!P->share_x) continue;
+    const sil_problem& u = P->prob[i];
+    for (int j = 0; j < i; ++j) {
+      const sil_problem& v = P->prob[j];
+      if (lead[j] == j && v.X == u.X && v.N == u.N && v.D == u.D && v.metric == u.metric &&
+          P->nb[j] == P->nb[i]) {
+        lead[i] = j;
+        break;
+      }
+    }
+  }
+  return lead;
+}
+
 // Build the header (descriptors, prefixes, queue order) for workspace `ws` into the staging
 // buffer and the launch description; returns the bytes to upload.
 size_t build_header(sil_plan* P, void* ws) {
   const int n = static_cast<int>(P->prob.size());
+  const std::vector<int> lead = group_leaders(P);
   uint8_t* base = static_cast<uint8_t*>(ws);
   std::memset(P->staging, 0, P->hdr_bytes);
   BatchProblem* bp = reinterpret_cast<BatchProblem*>(P->staging + P->o_prob);
@@ -117,14 +140,34 @@ size_t build_header(sil_plan* P, void* ws) {
     c[BP_RED1] = q.red_n1;
     c[BP_RED2] = 1;
     c[BP_POISON] = q.s ? ceil_div(L.N, kPoisonPerItem) : 0;
+    q.grp_n = 1;
+    q.grp_next = -1;
+  }
+  // groups: members take the leader's centring vector (so that every member's tables fit the
+  // rows as the leader centres them) and leave their fused-kernel items to the leader
+  std::vector<double> cost(n);
+  for (int i = 0; i < n; ++i) cost[i] = item_cost(P->L[i], P->nb[i]);
+  std::vector<int> last(n);
+  for (int i = 0; i < n; ++i) last[i] = i;
+  for (int i = 0; i < n; ++i) {
+    const int l = lead[i];
+    if (l == i) continue;
+    const WsPtrs wl = carve(P->L[l], base + P->off[l]);
+    bp[i].gmean = wl.gmean;
+    bp[i].mvec = wl.mvec;
+    cnt[static_cast<size_t>(i) * BP_COUNT + BP_GMEAN] = 0;
+    cnt[static_cast<size_t>(i) * BP_COUNT + BP_MAIN] = 0;
+    bp[last[l]].grp_next = i;
+    last[l] = i;
+    bp[l].grp_n += 1;
+    cost[l] += cost[i];
   }
   // queue order of the persistent kernel: costliest items first, or problem order
   std::vector<int32_t> ord(n);
   std::iota(ord.begin(), ord.end(), 0);
   if (P->order_mode == 0)
-    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
-      return item_cost(P->L[a], P->nb[a]) > item_cost(P->L[b], P->nb[b]);
-    });
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
   for (int j = 0; j < n; ++j) order[j] = ord[j];
   BatchLaunch& B = P->launch;
   for (int ph = 0; ph < BP_COUNT; ++ph) {
@@ -330,6 +373,12 @@ int silhouette_batched_tune(sil_plan* plan, void* ws, size_t ws_bytes, void* str
     rc = consider([&] { plan->order_mode = 1; }, [&] { plan->order_mode = old; });
     if (rc) return rc;
   }
+  // problems that share X: one pass over the rows for all of them, or one per problem
+  {
+    const int old = plan->share_x;
+    rc = consider([&] { plan->share_x = !old; }, [&] { plan->share_x = old; });
+    if (rc) return rc;
+  }
   if (best_ms) *best_ms = best;
   // leave the workspace consistent with the chosen configuration
   plan->uploaded_ws = nullptr;
@@ -345,6 +394,7 @@ int silhouette_batched_config(const sil_plan* plan, int32_t* out, int32_t len) {
   for (size_t i = 0; i < plan->prob.size(); ++i)
     for (int c = 0; c < 3; ++c)
       if (plan->L[i].DPX == kShallowDepths[c]) out[3 + c] = plan->nb[i];
+  if (len >= 7) out[6] = plan->share_x;
   return SIL_OK;
 }
 
@@ -354,9 +404,11 @@ int silhouette_batched_set_config(sil_plan* plan, const int32_t* cfg, int32_t le
     return SIL_E_ARG;
   for (int c = 0; c < 3; ++c)
     if (cfg[3 + c] < 1 || cfg[3 + c] > 2) return SIL_E_ARG;
+  if (len >= 7 && (cfg[6] < 0 || cfg[6] > 1)) return SIL_E_ARG;
   plan->grid = cfg[0];
   plan->grab = cfg[1];
   plan->order_mode = cfg[2];
+  if (len >= 7) plan->share_x = cfg[6];
   for (size_t i = 0; i < plan->prob.size(); ++i) {
     plan->nb[i] = 1;
     for (int c = 0; c < 3; ++c)

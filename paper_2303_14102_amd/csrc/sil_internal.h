@@ -292,6 +292,11 @@ struct BatchProblem {
   int64_t N;
   int32_t D, DPX, K, Kpad;
   int32_t dtype, metric, flags, nb;  // nb: 32-row blocks per wave of the fused kernel
+  // problems that share their X (the same rows, D and metric: labelings of one data set) form a
+  // group led by its first problem: the fused kernel's items of the group are the leader's, in
+  // the rows' original order, and run every member over the same loaded rows.  grp_n: members
+  // (on the leader; 1 when not grouped), grp_next: the next member (-1 after the last).
+  int32_t grp_n, grp_next;
   int64_t nseg, nblocks, zero_words;
   int32_t Gv;        // lanes per row of the 16-byte statistics reduction, 0 for the generic one
   int32_t rowch;     // bytes per lane of the whole-wave row reduction, 0 when not used

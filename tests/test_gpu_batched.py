@@ -193,6 +193,117 @@ def test_batched_euclid_approx(dev, mixed):
     batch.close()
 
 
+# Problems that share X (labelings of one data set) run as a group: one pass over the rows for
+# all its members.  Two data sets (D = 32: depth 32, where two row blocks per wave are possible;
+# D = 100: depth 128, ragged N), several labelings each (K from 2 to 300, singletons, a random
+# labeling), a standalone problem between them, and a cosine labeling of the first data set
+# (another metric: its own group).
+def make_group_problems(dev):
+    rng = np.random.default_rng(64)
+    a = wl.make_small(5_003, 32, 40, seed=61, singletons=1)
+    b = wl.make_small(3_001, 100, 12, seed=62)
+    c = wl.make_small(2_000, 16, 9, seed=63)
+    la, lb = a.labels.numpy(), b.labels.numpy()
+    labs = [
+        ("a", la, 40, "sqeuclid"),
+        ("a", wl.ksweep_labels(la, 40, 7, 0.05, rng), 7, "sqeuclid"),
+        ("c", c.labels.numpy(), 9, "sqeuclid"),
+        ("a", rng.integers(0, 300, len(la)).astype(np.int32), 300, "sqeuclid"),
+        ("a", la, 40, "cosine"),
+        ("b", lb, 12, "cosine"),
+        ("b", wl.ksweep_labels(lb, 12, 3, 0.02, rng), 3, "cosine"),
+        ("b", rng.integers(0, 2, len(lb)).astype(np.int32), 2, "cosine"),
+    ]
+    X = {"a": a.X, "b": b.X, "c": c.X}
+    Xd = {k: v.to(dev) for k, v in X.items()}
+    probs, refs = [], []
+    for name, lab, k, metric in labs:
+        probs.append((Xd[name], torch.from_numpy(np.ascontiguousarray(lab)).to(dev), k, metric))
+        refs.append((X[name].numpy(), lab, k, metric))
+    return probs, refs
+
+
+@pytest.fixture(scope="module")
+def grouped(dev):
+    probs, refs = make_group_problems(dev)
+    expect = []
+    for X, lab, k, metric in refs:
+        s_ref, S_ref, a, b, _ = oracle.silhouette(X, lab, k, metric, details=True)
+        bound = per_point_bound("f32", 0, metric, True, X, lab, k, a, b)
+        expect.append((s_ref, S_ref, bound))
+    return probs, refs, expect
+
+
+@pytest.mark.parametrize("share", [True, False])
+@pytest.mark.parametrize("cfg", [dict(grid=512, grab=1, order="cost"),
+                                 dict(grid=7, grab=3, order="problem", rows_per_item={32: 256})],
+                         ids=["g512", "g7-rows256"])
+def test_shared_rows_groups(dev, grouped, cfg, share):
+    from paper_2303_14102_amd import BatchedSilhouette
+    probs, _, expect = grouped
+    print(f"[batched-groups] share_x={share} {cfg}", flush=True)
+    batch = BatchedSilhouette(probs)
+    batch.set_config(**cfg, share_x=share)
+    assert batch.config()["share_x"] == share
+    batch.run()
+    torch.cuda.synchronize()
+    assert batch.status() == [0] * len(probs)
+    S = batch.S.cpu().numpy()
+    for i, (s_ref, S_ref, bound) in enumerate(expect):
+        ds = np.abs(batch.s[i].cpu().numpy().astype(np.float64) - s_ref)
+        assert np.all(ds <= bound), f"problem {i}: point {int((ds / bound).argmax())}"
+        assert abs(S[i] - S_ref) <= TOL_S_MEAN["f32"], f"problem {i}: S {S[i]} vs {S_ref}"
+    batch.close()
+
+
+def test_shared_rows_match_separate_passes(dev, grouped):
+    # the same per-row arithmetic either way, but for two roundings: a member's tables are
+    # centred with the leader's vector (its FP64 sum runs over other clusters in another order,
+    # so a table entry can round to the neighbouring fp32 value), and a member's cosine a-path
+    # starts from the stored z = x / |x| where the prologue may fuse that product into its first
+    # difference (measured: squared Euclidean identical, cosine members |dS| <= 8.4e-10)
+    from paper_2303_14102_amd import BatchedSilhouette
+    probs, _, _ = grouped
+    out = []
+    for share in (True, False):
+        batch = BatchedSilhouette(probs)
+        batch.set_config(grid=512, share_x=share)
+        batch.run()
+        torch.cuda.synchronize()
+        out.append((batch.S.cpu().numpy(), [s.cpu().numpy() for s in batch.s]))
+        batch.close()
+    (S1, s1), (S0, s0) = out
+    dS = np.abs(S1 - S0)
+    ds = [float(np.abs(a.astype(np.float64) - b).max()) for a, b in zip(s1, s0)]
+    print(f"  |dS| per problem {dS}, max |ds| {ds}", flush=True)
+    assert np.all(dS <= 1e-9)
+    assert max(ds) <= 1e-6
+
+
+def test_errors_inside_a_group_are_isolated(dev):
+    # three labelings of one data set: the leader and the last member carry a label outside
+    # [0, K); the middle member, which takes the leader's centring vector, is still exact
+    from paper_2303_14102_amd import BatchedSilhouette
+    d = wl.make_small(3_000, 24, 8, seed=71)
+    X = d.X.to(dev)
+    lab = d.labels.numpy()
+    bad0, bad2 = lab.copy(), lab.copy()
+    bad0[5] = 8
+    bad2[2_999] = -2
+    probs = [(X, torch.from_numpy(l).to(dev), 8, "sqeuclid") for l in (bad0, lab, bad2)]
+    batch = BatchedSilhouette(probs)
+    batch.run()
+    torch.cuda.synchronize()
+    assert batch.status() == [-3, 0, -3]  # SIL_E_LABEL
+    S = batch.S.cpu().numpy()
+    assert np.isnan(S[0]) and np.isnan(S[2])
+    s_ref, S_ref, a, b, _ = oracle.silhouette(d.X.numpy(), lab, 8, details=True)
+    bound = per_point_bound("f32", 0, "sqeuclid", True, d.X.numpy(), lab, 8, a, b)
+    ds = np.abs(batch.s[1].cpu().numpy().astype(np.float64) - s_ref)
+    assert np.all(ds <= bound) and abs(S[1] - S_ref) <= TOL_S_MEAN["f32"]
+    batch.close()
+
+
 def test_error_in_one_problem_is_isolated(dev):
     from paper_2303_14102_amd import BatchedSilhouette
     good = wl.make_small(2_000, 16, 10, seed=50)
