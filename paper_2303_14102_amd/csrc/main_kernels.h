@@ -295,7 +295,9 @@ __device__ __forceinline__ void load_f32w(const float* __restrict__ p, float* ou
 
 // VEC_ONLY: the caller guarantees D % W == 0 and 16-byte aligned column scales, so only the
 // whole-vector paths are compiled.
-template <int DT, int W, int NQ, int NB, int METRIC, bool RAW, bool VEC_ONLY = false, typename Emit>
+// ROWTERMS = false: only the emitted chunks; nrow and arow are left to the caller.
+template <int DT, int W, int NQ, int NB, int METRIC, bool RAW, bool VEC_ONLY = false,
+          bool ROWTERMS = true, typename Emit>
 __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B, int lane,
                                          float (&nrow)[NB], float (&arow)[NB], Emit&& emit) {
   constexpr int DPX = 2 * NQ * W;
@@ -359,6 +361,17 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
       }
       n2 += __shfl_xor(n2, 32, 64);
       inv = n2 > 0.0f ? 1.0f / sqrtf(n2) : 0.0f;
+    }
+    if constexpr (!ROWTERMS) {
+      static_assert(RAW, "without the row terms the prologue only hands over raw chunks");
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        float u[W];
+#pragma unroll
+        for (int e = 0; e < W; ++e) u[e] = ok ? xv[q][e] : 0.0f;
+        emit(nb, q, u);
+      }
+      continue;
     }
     float nx = 0.0f, ad = 0.0f;
 #pragma unroll

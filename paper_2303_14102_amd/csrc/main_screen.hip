@@ -76,6 +76,53 @@ __device__ __forceinline__ void screen_min_mixed(const f32x16_t& acc, float (&m1
   }
 }
 
+// fp8 codes: ||x'||^2 (x' = codes times column scales, centred) and the a-path term of each row,
+// from the rows' fp16 code fragments, formed after the sweep.  In the prologue, every chunk's
+// scales, centring values and own-cluster means would be loaded together beside the fragments
+// and spill; here the registers of the running minima are free.  Same arithmetic as the
+// prologue's row terms.
+template <int S, int NB>
+__device__ __forceinline__ void code_row_terms(const MainArgs& a, const Blocks<NB>& B, int lane,
+                                               const u32x4_t (&xf)[NB][S], float (&nrow)[NB],
+                                               float (&arow)[NB]) {
+  constexpr int DPX = 16 * S;
+  const int h = lane >> 5;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const bool ok = B.ok[nb];
+    const int32_t o = B.lab[nb];
+    const int64_t orow = static_cast<int64_t>(o >= 0 ? o : 0) * DPX;
+    float nx = 0.0f, ad = 0.0f;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int c0 = 16 * s + 8 * h;  // the chunk the prologue handed over as q = s
+      float sc[8], mv[8], at[8];
+      if (c0 < a.D) {
+        load_f32w<8>(a.col_scale + c0, sc);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sc[e] = 0.0f;
+      }
+      load_f32w<8>(a.mvec + c0, mv);
+      load_f32w<8>(a.atab + orow + c0, at);
+      const f16x8_t cf = __builtin_bit_cast(f16x8_t, xf[nb][s]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float x = static_cast<float>(cf[e]) * sc[e];
+        const float v = ok ? x - mv[e] : 0.0f;
+        nx = fmaf(v, v, nx);
+        const float dd = v - at[e];
+        ad = fmaf(dd, dd, ad);
+      }
+      if (s % 2 == 1) __builtin_amdgcn_sched_barrier(0);  // at most two chunks' loads in flight
+    }
+    nx += __shfl_xor(nx, 32, 64);
+    ad += __shfl_xor(ad, 32, 64);
+    nrow[nb] = nx;
+    arow[nb] = o >= 0 ? a.ascale[o] * (ad + a.avec[o]) : 0.0f;
+  }
+}
+
 // TC: clusters per table tile (64 or 128; a tile is one barrier and one ring stage).  NB: 32-row
 // blocks per wave: 2 (two workgroups per CU, one accumulator set) or 1 (three workgroups per CU,
 // two accumulator sets alternating between the tile's two 32-cluster blocks, TC = 64).
@@ -128,7 +175,7 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
     amax[nb] = 0.0f;
     ncode[nb] = 0.0f;
   }
-  prologue<DT, 8, S, NB, SIL_SQEUCLID, true, CODES>(
+  prologue<DT, 8, S, NB, SIL_SQEUCLID, true, CODES, !CODES>(
       a, B, lane, nrow, arow, [&](int nb, int q, const float* v) __attribute__((always_inline)) {
         uint32_t w[4];
 #pragma unroll
@@ -266,6 +313,7 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
         lwin[nb * 32 + out_row(j, h)] = win;
       }
     }
+  if constexpr (CODES) code_row_terms<S, NB>(a, B, lane, xf, nrow, arow);
   __syncthreads();
 
   const float inv_scale = ldexpf(1.0f, -screen_exponent(
