@@ -506,6 +506,43 @@ __device__ __forceinline__ float min_over_half(float v) {
   return fminf(v, __int_as_float(o));
 }
 
+// min(keep, send of the partner lane) for a data-parallel lane move CTRL.
+template <int CTRL>
+__device__ __forceinline__ float dpp_min2(float keep, float send) {
+  const int o = __builtin_amdgcn_update_dpp(__float_as_int(send), __float_as_int(send), CTRL, 0xf,
+                                            0xf, false);
+  return fminf(keep, __int_as_float(o));
+}
+
+// Minimum over the 32 lanes of each half of the wave for each of a lane's 16 values, spread over
+// the lanes: lane c of a half ends with the minimum of value j = c >> 1 (lanes c and c ^ 1 both
+// hold it).  Each step pairs lanes that differ in one lane bit (bit 4: lane ^ 16; bit 3: the
+// mirror within 16 lanes; bit 2: the mirror within 8; bit 1: lane ^ 2), and each lane keeps the
+// half of its values that its bit selects, taking the minimum with what its partner sends for
+// that half; a last step with lane ^ 1 completes the minimum.  8 + 4 + 2 + 1 + 1 exchanges for
+// the 16 values, against 5 per value when every lane reduces all 16.
+__device__ __forceinline__ float min_scatter16(const float (&v)[16], int lane) {
+  const bool b4 = (lane & 16) != 0, b3 = (lane & 8) != 0, b2 = (lane & 4) != 0,
+             b1 = (lane & 2) != 0;
+  float a[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float keep = b4 ? v[i + 8] : v[i], send = b4 ? v[i] : v[i + 8];
+    const int o = __builtin_amdgcn_ds_swizzle(__float_as_int(send), 0x401f);  // lane ^ 16 in 32
+    a[i] = fminf(keep, __int_as_float(o));
+  }
+  float b[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    b[i] = dpp_min2<0x140>(b3 ? a[i + 4] : a[i], b3 ? a[i] : a[i + 4]);  // row_mirror
+  float c[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    c[i] = dpp_min2<0x141>(b2 ? b[i + 2] : b[i], b2 ? b[i] : b[i + 2]);  // row_half_mirror
+  const float d = dpp_min2<0x4e>(b1 ? c[1] : c[0], b1 ? c[0] : c[1]);  // quad_perm [2,3,0,1]
+  return dpp_min2<0xb1>(d, d);                                          // quad_perm [1,0,3,2]
+}
+
 // After the sweep: row minima across the 32 lanes of each half, then s_i per row (written to
 // the row's original index) and the workgroup's sum of s_i.
 template <int NB, int METRIC, bool SAVE>
@@ -515,7 +552,12 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Bloc
                                        float* lds_min, int32_t* lds_arg, double* lds_bsum) {
   const int h = lane >> 5, col = lane & 31;
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
+  for (int nb = 0; nb < NB; ++nb) {
+    if constexpr (!SAVE) {
+      const float m = min_scatter16(mn[nb], lane);
+      if ((col & 1) == 0) lds_min[nb * 32 + out_row(col >> 1, h)] = m;
+      continue;
+    }
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       if constexpr (SAVE) {  // minimum and its (lowest) cluster id
@@ -536,6 +578,7 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Bloc
         if constexpr (SAVE) lds_arg[nb * 32 + out_row(j, h)] = arg[nb][j];
       }
     }
+  }
   __syncthreads();
   double bsum = 0.0;
 #pragma unroll
