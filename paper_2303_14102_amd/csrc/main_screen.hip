@@ -76,6 +76,78 @@ __device__ __forceinline__ void screen_min_mixed(const f32x16_t& acc, float (&m1
   }
 }
 
+// Smallest and second smallest over the 32 lanes of each half of the wave, for each of a lane's
+// 16 rows, with the lane (column) of the smallest: the reduce-scatter of min_scatter16, each
+// exchange merging two partial results (first = the smaller first, second = the smaller of the
+// larger first and both seconds, column of the smaller first).  Lane c of a half ends with row
+// j = c >> 1 (lanes c and c ^ 1 hold the same result up to the column of an exact tie, where the
+// two firsts are equal and the row fails the screen's test anyway).
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ void top2_merge(float& k1, float& k2, int& kw, float r1, float r2,
+                                           int rw) {
+  const bool take = r1 < k1;
+  k2 = fminf(fmaxf(k1, r1), fminf(k2, r2));
+  kw = take ? rw : kw;
+  k1 = fminf(k1, r1);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void top2_step(float& k1, float& k2, int& kw, float s1, float s2, int sw) {
+  top2_merge(k1, k2, kw, __int_as_float(dpp_mov<CTRL>(__float_as_int(s1))),
+             __int_as_float(dpp_mov<CTRL>(__float_as_int(s2))), dpp_mov<CTRL>(sw));
+}
+
+__device__ __forceinline__ void top2_scatter16(const float (&m1)[16], const float (&m2)[16], int lane,
+                                               float& g1, float& g2, int& win) {
+  const int col = lane & 31;
+  const bool b4 = (lane & 16) != 0, b3 = (lane & 8) != 0, b2 = (lane & 4) != 0,
+             b1 = (lane & 2) != 0;
+  float a1[8], a2[8];
+  int aw[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {  // partner lane ^ 16: its column is known
+    a1[i] = b4 ? m1[i + 8] : m1[i];
+    a2[i] = b4 ? m2[i + 8] : m2[i];
+    aw[i] = col;
+    const float s1 = b4 ? m1[i] : m1[i + 8], s2 = b4 ? m2[i] : m2[i + 8];
+    top2_merge(a1[i], a2[i], aw[i],
+               __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(s1), 0x401f)),
+               __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(s2), 0x401f)),
+               col ^ 16);
+  }
+  float c1[4], c2[4];
+  int cw[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {  // row_mirror
+    c1[i] = b3 ? a1[i + 4] : a1[i];
+    c2[i] = b3 ? a2[i + 4] : a2[i];
+    cw[i] = b3 ? aw[i + 4] : aw[i];
+    top2_step<0x140>(c1[i], c2[i], cw[i], b3 ? a1[i] : a1[i + 4], b3 ? a2[i] : a2[i + 4],
+                     b3 ? aw[i] : aw[i + 4]);
+  }
+  float d1[2], d2[2];
+  int dw[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {  // row_half_mirror
+    d1[i] = b2 ? c1[i + 2] : c1[i];
+    d2[i] = b2 ? c2[i + 2] : c2[i];
+    dw[i] = b2 ? cw[i + 2] : cw[i];
+    top2_step<0x141>(d1[i], d2[i], dw[i], b2 ? c1[i] : c1[i + 2], b2 ? c2[i] : c2[i + 2],
+                     b2 ? cw[i] : cw[i + 2]);
+  }
+  g1 = b1 ? d1[1] : d1[0];  // quad_perm [2,3,0,1]
+  g2 = b1 ? d2[1] : d2[0];
+  win = b1 ? dw[1] : dw[0];
+  top2_step<0x4e>(g1, g2, win, b1 ? d1[0] : d1[1], b1 ? d2[0] : d2[1], b1 ? dw[0] : dw[1]);
+  const float e1 = g1, e2 = g2;  // quad_perm [1,0,3,2]
+  const int ew = win;
+  top2_step<0xb1>(g1, g2, win, e1, e2, ew);
+}
+
 // fp8 codes: ||x'||^2 (x' = codes times column scales, centred) and the a-path term of each row,
 // from the rows' fp16 code fragments, formed after the sweep.  In the prologue, every chunk's
 // scales, centring values and own-cluster means would be loaded together beside the fragments
@@ -298,21 +370,16 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
   float* lm2 = lds_m2 + wave * NB * 32;
   int32_t* lwin = lds_win + wave * NB * 32;
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const float v1 = m1[nb][j];
-      const float g1 = min_over_half(v1);
-      const uint64_t bal = __ballot(v1 == g1);
-      const uint32_t hb = h ? static_cast<uint32_t>(bal >> 32) : static_cast<uint32_t>(bal);
-      const int win = __builtin_ctz(hb);  // lowest lane of the half holding the smallest
-      const float g2 = min_over_half(col == win ? m2[nb][j] : v1);
-      if (col == 0) {
-        lm1[nb * 32 + out_row(j, h)] = g1;
-        lm2[nb * 32 + out_row(j, h)] = g2;
-        lwin[nb * 32 + out_row(j, h)] = win;
-      }
+  for (int nb = 0; nb < NB; ++nb) {
+    float g1, g2;
+    int win;
+    top2_scatter16(m1[nb], m2[nb], lane, g1, g2, win);
+    if ((col & 1) == 0) {
+      lm1[nb * 32 + out_row(col >> 1, h)] = g1;
+      lm2[nb * 32 + out_row(col >> 1, h)] = g2;
+      lwin[nb * 32 + out_row(col >> 1, h)] = win;
     }
+  }
   if constexpr (CODES) code_row_terms<S, NB>(a, B, lane, xf, nrow, arow);
   __syncthreads();
 
