@@ -579,7 +579,9 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Bloc
       }
     }
   }
-  __syncthreads();
+  // lds_min / lds_arg are this wave's own: the LDS completes one wave's operations in order, so
+  // the reads below see the writes above without a workgroup barrier
+  __builtin_amdgcn_wave_barrier();
   double bsum = 0.0;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {

@@ -381,7 +381,8 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
     }
   }
   if constexpr (CODES) code_row_terms<S, NB>(a, B, lane, xf, nrow, arow);
-  __syncthreads();
+  // lm1 / lm2 / lwin are this wave's own (the LDS completes one wave's operations in order)
+  __builtin_amdgcn_wave_barrier();
 
   const float inv_scale = ldexpf(1.0f, -screen_exponent(
       fmax(__longlong_as_double(static_cast<long long>(
