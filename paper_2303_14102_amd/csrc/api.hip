@@ -1,4 +1,6 @@
 // C ABI entry points: argument checks, workspace carving, the stream-ordered launch sequence.
+#include <algorithm>
+
 #include "sil_internal.h"
 
 namespace sil {
@@ -42,7 +44,11 @@ WsLayout make_layout(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dt
   L.atab = take(static_cast<size_t>(K) * L.DPX * 4);
   L.avec = take(static_cast<size_t>(K) * 4);
   L.ascale = take(static_cast<size_t>(K) * 4);
-  L.bpart = take(static_cast<size_t>(L.nblocks) * 8);
+  // the one-product screen's regions whenever a call with this shape may take it
+  const bool scr = screen_applies(metric, dtype, L.DPX, 2, flags);
+  L.nsblk = scr ? ceil_div(N, screen_rows_per_block()) : 0;
+  // block partials of S: one per workgroup of the fused kernel, one per wave for the screen
+  L.bpart = take(static_cast<size_t>(std::max<int64_t>(L.nblocks, L.nsblk * kMainWaves)) * 8);
   L.bpart2 = take(1024 * 8);
   const bool save = (flags & SIL_FLAG_SAVE_FOR_GRAD) != 0;
   L.save_a = take(save ? static_cast<size_t>(N) * 4 : 0);
@@ -55,9 +61,6 @@ WsLayout make_layout(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dt
   L.gAB = take(save ? KW * 8 : 0);
   L.galpha = take(save ? static_cast<size_t>(N) * 16 : 0);
   L.gtab = take(save ? (static_cast<size_t>(K) * L.DPX + K) * 4 : 0);
-  // the one-product screen's regions whenever a call with this shape may take it
-  const bool scr = screen_applies(metric, dtype, L.DPX, 2, flags);
-  L.nsblk = scr ? ceil_div(N, screen_rows_per_block()) : 0;
   L.stab = take(scr ? static_cast<size_t>(L.Kpad) * screen_stride(L.DPX) * 2 : 0);
   L.c64 = take(scr ? static_cast<size_t>(L.Kpad) * 8 : 0);
   L.rtab = take(scr && dtype == SIL_FP8_E4M3 ? static_cast<size_t>(K) * L.DPX * 4 : 0);
@@ -164,6 +167,7 @@ int run_forward(int32_t metric, const void* X, int32_t dtype, const float* col_s
   Problem p{X, col_scale, labels, N, D, L.DPX, K, L.Kpad, dtype, metric, products, flags, s, S,
             nblocks};
   p.screen = screen;
+  p.nred = screen ? L.nsblk * kMainWaves : 0;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int call = g_prof.on && g_prof.used < g_prof.cap ? g_prof.used++ : -1;
   prof_record(call, 0, st);

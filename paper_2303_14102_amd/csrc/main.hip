@@ -133,8 +133,9 @@ hipError_t launch_reduce(const Problem& p, const WsLayout& L, const WsPtrs& w, h
   (void)L;
   int64_t chunk;
   int32_t n1;
-  reduce_split(p.nblocks, &chunk, &n1);
-  k_reduce1<<<static_cast<unsigned>(n1), 1024, 0, st>>>(w.bpart, p.nblocks, chunk, w.bpart2);
+  const int64_t nred = p.nred ? p.nred : p.nblocks;
+  reduce_split(nred, &chunk, &n1);
+  k_reduce1<<<static_cast<unsigned>(n1), 1024, 0, st>>>(w.bpart, nred, chunk, w.bpart2);
   const double* extra =
       p.screen ? reinterpret_cast<const double*>(w.hdr + kHdrFallbackSumWord) : nullptr;
   k_reduce2<<<1, 1024, 0, st>>>(w.bpart2, n1, p.N, w.hdr, p.S, (p.assign || p.reduce_sum) ? 0 : 1,

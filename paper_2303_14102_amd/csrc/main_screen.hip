@@ -211,17 +211,15 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
   using R = Ring<1, RSS * 2, TC == 64 ? 3 : 2, TC>;
   constexpr int64_t ROWS = kMainWaves * NB * 32;
   // the ring's stages (separate arrays, so that the compiler tells the stage being read from the
-  // stages being filled); after the sweep the first stage holds the row minima (3 x 1 KB)
+  // stages being filled); the row minima have arrays of their own, so that a wave that is done
+  // with the sweep goes on to its finish while the others still read the ring
   __shared__ __attribute__((aligned(16))) uint8_t ring0[R::STAGE_BYTES];
   __shared__ __attribute__((aligned(16))) uint8_t ring1[R::STAGE_BYTES];
   __shared__ __attribute__((aligned(16))) uint8_t ring2[R::NSTAGE == 3 ? R::STAGE_BYTES : 16];
-  static_assert(R::STAGE_BYTES >= 3 * kMainWaves * NB * 32 * 4, "minima fit one stage");
-  float* lds_m1 = reinterpret_cast<float*>(ring0);
-  float* lds_m2 = lds_m1 + kMainWaves * NB * 32;
-  int32_t* lds_win = reinterpret_cast<int32_t*>(lds_m2 + kMainWaves * NB * 32);
+  __shared__ float lds_m1[kMainWaves * NB * 32];
+  __shared__ float lds_m2[kMainWaves * NB * 32];
+  __shared__ int32_t lds_win[kMainWaves * NB * 32];
   __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves * NB * 32];
-  __shared__ double lds_bsum[kMainWaves];
-  __shared__ int32_t lds_cnt[kMainWaves + 1];
 
   const int64_t wb = blockIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -363,9 +361,8 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
     });
     if (last_b1) epi(acc1, 2 * ntiles - 1, c1p);
   }
-  __syncthreads();
 
-  // ---- finish: both minima across the row's 32 lanes
+  // ---- finish: both minima across the row's 32 lanes (no workgroup barrier from here on)
   float* lm1 = lds_m1 + wave * NB * 32;
   float* lm2 = lds_m2 + wave * NB * 32;
   int32_t* lwin = lds_win + wave * NB * 32;
@@ -454,27 +451,14 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
   int nflag = 0;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) nflag += __popcll(fmask[nb]);
+  // one partial sum per wave (kMainWaves per workgroup), and each wave reserves its own list
+  // entries: no workgroup barrier after the sweep's
   for (int off = 1; off < 64; off <<= 1) bsum += __shfl_xor(bsum, off, 64);
-  if (lane == 0) {
-    lds_bsum[wave] = bsum;
-    lds_cnt[wave] = nflag;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    int c = 0;
-    for (int w = 0; w < kMainWaves; ++w) {
-      t += lds_bsum[w];
-      const int cw = lds_cnt[w];
-      lds_cnt[w] = c;  // the wave's offset within the workgroup's entries
-      c += cw;
-    }
-    a.bpart[wb] = t;
-    lds_cnt[kMainWaves] = c > 0 ? atomicAdd(sa.hdr + kHdrFallbackWord, c) : 0;
-  }
-  __syncthreads();
+  if (lane == 0) a.bpart[wb * kMainWaves + wave] = bsum;
   if (nflag > 0) {  // wave-uniform: the wave's marked rows, in position order
-    int at = lds_cnt[kMainWaves] + lds_cnt[wave];
+    int base = 0;
+    if (lane == 0) base = atomicAdd(sa.hdr + kHdrFallbackWord, nflag);
+    int at = __shfl(base, 0, 64);
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const uint64_t m = fmask[nb];
