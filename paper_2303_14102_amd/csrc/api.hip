@@ -47,8 +47,8 @@ WsLayout make_layout(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dt
   // the one-product screen's regions whenever a call with this shape may take it
   const bool scr = screen_applies(metric, dtype, L.DPX, 2, flags);
   L.nsblk = scr ? ceil_div(N, screen_rows_per_block()) : 0;
-  // block partials of S: one per workgroup of the fused kernel, one per wave for the screen
-  L.bpart = take(static_cast<size_t>(std::max<int64_t>(L.nblocks, L.nsblk * kMainWaves)) * 8);
+  // block partials of S: one per wave of the fused kernel (kMainWaves per row block)
+  L.bpart = take(static_cast<size_t>(std::max(L.nblocks, L.nsblk)) * kMainWaves * 8);
   L.bpart2 = take(1024 * 8);
   const bool save = (flags & SIL_FLAG_SAVE_FOR_GRAD) != 0;
   L.save_a = take(save ? static_cast<size_t>(N) * 4 : 0);
@@ -66,7 +66,7 @@ WsLayout make_layout(int64_t N, int32_t D, int32_t K, int32_t metric, int32_t dt
   L.rtab = take(scr && dtype == SIL_FP8_E4M3 ? static_cast<size_t>(K) * L.DPX * 4 : 0);
   L.fblist = take(scr ? static_cast<size_t>(N) * 4 : 0);
   // fallback workgroups take at least 128 list entries each
-  L.fbpart = take(scr ? static_cast<size_t>(ceil_div(N, kMainWaves * 32)) * 8 : 0);
+  L.fbpart = take(scr ? static_cast<size_t>(ceil_div(N, kMainWaves * 32)) * kMainWaves * 8 : 0);
   L.total = o;
   return L;
 }

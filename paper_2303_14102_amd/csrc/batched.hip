@@ -108,7 +108,7 @@ size_t build_header(sil_plan* P, void* ws) {
     q.zero_words = static_cast<int64_t>((L.perm - L.hdr) / 4);
     stats_lanes(L.D, SIL_F32, &q.Gv, &q.G, &q.E);
     q.rowch = u.metric == SIL_SQEUCLID ? row_chunk(L.D, SIL_F32) : 0;
-    reduce_split(q.nblocks, &q.red_chunk, &q.red_n1);
+    reduce_split(q.nblocks * kMainWaves, &q.red_chunk, &q.red_n1);  // one partial per wave
     q.hdr = w.hdr;
     q.count = w.count;
     q.offset = w.offset;

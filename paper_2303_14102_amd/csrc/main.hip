@@ -133,7 +133,7 @@ hipError_t launch_reduce(const Problem& p, const WsLayout& L, const WsPtrs& w, h
   (void)L;
   int64_t chunk;
   int32_t n1;
-  const int64_t nred = p.nred ? p.nred : p.nblocks;
+  const int64_t nred = p.nred ? p.nred : p.nblocks * kMainWaves;  // one partial per wave
   reduce_split(nred, &chunk, &n1);
   k_reduce1<<<static_cast<unsigned>(n1), 1024, 0, st>>>(w.bpart, nred, chunk, w.bpart2);
   const double* extra =
@@ -161,7 +161,7 @@ __device__ __forceinline__ const BatchProblem& batch_item_red(const BatchDev& b,
 __global__ __launch_bounds__(1024) void kb_red1(BatchDev b) {
   int64_t it;
   const BatchProblem& q = batch_item_red(b, BP_RED1, &it);
-  reduce1_body(q.bpart, q.nblocks, q.red_chunk, q.bpart2, it);
+  reduce1_body(q.bpart, q.nblocks * kMainWaves, q.red_chunk, q.bpart2, it);
 }
 
 __global__ __launch_bounds__(1024) void kb_red2(BatchDev b) {

@@ -131,7 +131,7 @@ template <int DPX, int NB, int METRIC>
 __device__ __forceinline__ void group_body(const BatchDev& b, int lead, int64_t wb,
                                            const RowPre<kBatchNBMax>& pre0, uint8_t* ring0,
                                            uint8_t* ring1, float* lds_min, int32_t* lds_arg,
-                                           int32_t* lds_lab, double* lds_bsum, int tid) {
+                                           int32_t* lds_lab, int tid) {
   constexpr int NQ = DPX / 8;
   constexpr int RS = table_stride(DPX, SIL_F32);
   using R = f32_ring<DPX, 2>;
@@ -221,7 +221,7 @@ __device__ __forceinline__ void group_body(const BatchDev& b, int lead, int64_t 
       pn = group_rows(qn, wb, wave, lane);
     }
     finish<NB, METRIC, false>(a, wb, B, wave, lane, mn, arg, nrow, arow, lds_min + wave * NB * 32,
-                              lds_arg + wave, lds_bsum);
+                              lds_arg + wave);
     if (jn < 0) break;
     j = jn;
     a = batch_args(b.prob[j]);
@@ -239,8 +239,7 @@ __device__ __forceinline__ void group_body(const BatchDev& b, int lead, int64_t 
 template <int METRIC>
 __device__ __forceinline__ void batch_body(const MainArgs& a, int DPX, int nb, int64_t wb,
                                            const RowPre<kBatchNBMax>& pre, uint8_t* r0,
-                                           uint8_t* r1, float* lmin, int32_t* larg, int32_t* llab,
-                                           double* lbsum, int tid) {
+                                           uint8_t* r1, float* lmin, int32_t* larg, int32_t* llab, int tid) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
 #define SIL_BODY(DP, NB)                                                                      \
   do {                                                                                        \
@@ -251,7 +250,7 @@ __device__ __forceinline__ void batch_body(const MainArgs& a, int DPX, int nb, i
       p.row[i] = pre.row[i];                                                                  \
       p.lab[i] = pre.lab[i];                                                                  \
     }                                                                                         \
-    main_f32_body<DP, NB, METRIC, false, 2>(a, wb, p, r0, r1, r1, lmin, larg, llab, lbsum, tid); \
+    main_f32_body<DP, NB, METRIC, false, 2>(a, wb, p, r0, r1, r1, lmin, larg, llab, tid); \
   } while (0)
   switch (DPX) {
     case 16:
@@ -285,8 +284,7 @@ __device__ __forceinline__ void batch_body(const MainArgs& a, int DPX, int nb, i
 template <int METRIC>
 __device__ __forceinline__ void batch_group(const BatchDev& b, int lead, int DPX, int nb, int64_t wb,
                                             const RowPre<kBatchNBMax>& pre, uint8_t* r0,
-                                            uint8_t* r1, float* lmin, int32_t* larg, int32_t* llab,
-                                            double* lbsum, int tid) {
+                                            uint8_t* r1, float* lmin, int32_t* larg, int32_t* llab, int tid) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const BatchProblem& q = b.prob[lead];
 #define SIL_GROUP(DP, NB)                                                                      \
@@ -294,7 +292,7 @@ __device__ __forceinline__ void batch_group(const BatchDev& b, int lead, int DPX
     issue_first<f32_ring<DP, 2>>(static_cast<const char*>(q.btab),                              \
                                  static_cast<int64_t>(q.Kpad) * table_stride(DP, SIL_F32) * 4,  \
                                  q.Kpad / kColTile, r0, r1, wave, lane);                        \
-    group_body<DP, NB, METRIC>(b, lead, wb, pre, r0, r1, lmin, larg, llab, lbsum, tid);         \
+    group_body<DP, NB, METRIC>(b, lead, wb, pre, r0, r1, lmin, larg, llab, tid);         \
   } while (0)
   switch (DPX) {
     case 16:
@@ -332,7 +330,6 @@ __global__ __launch_bounds__(256, 2) void k_main_f32_batched(BatchDev b, int32_t
   __shared__ float lds_min[kMainWaves * kBatchNBMax * 32];
   __shared__ int32_t lds_arg[kMainWaves];
   __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves * kBatchNBMax * 32];
-  __shared__ double lds_bsum[kMainWaves];
   __shared__ int32_t pre_items[kBatchMaxProblems + 1];
   __shared__ int32_t next_base;
 
@@ -374,16 +371,15 @@ __global__ __launch_bounds__(256, 2) void k_main_f32_batched(BatchDev b, int32_t
         const int lead = uniform(b.order[jc]);
         if (q.metric == SIL_SQEUCLID)
           batch_group<SIL_SQEUCLID>(b, lead, q.DPX, q.nb, wb, rows, ring0, ring1, lds_min,
-                                    lds_arg, lds_lab, lds_bsum, tid);
+                                    lds_arg, lds_lab, tid);
         else
           batch_group<SIL_COSINE>(b, lead, q.DPX, q.nb, wb, rows, ring0, ring1, lds_min, lds_arg,
-                                  lds_lab, lds_bsum, tid);
+                                  lds_lab, tid);
       } else if (q.metric == SIL_SQEUCLID) {
         batch_body<SIL_SQEUCLID>(a, q.DPX, q.nb, wb, rows, ring0, ring1, lds_min, lds_arg,
-                                 lds_lab, lds_bsum, tid);
+                                 lds_lab, tid);
       } else {
-        batch_body<SIL_COSINE>(a, q.DPX, q.nb, wb, rows, ring0, ring1, lds_min, lds_arg, lds_lab,
-                               lds_bsum, tid);
+        batch_body<SIL_COSINE>(a, q.DPX, q.nb, wb, rows, ring0, ring1, lds_min, lds_arg, lds_lab, tid);
       }
       rows = nrows;
       jc = jn;

@@ -544,12 +544,12 @@ __device__ __forceinline__ float min_scatter16(const float (&v)[16], int lane) {
 }
 
 // After the sweep: row minima across the 32 lanes of each half, then s_i per row (written to
-// the row's original index) and the workgroup's sum of s_i.
+// the row's original index) and each wave's sum of s_i (bpart[kMainWaves wb + wave]).
 template <int NB, int METRIC, bool SAVE>
 __device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Blocks<NB>& B, int wave, int lane,
                                        float (&mn)[NB][16], int32_t (&arg)[NB][16],
                                        const float (&nrow)[NB], const float (&arow)[NB],
-                                       float* lds_min, int32_t* lds_arg, double* lds_bsum) {
+                                       float* lds_min, int32_t* lds_arg) {
   const int h = lane >> 5, col = lane & 31;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
@@ -621,15 +621,9 @@ __device__ __forceinline__ void finish(const MainArgs& a, int64_t wb, const Bloc
     }
     bsum += static_cast<double>(s);
   }
+  // one partial sum per wave (kMainWaves per row block): no workgroup barrier in the finish
   for (int off = 1; off < 64; off <<= 1) bsum += __shfl_xor(bsum, off, 64);
-  if (lane == 0) lds_bsum[wave] = bsum;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < kMainWaves; ++w) t += lds_bsum[w];
-    a.bpart[wb] = t;
-  }
-  __syncthreads();  // lds_min / lds_bsum are reused by the next row block
+  if (lane == 0) a.bpart[wb * kMainWaves + wave] = bsum;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -737,8 +731,7 @@ template <int DPX, int NB, int P, int DT, int METRIC, bool SAVE, int TC = kColTi
 __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
                                                const RowPre<NB>& pre, uint8_t* ring0,
                                                uint8_t* ring1, uint8_t* ring2, float* lds_min,
-                                               int32_t* lds_arg, int32_t* lds_lab,
-                                               double* lds_bsum, int tid) {
+                                               int32_t* lds_arg, int32_t* lds_lab, int tid) {
   constexpr int S = DPX / 16;
   constexpr int NPC = P >= 2 ? 2 : 1;
   constexpr int RS = table_stride(DPX, SIL_BF16);
@@ -874,7 +867,7 @@ __device__ __forceinline__ void main_bf16_body(const MainArgs& a, int64_t wb,
 
   __syncthreads();
   finish<NB, METRIC, SAVE>(a, wb, B, wave, lane, mn, arg, nrow, arow, lds_min + wave * NB * 32,
-                           lds_arg + wave * ARGW, lds_bsum);
+                           lds_arg + wave * ARGW);
 }
 
 // One row block per workgroup; two workgroups share a CU, so that one's prologue and finish
@@ -892,7 +885,6 @@ __global__ __launch_bounds__(256, DPX > 128 ? 1 : (TC == 32 ? 3 : 2)) void k_mai
   __shared__ float lds_min[kMainWaves * NB * 32];
   __shared__ int32_t lds_arg[kMainWaves * (SAVE ? NB * 32 : 1)];
   __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves * NB * 32];
-  __shared__ double lds_bsum[kMainWaves];
 
   constexpr int64_t ROWS = kMainWaves * NB * 32;
   const int64_t wb = blockIdx.x;
@@ -901,7 +893,7 @@ __global__ __launch_bounds__(256, DPX > 128 ? 1 : (TC == 32 ? 3 : 2)) void k_mai
   issue_first<R>(static_cast<const char*>(a.btab), a.piece * 2, a.ntiles, ring0, ring1, wave, lane);
   const RowPre<NB> pre = fetch_rows<NB>(a, wb * ROWS + wave * NB * 32, lane);
   main_bf16_body<DPX, NB, P, DT, METRIC, SAVE, TC>(a, wb, pre, ring0, ring1, ring2, lds_min,
-                                                   lds_arg, lds_lab, lds_bsum, threadIdx.x);
+                                                   lds_arg, lds_lab, threadIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -912,8 +904,7 @@ __global__ __launch_bounds__(256, DPX > 128 ? 1 : (TC == 32 ? 3 : 2)) void k_mai
 // One row block (wb) of the fp32 kernel, given the wave's row ids and labels (pre) and with
 // the block's first table tiles already issued into the ring (f32_ring<DPX, NS_MAX>).  The LDS
 // buffers come from the caller: ring0..2 the table stages (ring2 unused with two stages),
-// lds_min/lds_lab [kMainWaves][NB*32], lds_arg [kMainWaves][SAVE ? NB*32 : 1], lds_bsum
-// [kMainWaves].  NS_MAX caps the ring at two stages where the caller provides only two.  tid
+// lds_min/lds_lab [kMainWaves][NB*32], lds_arg [kMainWaves][SAVE ? NB*32 : 1].  NS_MAX caps the ring at two stages where the caller provides only two.  tid
 // is the thread's index in the workgroup; a caller that runs the body in a loop passes it
 // through an opaque copy, so that the lane-dependent addresses are recomputed per block
 // instead of being kept live across the loop.
@@ -923,8 +914,7 @@ using f32_ring = Ring<1, table_stride(DPX, SIL_F32) * 4, NS_MAX>;
 template <int DPX, int NB, int METRIC, bool SAVE, int NS_MAX>
 __device__ __forceinline__ void main_f32_body(const MainArgs& a, int64_t wb, const RowPre<NB>& pre,
                                               uint8_t* ring0, uint8_t* ring1, uint8_t* ring2,
-                                              float* lds_min, int32_t* lds_arg, int32_t* lds_lab,
-                                              double* lds_bsum, int tid) {
+                                              float* lds_min, int32_t* lds_arg, int32_t* lds_lab, int tid) {
   constexpr int NQ = DPX / 8;
   constexpr int RS = table_stride(DPX, SIL_F32);
   using R = f32_ring<DPX, NS_MAX>;
@@ -1002,7 +992,7 @@ __device__ __forceinline__ void main_f32_body(const MainArgs& a, int64_t wb, con
 
   __syncthreads();
   finish<NB, METRIC, SAVE>(a, wb, B, wave, lane, mn, arg, nrow, arow, lds_min + wave * NB * 32,
-                           lds_arg + wave * ARGW, lds_bsum);
+                           lds_arg + wave * ARGW);
 }
 
 template <int DPX, int NB, int METRIC, bool SAVE>
@@ -1015,7 +1005,6 @@ __global__ __launch_bounds__(256, DPX > 128 ? 1 : 2) void k_main_f32(MainArgs a)
   __shared__ float lds_min[kMainWaves * NB * 32];
   __shared__ int32_t lds_arg[kMainWaves * (SAVE ? NB * 32 : 1)];
   __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves * NB * 32];
-  __shared__ double lds_bsum[kMainWaves];
   constexpr int64_t ROWS = kMainWaves * NB * 32;
   const int64_t wb = blockIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -1023,7 +1012,7 @@ __global__ __launch_bounds__(256, DPX > 128 ? 1 : 2) void k_main_f32(MainArgs a)
   issue_first<R>(static_cast<const char*>(a.btab), a.piece * 4, a.ntiles, ring0, ring1, wave, lane);
   const RowPre<NB> pre = fetch_rows<NB>(a, wb * ROWS + wave * NB * 32, lane);
   main_f32_body<DPX, NB, METRIC, SAVE, 3>(a, wb, pre, ring0, ring1, ring2, lds_min, lds_arg,
-                                          lds_lab, lds_bsum, threadIdx.x);
+                                          lds_lab, threadIdx.x);
 }
 
 }  // namespace sil

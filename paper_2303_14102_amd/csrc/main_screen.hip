@@ -488,7 +488,6 @@ __global__ __launch_bounds__(256, 2) void k_main_fallback(MainArgs a, const int3
   __shared__ float lds_min[kMainWaves * NB * 32];
   __shared__ int32_t lds_arg[kMainWaves];
   __shared__ __attribute__((aligned(16))) int32_t lds_lab[kMainWaves * NB * 32];
-  __shared__ double lds_bsum[kMainWaves];
 
   const int32_t total = hdr[kHdrFallbackWord];
   MainArgs b = a;
@@ -513,7 +512,7 @@ __global__ __launch_bounds__(256, 2) void k_main_fallback(MainArgs a, const int3
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));  // keep the body's lane addresses inside the loop
     main_bf16_body<DPX, NB, 2, DT, SIL_SQEUCLID, false, kColTile>(
-        b, lb, pre, ring0, ring1, ring2, lds_min, lds_arg, lds_lab, lds_bsum, tid);
+        b, lb, pre, ring0, ring1, ring2, lds_min, lds_arg, lds_lab, tid);
   }
 }
 

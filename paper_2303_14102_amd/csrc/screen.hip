@@ -124,7 +124,7 @@ __global__ __launch_bounds__(1024) void k_fb_sum(const double* __restrict__ part
   __shared__ double sh[1024];
   const int t = threadIdx.x;
   const int64_t total = hdr[kHdrFallbackWord];
-  const int64_t nwg = (total + rows_per_wg - 1) / rows_per_wg;
+  const int64_t nwg = (total + rows_per_wg - 1) / rows_per_wg * kMainWaves;  // per wave
   double v = 0.0;
   for (int64_t i = t; i < nwg; i += 1024) v += part[i];
   sh[t] = v;

@@ -109,7 +109,7 @@ struct WsLayout {
   size_t atab;     // f32[K*DPX]     cluster means (centred) for the a-path
   size_t avec;     // f32[K]         sigma_k^2 (sq. Euclidean) or 1-||mu_k||^2 (cosine)
   size_t ascale;   // f32[K]         N_k/(N_k-1), 0 for singletons
-  size_t bpart;    // f64[max(nblocks, 4 nsblk)] per-workgroup (screen: per-wave) sums of s_i
+  size_t bpart;    // f64[4 max(nblocks, nsblk)] per-wave sums of s_i
   size_t bpart2;   // f64[1024]      first-stage sums of bpart
   size_t save_a;   // f32[N]         a_i            (SIL_FLAG_SAVE_FOR_GRAD)
   size_t save_b;   // f32[N]         b_i
@@ -123,7 +123,7 @@ struct WsLayout {
   size_t c64;      // f64[Kpad]      c_k in binary64
   size_t rtab;     // f32[K*DPX]     fp8: the column scales times mu'_k (the exact score's table)
   size_t fblist;   // i32[N]         sorted positions of the rows left to the fallback
-  size_t fbpart;   // f64[N/128]     per-workgroup sums of s_i of the fallback rows
+  size_t fbpart;   // f64[4 N/128]   per-wave sums of s_i of the fallback rows
   size_t total;
   // shape
   int64_t N;
@@ -189,7 +189,7 @@ struct Problem {
   float* s;
   double* S;
   int64_t nblocks;  // workgroups of the fused kernel for this call
-  int64_t nred = 0; // block partials of S for the reduction (0: nblocks)
+  int64_t nred = 0; // partials of S for the reduction (0: one per wave of nblocks workgroups)
   // K-means step: the nearest mean of every row over all non-empty clusters goes to labels_out,
   // and S receives the sum of the squared distances to it
   int32_t* labels_out = nullptr;
