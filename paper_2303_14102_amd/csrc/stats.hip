@@ -116,6 +116,62 @@ __global__ __launch_bounds__(256) void k_hist(const int32_t* __restrict__ labels
   hist_body(labels, N, K, count, hdr, blockIdx.x, sh_dyn);
 }
 
+// The sort passes for K <= kLdsHistMaxK run kSortThreads per workgroup and read the labels four
+// at a time: one 16-byte load when the labels start at a 16-byte aligned address (uniform over
+// the grid), four 4-byte loads otherwise and at the end of the array.  Positions past N read as
+// -1 and are never counted.
+constexpr int kSortThreads = 1024;
+
+__device__ __forceinline__ int4 load_label4(const int32_t* __restrict__ labels, int64_t N,
+                                            int64_t i, bool vec) {
+  if (vec && i + 3 < N) return *reinterpret_cast<const int4*>(labels + i);
+  int4 v;
+  v.x = i < N ? labels[i] : -1;
+  v.y = i + 1 < N ? labels[i + 1] : -1;
+  v.z = i + 2 < N ? labels[i + 2] : -1;
+  v.w = i + 3 < N ? labels[i + 3] : -1;
+  return v;
+}
+
+// Label histogram, K <= kLdsHistMaxK: CHUNK labels per workgroup, every load issued before the
+// first LDS atomic, then one global atomic per cluster present in the chunk.  Large chunks keep
+// the number of global atomics on each count (one per workgroup) low.
+template <int CHUNK>
+__global__ __launch_bounds__(kSortThreads) void k_hist_lds(const int32_t* __restrict__ labels,
+                                                           int64_t N, int32_t K,
+                                                           int32_t* __restrict__ count,
+                                                           int32_t* __restrict__ hdr) {
+  constexpr int PER = CHUNK / (kSortThreads * 4);
+  extern __shared__ int32_t sh_dyn[];
+  const int t = threadIdx.x;
+  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * CHUNK;
+  const bool vec = (reinterpret_cast<uintptr_t>(labels) & 15) == 0;
+  for (int k = t; k < K; k += kSortThreads) sh_dyn[k] = 0;
+  int4 v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u)
+    v[u] = load_label4(labels, N, c0 + static_cast<int64_t>(u * kSortThreads + t) * 4, vec);
+  __syncthreads();
+  bool bad = false;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int64_t i = c0 + static_cast<int64_t>(u * kSortThreads + t) * 4;
+    const int32_t a[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (i + e >= N) continue;
+      if (a[e] < 0 || a[e] >= K)
+        bad = true;
+      else
+        atomicAdd(&sh_dyn[a[e]], 1);
+    }
+  }
+  if (bad) set_status(hdr, SIL_E_LABEL);
+  __syncthreads();
+  for (int k = t; k < K; k += kSortThreads)
+    if (const int32_t n = sh_dyn[k]) atomicAdd(&count[k], n);
+}
+
 // Exclusive prefix of the cluster sizes, scatter cursors, number of valid points and of
 // non-empty clusters (fewer than min_nonempty is an error).  One workgroup of 1024 threads.
 __device__ __forceinline__ void scan_body(const int32_t* __restrict__ count, int32_t K,
@@ -205,77 +261,103 @@ __device__ __forceinline__ void scatter_body(const int32_t* __restrict__ labels,
   }
 }
 
+// Exclusive prefix of one int per thread over a workgroup of THREADS; wsum holds THREADS/64 ints
+// of LDS; *total receives the workgroup's sum.
+template <int THREADS>
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* wsum, int32_t* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t u = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += u;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int32_t before = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < THREADS / 64; ++w) {
+    const int32_t s = wsum[w];
+    before += w < wv ? s : 0;
+    tot += s;
+  }
+  *total = tot;
+  return before + inc - v;
+}
+
 // The same scatter with the chunk sorted in LDS first (K <= kStageMaxK): the chunk's rows are
 // counted per cluster, the counts scanned into local offsets, each present cluster's block of
 // positions reserved once, the rows placed in LDS by cluster, and the chunk written out in that
 // order.  A cluster's rows then go to consecutive positions from consecutive lanes, so the
-// stores coalesce into whole-line writes instead of one 4-byte request per row.
-constexpr int kStageChunk = 8192;   // labels per workgroup
-constexpr int kStageThreads = 512;
-constexpr int kStageMaxK = 4096;    // LDS: 8 B per staged row + 12 B per cluster
+// stores coalesce into whole-line writes instead of one 4-byte request per row; the larger the
+// chunk, the longer those runs and the fewer the reservations.  A staged row is one word, its
+// cluster in the high half and its offset in the chunk in the low half; LDS: 4 CHUNK + 8 K bytes.
+constexpr int kStageMaxK = 4096;
+constexpr int kStageBig = 32768, kStageSmall = 16384;  // labels per workgroup
+constexpr int stage_lds(int chunk, int K) { return (chunk + 2 * K) * 4; }
+static_assert(stage_lds(kStageBig, kStageMaxK) <= 160 * 1024, "staged scatter exceeds the LDS");
 
-__global__ __launch_bounds__(kStageThreads) void k_scatter_staged(
+template <int CHUNK>
+__global__ __launch_bounds__(kSortThreads) void k_scatter_staged(
     const int32_t* __restrict__ labels, int64_t N, int32_t K, int32_t* __restrict__ cursor,
     int32_t* __restrict__ perm, int32_t* __restrict__ lsorted) {
-  constexpr int PER = kStageChunk / kStageThreads;
-  extern __shared__ int32_t sh_dyn[];
-  int32_t* st_row = sh_dyn;                    // [kStageChunk]
-  int32_t* st_lab = st_row + kStageChunk;      // [kStageChunk]
-  int32_t* cnt = st_lab + kStageChunk;         // [K]: counts, then placement cursors
-  int32_t* lbase = cnt + K;                    // [K]: local offsets
-  int32_t* gbase = lbase + K;                  // [K]: reserved global positions
-  __shared__ int32_t part[kStageThreads];
+  static_assert(CHUNK <= 65536, "row offset in the low half of a staged word");
+  constexpr int PER = CHUNK / (kSortThreads * 4);
+  extern __shared__ uint32_t st_dyn[];
+  uint32_t* staged = st_dyn;                                    // [CHUNK]
+  int32_t* cnt = reinterpret_cast<int32_t*>(st_dyn + CHUNK);    // [K] counts, then cursors
+  int32_t* delta = cnt + K;                                     // [K] global - local position
+  int32_t* wsum = reinterpret_cast<int32_t*>(st_dyn);           // scan scratch, before placement
   const int t = threadIdx.x;
-  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kStageChunk;
-  for (int k = t; k < K; k += kStageThreads) cnt[k] = 0;
-  __syncthreads();
-  int32_t lab[PER];
+  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * CHUNK;
+  const bool vec = (reinterpret_cast<uintptr_t>(labels) & 15) == 0;
+  for (int k = t; k < K; k += kSortThreads) cnt[k] = 0;
+  int4 v[PER];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int64_t i = c0 + u * kStageThreads + t;
-    int32_t k = i < N ? labels[i] : -1;
-    if (k < 0 || k >= K) k = -1;
-    lab[u] = k;
-    if (k >= 0) atomicAdd(&cnt[k], 1);
-  }
-  __syncthreads();
-  // exclusive scan of cnt: contiguous segments per thread, then the segment sums
-  const int seg = (K + kStageThreads - 1) / kStageThreads;
-  const int k0 = min(K, t * seg), k1 = min(K, k0 + seg);
-  int32_t sum = 0;
-  for (int k = k0; k < k1; ++k) sum += cnt[k];
-  part[t] = sum;
-  __syncthreads();
-  for (int d = 1; d < kStageThreads; d <<= 1) {
-    const int32_t v = t >= d ? part[t - d] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int32_t run = part[t] - sum;
-  for (int k = k0; k < k1; ++k) {
-    const int32_t n = cnt[k];
-    lbase[k] = run;
-    if (n) gbase[k] = atomicAdd(&cursor[k], n);
-    cnt[k] = run;  // placement cursor
-    run += n;
-  }
-  const int32_t nvalid = part[kStageThreads - 1];
+  for (int u = 0; u < PER; ++u)
+    v[u] = load_label4(labels, N, c0 + static_cast<int64_t>(u * kSortThreads + t) * 4, vec);
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int32_t k = lab[u];
-    if (k >= 0) {
-      const int32_t slot = atomicAdd(&cnt[k], 1);
-      st_row[slot] = static_cast<int32_t>(c0 + u * kStageThreads + t);
-      st_lab[slot] = k;
+    int32_t* a = reinterpret_cast<int32_t*>(&v[u]);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (a[e] < 0 || a[e] >= K) a[e] = -1;  // past N, or invalid (the histogram reports it)
+      if (a[e] >= 0) atomicAdd(&cnt[a[e]], 1);
     }
   }
   __syncthreads();
-  for (int j = t; j < nvalid; j += kStageThreads) {
-    const int32_t k = st_lab[j];
-    const int32_t pos = gbase[k] + (j - lbase[k]);
-    perm[pos] = st_row[j];
+  const int seg = (K + kSortThreads - 1) / kSortThreads;
+  const int k0 = min(K, t * seg), k1 = min(K, k0 + seg);
+  int32_t sum = 0;
+  for (int k = k0; k < k1; ++k) sum += cnt[k];
+  int32_t nvalid;
+  int32_t run = block_excl_scan<kSortThreads>(sum, wsum, &nvalid);
+  for (int k = k0; k < k1; ++k) {
+    const int32_t n = cnt[k];
+    if (n) delta[k] = atomicAdd(&cursor[k], n) - run;
+    cnt[k] = run;  // placement cursor
+    run += n;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int32_t* a = reinterpret_cast<const int32_t*>(&v[u]);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (a[e] >= 0) {
+        const int32_t slot = atomicAdd(&cnt[a[e]], 1);
+        staged[slot] = (static_cast<uint32_t>(a[e]) << 16) |
+                       static_cast<uint32_t>((u * kSortThreads + t) * 4 + e);
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = t; j < nvalid; j += kSortThreads) {
+    const uint32_t w = staged[j];
+    const int32_t k = static_cast<int32_t>(w >> 16);
+    const int32_t pos = delta[k] + j;
+    perm[pos] = static_cast<int32_t>(c0 + (w & 0xffffu));
     lsorted[pos] = k;
   }
 }
@@ -288,21 +370,44 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ lab
   scatter_body(labels, N, K, cursor, perm, lsorted, blockIdx.x, sh_dyn);
 }
 
-static hipError_t launch_scatter(const Problem& p, const WsPtrs& w, unsigned nchunk, size_t lds,
-                                 hipStream_t st) {
+// zero is done; histogram, scan and scatter
+static hipError_t launch_hist_scatter(const Problem& p, const WsPtrs& w, hipStream_t st) {
+  const unsigned nchunk = static_cast<unsigned>(ceil_div(p.N, kChunk));
+  if (p.K <= kLdsHistMaxK) {
+    const size_t lds = static_cast<size_t>(p.K) * 4;
+    if (p.N >= (int64_t{1} << 24))  // enough 64K-label chunks to fill the chip
+      k_hist_lds<65536><<<static_cast<unsigned>(ceil_div(p.N, 65536)), kSortThreads, lds, st>>>(
+          p.labels, p.N, p.K, w.count, w.hdr);
+    else
+      k_hist_lds<16384><<<static_cast<unsigned>(ceil_div(p.N, 16384)), kSortThreads, lds, st>>>(
+          p.labels, p.N, p.K, w.count, w.hdr);
+  } else {
+    k_hist<<<nchunk, 256, 0, st>>>(p.labels, p.N, p.K, w.count, w.hdr);
+  }
+  k_scan<<<1, 1024, 0, st>>>(w.count, p.K, w.offset, w.cursor, w.hdr, p.min_nonempty);
   if (p.K <= kStageMaxK) {
-    static bool lds_set = false;  // above 64 KB of dynamic LDS the kernel must say so once
+    static bool lds_set = false;  // above 64 KB of dynamic LDS the kernels must say so once
     if (!lds_set) {
-      const hipError_t e = hipFuncSetAttribute(
-          reinterpret_cast<const void*>(&k_scatter_staged), hipFuncAttributeMaxDynamicSharedMemorySize,
-          static_cast<int>((2 * kStageChunk + 3 * kStageMaxK) * 4));
-      if (e != hipSuccess) return e;
+      for (const void* f : {reinterpret_cast<const void*>(&k_scatter_staged<kStageBig>),
+                            reinterpret_cast<const void*>(&k_scatter_staged<kStageSmall>)}) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 stage_lds(kStageBig, kStageMaxK));
+        if (e != hipSuccess) return e;
+      }
       lds_set = true;
     }
-    const size_t sl = (2 * static_cast<size_t>(kStageChunk) + 3 * static_cast<size_t>(p.K)) * 4;
-    k_scatter_staged<<<static_cast<unsigned>(ceil_div(p.N, kStageChunk)), kStageThreads, sl, st>>>(
-        p.labels, p.N, p.K, w.cursor, w.perm, w.lsorted);
+    // the larger chunk where the reservations dominate (many clusters) and it still makes at
+    // least one workgroup per compute unit
+    if (p.K >= 512 && p.N >= int64_t{256} * kStageBig)
+      k_scatter_staged<kStageBig><<<static_cast<unsigned>(ceil_div(p.N, kStageBig)), kSortThreads,
+                                    stage_lds(kStageBig, p.K), st>>>(p.labels, p.N, p.K, w.cursor,
+                                                                     w.perm, w.lsorted);
+    else
+      k_scatter_staged<kStageSmall><<<static_cast<unsigned>(ceil_div(p.N, kStageSmall)),
+                                      kSortThreads, stage_lds(kStageSmall, p.K), st>>>(
+          p.labels, p.N, p.K, w.cursor, w.perm, w.lsorted);
   } else {
+    const size_t lds = p.K <= kLdsHistMaxK ? static_cast<size_t>(p.K) * 4 : 0;
     k_scatter<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.cursor, w.perm, w.lsorted);
   }
   return hipSuccess;
@@ -849,11 +954,19 @@ __device__ __forceinline__ void combine_body(const int32_t* __restrict__ offset,
   if (a == b) return;
   const int64_t s0 = a / kSegLen, s1 = (b - 1) / kSegLen;
   if (s0 == s1) return;
+  // the largest cluster spans many segments: eight loads in flight at a time, each group added
+  // in segment order (the same additions as one at a time)
+  const int first = a != s0 * kSegLen ? 1 : 0;  // the first segment's slot
   double sum = 0.0;
-  for (int64_t s = s0; s <= s1; ++s) {
-    const int slot = (s == s0 && a != s0 * kSegLen) ? 1 : 0;
-    sum += segpart[(s * 2 + slot) * W + col];
+  int64_t s = s0;
+  for (; s + 7 <= s1; s += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = segpart[((s + u) * 2 + (s + u == s0 ? first : 0)) * W + col];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sum += v[u];
   }
+  for (; s <= s1; ++s) sum += segpart[(s * 2 + (s == s0 ? first : 0)) * W + col];
   if (col < D)
     V[static_cast<int64_t>(k) * D + col] = sum;
   else
@@ -891,26 +1004,15 @@ hipError_t launch_sort(const Problem& p, const WsLayout& L, const WsPtrs& w, hip
   const int64_t zblocks = ceil_div(words, 256) < 2048 ? ceil_div(words, 256) : 2048;
   k_fill_zero<<<static_cast<unsigned>(zblocks), 256, 0, st>>>(
       reinterpret_cast<uint32_t*>(w.hdr), words);
-  const unsigned nchunk = static_cast<unsigned>(ceil_div(p.N, kChunk));
-  const size_t lds = p.K <= kLdsHistMaxK ? static_cast<size_t>(p.K) * 4 : 0;
-  k_hist<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.count, w.hdr);
-  k_scan<<<1, 1024, 0, st>>>(w.count, p.K, w.offset, w.cursor, w.hdr, p.min_nonempty);
-  if (const hipError_t e = launch_scatter(p, w, nchunk, lds, st); e != hipSuccess) return e;
+  if (const hipError_t e = launch_hist_scatter(p, w, st); e != hipSuccess) return e;
   return hipGetLastError();
 }
 
 hipError_t launch_stats(const Problem& p, const WsLayout& L, const WsPtrs& w, hipStream_t st) {
-  // zero: header .. segpart are contiguous in the layout; zero [hdr, perm)
-  const int64_t words = static_cast<int64_t>((L.perm - L.hdr) / 4);
-  const int64_t zblocks = ceil_div(words, 256) < 2048 ? ceil_div(words, 256) : 2048;
-  k_fill_zero<<<static_cast<unsigned>(zblocks), 256, 0, st>>>(
-      reinterpret_cast<uint32_t*>(w.hdr), words);
-  const unsigned nchunk = static_cast<unsigned>(ceil_div(p.N, kChunk));
-  const size_t lds = p.K <= kLdsHistMaxK ? static_cast<size_t>(p.K) * 4 : 0;
-  k_hist<<<nchunk, 256, lds, st>>>(p.labels, p.N, p.K, w.count, w.hdr);
-  // the Silhouette needs a neighbouring cluster; a K-means step needs one non-empty cluster
-  k_scan<<<1, 1024, 0, st>>>(w.count, p.K, w.offset, w.cursor, w.hdr, p.min_nonempty);
-  if (const hipError_t e = launch_scatter(p, w, nchunk, lds, st); e != hipSuccess) return e;
+  // zero [hdr, perm) (header .. segpart are contiguous in the layout), then the counting sort;
+  // k_scan checks the non-empty clusters (the Silhouette needs a neighbouring cluster, a K-means
+  // step one non-empty cluster)
+  if (const hipError_t e = launch_sort(p, L, w, st); e != hipSuccess) return e;
   const unsigned nblk = static_cast<unsigned>(ceil_div(L.nseg, 4));
   // 16-byte chunks when a row splits into a power-of-two number of them
   int32_t Gv, G, E;

@@ -150,6 +150,28 @@ def test_stats_scatter_forms(dev, K):
     np.testing.assert_allclose(psi.cpu().numpy(), p_ref, rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("K, offset_labels", [(600, False), (4096, True)])
+def test_stats_large_chunk_sort(dev, K, offset_labels):
+    # at least 256 chunks of 32768 labels and K >= 512: the histogram reads 64K-label chunks and
+    # the scatter stages 32K-label chunks; labels that start 4 bytes past an aligned address take
+    # the 4-byte loads instead of the 16-byte ones
+    from paper_2303_14102_amd import binding as sil
+    n = 256 * 32768 + 12_345
+    b = wl.make_small(n, 4, K, seed=K + 1)
+    lab = b.labels.to(dev)
+    if offset_labels:
+        buf = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        buf[1:] = lab
+        lab = buf[1:]
+        assert lab.data_ptr() % 16 == 4
+    print(f"[stats-large-chunk] N={n} K={K} offset={offset_labels}", flush=True)
+    count, V, psi = sil.cluster_stats(b.X.to(dev), lab, K)
+    c_ref, V_ref, p_ref = oracle.cluster_stats(b.X.numpy(), b.labels.numpy(), K)
+    assert np.array_equal(count.cpu().numpy(), c_ref)
+    np.testing.assert_allclose(V.cpu().numpy(), V_ref, rtol=1e-11, atol=1e-11 * np.abs(V_ref).max())
+    np.testing.assert_allclose(psi.cpu().numpy(), p_ref, rtol=1e-12, atol=0)
+
+
 def test_stats_large_clusters_span_segments(dev):
     # a few clusters of ~1e5 points: every cluster crosses many segment borders
     from paper_2303_14102_amd import binding as sil
