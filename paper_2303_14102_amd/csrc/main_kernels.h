@@ -296,14 +296,18 @@ __device__ __forceinline__ void load_f32w(const float* __restrict__ p, float* ou
 // VEC_ONLY: the caller guarantees D % W == 0 and 16-byte aligned column scales, so only the
 // whole-vector paths are compiled.
 // ROWTERMS = false: only the emitted chunks; nrow and arow are left to the caller.
+// WHOLE: the caller guarantees D == DPX (no chunk past D) and discards every result of a row
+// past N, so those rows (which read row 0's values) are not zeroed.
 template <int DT, int W, int NQ, int NB, int METRIC, bool RAW, bool VEC_ONLY = false,
-          bool ROWTERMS = true, typename Emit>
+          bool ROWTERMS = true, bool WHOLE = false, typename Emit>
 __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B, int lane,
                                          float (&nrow)[NB], float (&arow)[NB], Emit&& emit) {
   constexpr int DPX = 2 * NQ * W;
   constexpr bool CODES = RAW && DT == SIL_FP8_E4M3;  // xv holds unscaled fp8 codes
   const int h = lane >> 5;
-  const bool vec = VEC_ONLY || (a.D % W) == 0;  // wave-uniform
+  const bool vec = VEC_ONLY || WHOLE || (a.D % W) == 0;  // wave-uniform
+  // chunk c0 lies inside the row
+  auto inside = [&](int c0) __attribute__((always_inline)) { return WHOLE || c0 < a.D; };
   // the column scales of chunk c0 (fp8 codes), zero past D: whole-vector loads when every chunk
   // lies inside the row and the scales are 16-byte aligned
   const bool svec =
@@ -311,7 +315,7 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
   const float* colsc = a.col_scale;
   auto scales = [&](int c0, float* sc) __attribute__((always_inline)) {
     if (svec) {
-      if (c0 < a.D) {
+      if (inside(c0)) {
         load_f32w<W>(colsc + c0, sc);
       } else {
 #pragma unroll
@@ -324,8 +328,8 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
   };
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    const bool ok = B.ok[nb];
-    const int64_t row = ok ? B.row[nb] : 0;
+    const bool ok = WHOLE || B.ok[nb];  // zero the row's values unless it lies below N
+    const int64_t row = B.ok[nb] ? B.row[nb] : 0;
     const int32_t o = B.lab[nb];
     const int64_t orow = static_cast<int64_t>(o >= 0 ? o : 0) * DPX;
     float xv[NQ][W];
@@ -334,12 +338,13 @@ __device__ __forceinline__ void prologue(const MainArgs& a, const Blocks<NB>& B,
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int c0 = (2 * q + h) * W;
-        raw[q] = load_raw<DT, W>(a.X, row, a.D, c0 < a.D ? c0 : 0);
+        raw[q] = load_raw<DT, W>(a.X, row, a.D, inside(c0) ? c0 : 0);
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int c0 = (2 * q + h) * W;
-        decode_raw<DT, W, !CODES>(raw[q], a.col_scale, c0 < a.D ? c0 : 0, ok && c0 < a.D, xv[q]);
+        decode_raw<DT, W, !CODES>(raw[q], a.col_scale, inside(c0) ? c0 : 0, ok && inside(c0),
+                                  xv[q]);
       }
     } else {
 #pragma unroll

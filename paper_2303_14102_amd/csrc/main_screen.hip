@@ -153,7 +153,7 @@ __device__ __forceinline__ void top2_scatter16(const float (&m1)[16], const floa
 // scales, centring values and own-cluster means would be loaded together beside the fragments
 // and spill; here the registers of the running minima are free.  Same arithmetic as the
 // prologue's row terms.
-template <int S, int NB>
+template <int S, int NB, bool WHOLE>
 __device__ __forceinline__ void code_row_terms(const MainArgs& a, const Blocks<NB>& B, int lane,
                                                const u32x4_t (&xf)[NB][S], float (&nrow)[NB],
                                                float (&arow)[NB]) {
@@ -161,7 +161,7 @@ __device__ __forceinline__ void code_row_terms(const MainArgs& a, const Blocks<N
   const int h = lane >> 5;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    const bool ok = B.ok[nb];
+    const bool ok = WHOLE || B.ok[nb];  // as in the prologue
     const int32_t o = B.lab[nb];
     const int64_t orow = static_cast<int64_t>(o >= 0 ? o : 0) * DPX;
     float nx = 0.0f, ad = 0.0f;
@@ -169,7 +169,7 @@ __device__ __forceinline__ void code_row_terms(const MainArgs& a, const Blocks<N
     for (int s = 0; s < S; ++s) {
       const int c0 = 16 * s + 8 * h;  // the chunk the prologue handed over as q = s
       float sc[8], mv[8], at[8];
-      if (c0 < a.D) {
+      if (WHOLE || c0 < a.D) {
         load_f32w<8>(a.col_scale + c0, sc);
       } else {
 #pragma unroll
@@ -200,7 +200,9 @@ __device__ __forceinline__ void code_row_terms(const MainArgs& a, const Blocks<N
 // two accumulator sets alternating between the tile's two 32-cluster blocks, TC = 64).
 // DT: X stored bf16 (x itself in the GEMM) or fp8 e4m3 (its codes in the GEMM, the column scales
 // in the table); both are exact in fp16 (fp8 always, bf16 for magnitudes 2^-14 .. 65504).
-template <int DPX, int TC, int NB, int DT>
+// WHOLE: D == DPX, so no chunk lies past D, and the rows past N are not zeroed (the finish
+// discards them).
+template <int DPX, int TC, int NB, int DT, bool WHOLE>
 __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a, ScreenArgs sa) {
   static_assert(NB == 2 || (NB == 1 && TC == 64), "screen configurations");
   static_assert(DT == SIL_BF16 || DT == SIL_FP8_E4M3, "bf16 or fp8 storage");
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
     amax[nb] = 0.0f;
     ncode[nb] = 0.0f;
   }
-  prologue<DT, 8, S, NB, SIL_SQEUCLID, true, CODES, !CODES>(
+  prologue<DT, 8, S, NB, SIL_SQEUCLID, true, CODES, !CODES, WHOLE>(
       a, B, lane, nrow, arow, [&](int nb, int q, const float* v) __attribute__((always_inline)) {
         uint32_t w[4];
 #pragma unroll
@@ -377,7 +379,7 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
       lwin[nb * 32 + out_row(col >> 1, h)] = win;
     }
   }
-  if constexpr (CODES) code_row_terms<S, NB>(a, B, lane, xf, nrow, arow);
+  if constexpr (CODES) code_row_terms<S, NB, WHOLE>(a, B, lane, xf, nrow, arow);
   // lm1 / lm2 / lwin are this wave's own (the LDS completes one wave's operations in order)
   __builtin_amdgcn_wave_barrier();
 
@@ -525,7 +527,12 @@ int screen_rows_per_block() { return kMainWaves * kScreenNB * 32; }
 template <int DPX, int DT>
 static void run_screen(const MainArgs& m, const ScreenArgs& sa, const WsLayout& L,
                        const WsPtrs& w, hipStream_t st) {
-  k_main_screen<DPX, kScreenTile, kScreenNB, DT><<<static_cast<unsigned>(L.nsblk), 256, 0, st>>>(m, sa);
+  if (m.D == DPX)
+    k_main_screen<DPX, kScreenTile, kScreenNB, DT, true>
+        <<<static_cast<unsigned>(L.nsblk), 256, 0, st>>>(m, sa);
+  else
+    k_main_screen<DPX, kScreenTile, kScreenNB, DT, false>
+        <<<static_cast<unsigned>(L.nsblk), 256, 0, st>>>(m, sa);
   MainArgs f = m;
   f.bpart = w.fbpart;
   constexpr int rows = kMainWaves * bf16_nb(DPX, 2, DT) * 32;
