@@ -22,6 +22,8 @@
 //   k_combine   adds the partial slots of clusters that span several segments, in segment order
 // No floating-point atomics are used, so the sums do not depend on the schedule except through
 // the order of rows within a cluster, which the scatter leaves unspecified.
+#include <algorithm>
+
 #include "sil_internal.h"
 
 namespace sil {
@@ -297,19 +299,19 @@ constexpr int kStageBig = 32768, kStageSmall = 16384;  // labels per workgroup
 constexpr int stage_lds(int chunk, int K) { return (chunk + 2 * K) * 4; }
 static_assert(stage_lds(kStageBig, kStageMaxK) <= 160 * 1024, "staged scatter exceeds the LDS");
 
+// chunk `bid` of CHUNK labels, by a workgroup of kSortThreads; st_dyn: stage_lds(CHUNK, K) bytes
 template <int CHUNK>
-__global__ __launch_bounds__(kSortThreads) void k_scatter_staged(
+__device__ __forceinline__ void scatter_staged_body(
     const int32_t* __restrict__ labels, int64_t N, int32_t K, int32_t* __restrict__ cursor,
-    int32_t* __restrict__ perm, int32_t* __restrict__ lsorted) {
+    int32_t* __restrict__ perm, int32_t* __restrict__ lsorted, int64_t bid, uint32_t* st_dyn) {
   static_assert(CHUNK <= 65536, "row offset in the low half of a staged word");
   constexpr int PER = CHUNK / (kSortThreads * 4);
-  extern __shared__ uint32_t st_dyn[];
   uint32_t* staged = st_dyn;                                    // [CHUNK]
   int32_t* cnt = reinterpret_cast<int32_t*>(st_dyn + CHUNK);    // [K] counts, then cursors
   int32_t* delta = cnt + K;                                     // [K] global - local position
   int32_t* wsum = reinterpret_cast<int32_t*>(st_dyn);           // scan scratch, before placement
   const int t = threadIdx.x;
-  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * CHUNK;
+  const int64_t c0 = bid * CHUNK;
   const bool vec = (reinterpret_cast<uintptr_t>(labels) & 15) == 0;
   for (int k = t; k < K; k += kSortThreads) cnt[k] = 0;
   int4 v[PER];
@@ -360,6 +362,14 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter_staged(
     perm[pos] = static_cast<int32_t>(c0 + (w & 0xffffu));
     lsorted[pos] = k;
   }
+}
+
+template <int CHUNK>
+__global__ __launch_bounds__(kSortThreads) void k_scatter_staged(
+    const int32_t* __restrict__ labels, int64_t N, int32_t K, int32_t* __restrict__ cursor,
+    int32_t* __restrict__ perm, int32_t* __restrict__ lsorted) {
+  extern __shared__ uint32_t st_dyn[];
+  scatter_staged_body<CHUNK>(labels, N, K, cursor, perm, lsorted, blockIdx.x, st_dyn);
 }
 
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ labels, int64_t N,
@@ -1086,11 +1096,17 @@ __global__ __launch_bounds__(1024) void kb_scan(BatchDev b) {
   scan_body(q.count, q.K, q.offset, q.cursor, q.hdr, 2);
 }
 
-__global__ __launch_bounds__(256) void kb_scatter(BatchDev b) {
+// kChunk labels per item, as the histogram: staged in LDS for K <= kStageMaxK
+static_assert(kChunk == kStageSmall, "batched scatter items are staged chunks");
+__global__ __launch_bounds__(kSortThreads) void kb_scatter(BatchDev b) {
   extern __shared__ int32_t sh_dyn[];
   int64_t it;
   const BatchProblem& q = batch_item(b, BP_HIST, &it);
-  scatter_body(q.labels, q.N, q.K, q.cursor, q.perm, q.lsorted, it, sh_dyn);
+  if (q.K <= kStageMaxK)
+    scatter_staged_body<kStageSmall>(q.labels, q.N, q.K, q.cursor, q.perm, q.lsorted, it,
+                                     reinterpret_cast<uint32_t*>(sh_dyn));
+  else
+    scatter_body(q.labels, q.N, q.K, q.cursor, q.perm, q.lsorted, it, sh_dyn);
 }
 
 // fp32 storage only (the batched path's storage type)
@@ -1152,7 +1168,20 @@ hipError_t launch_stats_batched(const BatchLaunch& b, hipStream_t st) {
   kb_zero<<<static_cast<unsigned>(b.items[BP_ZERO]), 256, 0, st>>>(b.dev);
   kb_hist<<<static_cast<unsigned>(b.items[BP_HIST]), 256, lds, st>>>(b.dev);
   kb_scan<<<static_cast<unsigned>(b.items[BP_SCAN]), 1024, 0, st>>>(b.dev);
-  kb_scatter<<<static_cast<unsigned>(b.items[BP_HIST]), 256, lds, st>>>(b.dev);
+  {
+    // staged items: stage_lds(kChunk, K) for K <= kStageMaxK; the others K ints
+    const int kst = b.maxK < kStageMaxK ? b.maxK : kStageMaxK;
+    const size_t sl = std::max<size_t>(static_cast<size_t>(stage_lds(kStageSmall, kst)), lds);
+    static bool lds_set = false;  // above 64 KB of dynamic LDS the kernel must say so once
+    if (!lds_set) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_scatter),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               stage_lds(kStageSmall, kStageMaxK));
+      if (e != hipSuccess) return e;
+      lds_set = true;
+    }
+    kb_scatter<<<static_cast<unsigned>(b.items[BP_HIST]), kSortThreads, sl, st>>>(b.dev);
+  }
   kb_seg<<<static_cast<unsigned>(b.items[BP_SEG]), 256, 0, st>>>(b.dev);
   kb_combine<<<static_cast<unsigned>(b.items[BP_COMBINE]), 256, 0, st>>>(b.dev);
   return hipGetLastError();
