@@ -14,9 +14,11 @@
 //      first by more than 2 E (plus the perturbation of the index bits), the smallest names the
 //      row's closest other cluster n exactly, and b_i = ||x'||^2 + c_n - 2 x . mu'_n is formed
 //      for n alone in fp32 (x exact, mu'_n and c_n as the two-product form rounds them).
-//   3. the other rows are appended to a list (one atomic per workgroup reserves its entries), and
+//   3. the other rows are appended to a list (one atomic per wave reserves its entries), and
 //      the two-product kernel runs over that list (fallback), adding its own partial sums of
-//      s_i.  S = (sum over screened rows + sum over fallback rows) / N; the fallback's sums follow
+//      s_i.  When the clusters are large (N >= 512 K, so at most one row in 16 lies in a 32-row
+//      block that straddles a cluster boundary), such blocks are deferred whole to the fallback
+//      and the sweep excludes only a whole block's own cluster, with selects and no branches.  S = (sum over screened rows + sum over fallback rows) / N; the fallback's sums follow
 //      the list's order, which depends on the schedule (as the order of rows within a cluster
 //      does in the statistics pass), so S is reproducible to binary64 rounding, not bitwise.
 // Rows are visited in label-sorted order as in the other fused kernels; 4 waves, two 32-row
@@ -201,8 +203,9 @@ __device__ __forceinline__ void code_row_terms(const MainArgs& a, const Blocks<N
 // DT: X stored bf16 (x itself in the GEMM) or fp8 e4m3 (its codes in the GEMM, the column scales
 // in the table); both are exact in fp16 (fp8 always, bf16 for magnitudes 2^-14 .. 65504).
 // WHOLE: D == DPX, so no chunk lies past D, and the rows past N are not zeroed (the finish
-// discards them).
-template <int DPX, int TC, int NB, int DT, bool WHOLE>
+// discards them).  DEFER: the rows of a block that straddles a cluster boundary go to the
+// fallback (the sweep has no per-row exclusion).
+template <int DPX, int TC, int NB, int DT, bool WHOLE, bool DEFER>
 __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a, ScreenArgs sa) {
   static_assert(NB == 2 || (NB == 1 && TC == 64), "screen configurations");
   static_assert(DT == SIL_BF16 || DT == SIL_FP8_E4M3, "bf16 or fp8 storage");
@@ -307,9 +310,29 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
     }
   };
   const uint32_t keep_in = ~((1u << sa.ibits) - 1u);
+  int town_x[NB];  // DEFER: the 32-cluster block holding the own cluster (-1: none excluded)
+  bool mycol[NB];  // DEFER: the lane's column is the own cluster's
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    town_x[nb] = __builtin_amdgcn_readfirstlane(B.mixed[nb] ? -1 : B.town[nb]);
+    mycol[nb] = col == B.cown[nb];
+  }
   // minima over 32-cluster block blk; cv = c_k of the lane's column (1e30: empty or padding)
-  auto epi = [&](const f32x16_t (&acc)[NB], int blk, float cv) __attribute__((always_inline)) {
+  auto epi = [&](const f32x16_t (&acc)[NB], int blk_in, float cv) __attribute__((always_inline)) {
     const bool empty = cv >= 1.0e29f;
+    if constexpr (DEFER) {
+      const int blk = __builtin_amdgcn_readfirstlane(blk_in);  // wave-uniform
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        // selects, not branches: excluded are empty (or padding) columns and the own cluster
+        const bool out = empty | ((blk == town_x[nb]) & mycol[nb]);
+        const uint32_t keep = out ? 0u : keep_in;
+        const uint32_t tag = out ? kExcluded : static_cast<uint32_t>(blk);
+        screen_min(acc[nb], m1[nb], m2[nb], keep, tag);
+      }
+      return;
+    }
+    const int blk = blk_in;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const bool out = empty || (!B.mixed[nb] && blk == B.town[nb] && col == B.cown[nb]);
@@ -415,7 +438,8 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
     // that the fp16 rounding of their smallest values could reach the two-product form's error
     // in the exact score, are not screened
     const bool fits = CODES || (amax[nb] < 65504.0f && amax[nb] >= tiny_row);
-    const bool unique = valid && !single && fits && n < a.K && (g2 - g1) > 2.0f * E + P;
+    const bool unique = valid && !single && !(DEFER && B.mixed[nb]) && fits && n < a.K &&
+                        (g2 - g1) > 2.0f * E + P;
     const bool flag = valid && !single && !unique;
     // the exact score of cluster n: this lane's half of x . mu'_n (x from its fp16 fragments;
     // fp8: the codes against the column scales times mu'_n)
@@ -527,12 +551,20 @@ int screen_rows_per_block() { return kMainWaves * kScreenNB * 32; }
 template <int DPX, int DT>
 static void run_screen(const MainArgs& m, const ScreenArgs& sa, const WsLayout& L,
                        const WsPtrs& w, hipStream_t st) {
-  if (m.D == DPX)
-    k_main_screen<DPX, kScreenTile, kScreenNB, DT, true>
-        <<<static_cast<unsigned>(L.nsblk), 256, 0, st>>>(m, sa);
-  else
-    k_main_screen<DPX, kScreenTile, kScreenNB, DT, false>
-        <<<static_cast<unsigned>(L.nsblk), 256, 0, st>>>(m, sa);
+  // large clusters: at most 32 (K - 1) rows lie in blocks that straddle a boundary
+  const bool defer = m.N >= int64_t{512} * m.K;
+  const unsigned g = static_cast<unsigned>(L.nsblk);
+  if (m.D == DPX) {
+    if (defer)
+      k_main_screen<DPX, kScreenTile, kScreenNB, DT, true, true><<<g, 256, 0, st>>>(m, sa);
+    else
+      k_main_screen<DPX, kScreenTile, kScreenNB, DT, true, false><<<g, 256, 0, st>>>(m, sa);
+  } else {
+    if (defer)
+      k_main_screen<DPX, kScreenTile, kScreenNB, DT, false, true><<<g, 256, 0, st>>>(m, sa);
+    else
+      k_main_screen<DPX, kScreenTile, kScreenNB, DT, false, false><<<g, 256, 0, st>>>(m, sa);
+  }
   MainArgs f = m;
   f.bpart = w.fbpart;
   constexpr int rows = kMainWaves * bf16_nb(DPX, 2, DT) * 32;

@@ -1,7 +1,8 @@
 """The one-product screen (squared Euclidean, bf16 or fp8 storage, two products): every s_i within
 the two-product form's bound of the FP64 oracle and S within 1e-4, next to the plain two-product
 sweep (SIL_FLAG_NO_SCREEN) on the same inputs.  Cases cover every screen depth class, K from 2
-(one 32-cluster block) to past a thousand, ragged N, singletons and blocks straddling clusters,
+(one 32-cluster block) to past a thousand, ragged N, singletons and blocks straddling clusters
+(excluded per row when clusters are small, deferred to the fallback when N >= 512 K),
 and inputs built to send rows to the two-product fallback: exactly tied clusters (duplicated
 points), and rows with values beyond fp16's range (values below its finest step are screened with
 their rounding in the bound)."""
@@ -73,6 +74,9 @@ CASES = [
     (40_009, 128, 1000, 2, 107),
     (7_777, 128, 2050, 0, 108),  # more clusters than rows in some blocks; K past 2048
     (255, 128, 7, 1, 109),       # fewer rows than one workgroup
+    # N >= 512 K: blocks that straddle a cluster boundary go whole to the fallback
+    (60_013, 128, 100, 1, 131),  # D equal to the depth class
+    (40_009, 100, 64, 2, 132),   # D below it
 ]
 
 
@@ -148,6 +152,7 @@ FP8_CASES = [
     (20_011, 64, 100, 0, 122),
     (30_007, 96, 257, 2, 123),
     (40_009, 128, 1000, 1, 124),
+    (50_021, 128, 80, 1, 133),   # N >= 512 K: straddling blocks go to the fallback
 ]
 
 
