@@ -1,4 +1,4 @@
-// Fused pass 2 with a one-product screen (squared Euclidean, X stored bf16, Eq.11).
+// Fused pass 2 with a one-product screen (squared Euclidean, X stored bf16 or fp8, Eq.11).
 //
 // The two-product kernel spends half its MFMA work on the low half of the cluster means, which
 // only matters for the few clusters that can be a row's closest other cluster.  Here one fp16
@@ -16,11 +16,14 @@
 //      for n alone in fp32 (x exact, mu'_n and c_n as the two-product form rounds them).
 //   3. the other rows are appended to a list (one atomic per wave reserves its entries), and
 //      the two-product kernel runs over that list (fallback), adding its own partial sums of
-//      s_i.  When the clusters are large (N >= 512 K, so at most one row in 16 lies in a 32-row
-//      block that straddles a cluster boundary), such blocks are deferred whole to the fallback
-//      and the sweep excludes only a whole block's own cluster, with selects and no branches.  S = (sum over screened rows + sum over fallback rows) / N; the fallback's sums follow
-//      the list's order, which depends on the schedule (as the order of rows within a cluster
-//      does in the statistics pass), so S is reproducible to binary64 rounding, not bitwise.
+//      s_i.  S = (sum over screened rows + sum over fallback rows) / N; the fallback's sums
+//      follow the list's order, which depends on the schedule (as the order of rows within a
+//      cluster does in the statistics pass), so S is reproducible to binary64 rounding, not
+//      bitwise.
+// When the clusters are large (N >= 512 K, so at most one row in 16 lies in a 32-row block that
+// straddles a cluster boundary), such blocks are deferred whole to the fallback and the sweep
+// excludes only a uniform block's own cluster, with selects and no branches; otherwise the sweep
+// tests every row of a straddling block against its own cluster.
 // Rows are visited in label-sorted order as in the other fused kernels; 4 waves, two 32-row
 // blocks per wave, 64-cluster tiles through the same LDS ring.
 #include "main_kernels.h"

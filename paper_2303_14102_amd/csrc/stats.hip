@@ -138,15 +138,15 @@ __device__ __forceinline__ int4 load_label4(const int32_t* __restrict__ labels, 
 // Label histogram, K <= kLdsHistMaxK: CHUNK labels per workgroup, every load issued before the
 // first LDS atomic, then one global atomic per cluster present in the chunk.  Large chunks keep
 // the number of global atomics on each count (one per workgroup) low.
+// chunk `bid` of CHUNK labels, by a workgroup of kSortThreads; sh_dyn: K ints of LDS
 template <int CHUNK>
-__global__ __launch_bounds__(kSortThreads) void k_hist_lds(const int32_t* __restrict__ labels,
-                                                           int64_t N, int32_t K,
-                                                           int32_t* __restrict__ count,
-                                                           int32_t* __restrict__ hdr) {
+__device__ __forceinline__ void hist_lds_body(const int32_t* __restrict__ labels, int64_t N,
+                                              int32_t K, int32_t* __restrict__ count,
+                                              int32_t* __restrict__ hdr, int64_t bid,
+                                              int32_t* sh_dyn) {
   constexpr int PER = CHUNK / (kSortThreads * 4);
-  extern __shared__ int32_t sh_dyn[];
   const int t = threadIdx.x;
-  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * CHUNK;
+  const int64_t c0 = bid * CHUNK;
   const bool vec = (reinterpret_cast<uintptr_t>(labels) & 15) == 0;
   for (int k = t; k < K; k += kSortThreads) sh_dyn[k] = 0;
   int4 v[PER];
@@ -172,6 +172,15 @@ __global__ __launch_bounds__(kSortThreads) void k_hist_lds(const int32_t* __rest
   __syncthreads();
   for (int k = t; k < K; k += kSortThreads)
     if (const int32_t n = sh_dyn[k]) atomicAdd(&count[k], n);
+}
+
+template <int CHUNK>
+__global__ __launch_bounds__(kSortThreads) void k_hist_lds(const int32_t* __restrict__ labels,
+                                                           int64_t N, int32_t K,
+                                                           int32_t* __restrict__ count,
+                                                           int32_t* __restrict__ hdr) {
+  extern __shared__ int32_t sh_dyn[];
+  hist_lds_body<CHUNK>(labels, N, K, count, hdr, blockIdx.x, sh_dyn);
 }
 
 // Exclusive prefix of the cluster sizes, scatter cursors, number of valid points and of
@@ -1083,11 +1092,12 @@ __global__ __launch_bounds__(256) void kb_zero(BatchDev b) {
   fill_zero_body(reinterpret_cast<uint32_t*>(q.hdr) + w0, n, 0, 1);
 }
 
-__global__ __launch_bounds__(256) void kb_hist(BatchDev b) {
+// kChunk labels per item (K <= kLdsHistMaxK for every batched problem)
+__global__ __launch_bounds__(kSortThreads) void kb_hist(BatchDev b) {
   extern __shared__ int32_t sh_dyn[];
   int64_t it;
   const BatchProblem& q = batch_item(b, BP_HIST, &it);
-  hist_body(q.labels, q.N, q.K, q.count, q.hdr, it, sh_dyn);
+  hist_lds_body<kChunk>(q.labels, q.N, q.K, q.count, q.hdr, it, sh_dyn);
 }
 
 __global__ __launch_bounds__(1024) void kb_scan(BatchDev b) {
@@ -1166,7 +1176,7 @@ void stats_lanes(int32_t D, int32_t dtype, int32_t* Gv, int32_t* G, int32_t* E) 
 hipError_t launch_stats_batched(const BatchLaunch& b, hipStream_t st) {
   const size_t lds = static_cast<size_t>(b.maxK) * 4;
   kb_zero<<<static_cast<unsigned>(b.items[BP_ZERO]), 256, 0, st>>>(b.dev);
-  kb_hist<<<static_cast<unsigned>(b.items[BP_HIST]), 256, lds, st>>>(b.dev);
+  kb_hist<<<static_cast<unsigned>(b.items[BP_HIST]), kSortThreads, lds, st>>>(b.dev);
   kb_scan<<<static_cast<unsigned>(b.items[BP_SCAN]), 1024, 0, st>>>(b.dev);
   {
     // staged items: stage_lds(kChunk, K) for K <= kStageMaxK; the others K ints
