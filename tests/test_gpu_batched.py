@@ -111,6 +111,25 @@ def test_batched_equals_single_problem_calls(dev, mixed):
         np.testing.assert_allclose(batch.s[i].cpu().numpy(), s1.cpu().numpy(), rtol=0, atol=1e-6)
 
 
+def test_batched_offset_labels(dev, mixed):
+    # labels that start 4 bytes past an aligned address: the histogram and the staged scatter take
+    # their 4-byte label loads for those problems, the 16-byte ones for the others
+    from paper_2303_14102_amd import BatchedSilhouette
+    probs, _, expect = mixed
+    shifted = []
+    for i, (X, lab, k, metric) in enumerate(probs):
+        if i % 2 == 0:
+            buf = torch.empty(lab.numel() + 1, dtype=torch.int32, device=dev)
+            buf[1:] = lab
+            lab = buf[1:]
+            assert lab.data_ptr() % 16 == 4
+        shifted.append((X, lab, k, metric))
+    batch = BatchedSilhouette(shifted)
+    batch.run()
+    check_against_oracle(batch, expect, "offset labels")
+    batch.close()
+
+
 def test_autotuner_choice(dev, mixed):
     from paper_2303_14102_amd import BatchedSilhouette
     probs, _, expect = mixed
