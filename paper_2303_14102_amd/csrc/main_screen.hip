@@ -5,9 +5,9 @@
 // product finds that cluster and the epilogue scores it exactly:
 //   1. screen: x in fp16 (exact for bf16 values of magnitude 2^-14 .. 65504, off by less than
 //      2^-24 below that; rows with larger values go to the fallback) times the fp16 table
-//      T16_k ~ -2 mu'_k, plus the constant c_k in three fp16 pieces carried in one more k-step
-//      (so the epilogue has no add); every value is known to within the row's bound E (see
-//      screen.hip).  Each lane keeps, per row, the smallest and second smallest value over its
+//      T16_k ~ -2 mu'_k, accumulated onto the fp32 constant c_k (the first MFMA's accumulator
+//      input, so the epilogue has no add and no k-step carries the constant); every value is
+//      known to within the row's bound E (see screen.hip).  Each lane keeps, per row, the smallest and second smallest value over its
 //      columns (v_med3 + v_min); the 32-cluster block index rides in the low mantissa bits of
 //      the smallest, so that the lane and those bits name the cluster.
 //   2. the finish takes both minima across the 32 lanes of a row.  When the second exceeds the
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
   static_assert(NB == 2 || (NB == 1 && TC == 64), "screen configurations");
   static_assert(DT == SIL_BF16 || DT == SIL_FP8_E4M3, "bf16 or fp8 storage");
   constexpr bool CODES = DT == SIL_FP8_E4M3;
-  constexpr int S = DPX / 16;  // k-steps over the coordinates; step S carries the constant
+  constexpr int S = DPX / 16;  // k-steps over the coordinates
   constexpr int RSS = screen_stride(DPX);
   constexpr int BPT = TC / 32;  // 32-cluster blocks per tile
   using R = Ring<1, RSS * 2, TC == 64 ? 3 : 2, TC>;
@@ -273,8 +273,12 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
     amax[nb] = fmaxf(amax[nb], __shfl_xor(amax[nb], 32, 64));
     ncode[nb] += __shfl_xor(ncode[nb], 32, 64);
   }
-  // A-side of the constant's k-step: fp16 ones against c1, c2, c3 (lanes of half 0)
-  const u32x4_t onef = h == 0 ? u32x4_t{0x3c003c00u, 0x00003c00u, 0u, 0u} : u32x4_t{0u, 0u, 0u, 0u};
+  // the table's scale 2^-f (see screen.hip), for the constant the accumulations start from
+  const float inv_scale = ldexpf(1.0f, -screen_exponent(
+      fmax(__longlong_as_double(static_cast<long long>(
+               reinterpret_cast<const unsigned long long*>(sa.hdr + kHdrScreenWord)[SC_TMAX])),
+           __longlong_as_double(static_cast<long long>(
+               reinterpret_cast<const unsigned long long*>(sa.hdr + kHdrScreenWord)[SC_CMAX])))));
 
   float m1[NB][16], m2[NB][16];
 #pragma unroll
@@ -290,25 +294,26 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
     return __builtin_bit_cast(f16x8_t, *reinterpret_cast<const u32x4_t*>(st + off));
   };
   constexpr int LA = 2;  // k-steps of table fragments read ahead
-  auto gemm = [&](const uint8_t* st, int cb, f32x16_t (&acc)[NB], auto&& after_first_read)
-      __attribute__((always_inline)) {
+  // cv: c_k of the lane's column (fp32, unscaled); every accumulator of a lane lies in that
+  // column, so the block's accumulations of both row blocks start from cv 2^-f
+  auto gemm = [&](const uint8_t* st, int cb, f32x16_t (&acc)[NB], auto&& after_first_read,
+                  float cv) __attribute__((always_inline)) {
     f16x8_t f[LA + 1];
     f[0] = bfrag(st, cb, 0);
     after_first_read();
 #pragma unroll
     for (int s = 1; s < LA; ++s) f[s] = bfrag(st, cb, s);
+    const float c = cv * inv_scale;
+    const f32x16_t cinit = {c, c, c, c, c, c, c, c, c, c, c, c, c, c, c, c};
 #pragma unroll
-    for (int s = 0; s <= S; ++s) {
-      if (s + LA <= S) f[(s + LA) % (LA + 1)] = bfrag(st, cb, s + LA);
+    for (int s = 0; s < S; ++s) {
+      if (s + LA < S) f[(s + LA) % (LA + 1)] = bfrag(st, cb, s + LA);
       __builtin_amdgcn_sched_barrier(0);
       const f16x8_t g = f[s % (LA + 1)];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const f16x8_t x = __builtin_bit_cast(f16x8_t, s < S ? xf[nb][s < S ? s : 0] : onef);
-        if (s == 0)
-          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x, g, f32x16_t{}, 0, 0, 0);
-        else
-          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x, g, acc[nb], 0, 0, 0);
+        const f16x8_t x = __builtin_bit_cast(f16x8_t, xf[nb][s]);
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x, g, s == 0 ? cinit : acc[nb], 0, 0, 0);
       }
     }
   };
@@ -361,12 +366,12 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
 #pragma unroll
       for (int cb = 0; cb < BPT; ++cb)
         cv[cb] = BPT * t + cb < nblk ? a.ctab[TC * t + 32 * cb + col] : 0.0f;
-      gemm(st, 0, acc, prefetch);
+      gemm(st, 0, acc, prefetch, cv[0]);
       epi(acc, BPT * t, cv[0]);
 #pragma unroll
       for (int cb = 1; cb < BPT; ++cb) {
         if (BPT * t + cb < nblk) {
-          gemm(st, cb, acc, [] {});
+          gemm(st, cb, acc, [] {}, cv[cb]);
           epi(acc, BPT * t + cb, cv[cb]);
         }
       }
@@ -381,9 +386,9 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
              [&](int t, const uint8_t* st, auto&& prefetch) __attribute__((always_inline)) {
       const float c0 = a.ctab[64 * t + col];
       const float c1 = 2 * t + 1 < nblk ? a.ctab[64 * t + 32 + col] : 0.0f;
-      gemm(st, 0, acc0, prefetch);
+      gemm(st, 0, acc0, prefetch, c0);
       if (t > 0) epi(acc1, 2 * t - 1, c1p);
-      if (t + 1 < ntiles || last_b1) gemm(st, 1, acc1, [] {});
+      if (t + 1 < ntiles || last_b1) gemm(st, 1, acc1, [] {}, c1);
       epi(acc0, 2 * t, c0);
       c1p = c1;
     });
@@ -409,11 +414,6 @@ __global__ __launch_bounds__(256, NB == 2 ? 2 : 3) void k_main_screen(MainArgs a
   // lm1 / lm2 / lwin are this wave's own (the LDS completes one wave's operations in order)
   __builtin_amdgcn_wave_barrier();
 
-  const float inv_scale = ldexpf(1.0f, -screen_exponent(
-      fmax(__longlong_as_double(static_cast<long long>(
-               reinterpret_cast<const unsigned long long*>(sa.hdr + kHdrScreenWord)[SC_TMAX])),
-           __longlong_as_double(static_cast<long long>(
-               reinterpret_cast<const unsigned long long*>(sa.hdr + kHdrScreenWord)[SC_CMAX])))));
   const float L1 = slot_f(sa.hdr, SC_L1), L2 = slot_f(sa.hdr, SC_L2);
   const float L3 = slot_f(sa.hdr, SC_L3), EC = slot_f(sa.hdr, SC_EC);
   const float MN = slot_f(sa.hdr, SC_MNORM);

@@ -3,15 +3,17 @@
 // two-product kernel, and the sum of their s_i.
 //
 // The screen value of row x and cluster k is
-//     v~_k = x16 . T16_k + (c1 + c2 + c3)_k        (fp16 products, fp32 accumulation, all scaled
-//                                                   by the table's power of two 2^-f)
+//     v~_k = fl32(c_k) + x16 . T16_k          (fp16 products accumulated in fp32 onto the fp32
+//                                              constant, all scaled by the table's power of two
+//                                              2^-f, which scales fl32(c_k) exactly)
 // against the exact v_k = x . T_k + c_k, with T_k = -2 mu'_k and c_k the binary64 table values
 // of the two-product form.  x is exact in fp16 (rows where it is not go to the fallback), so
 //     |v~_k - v_k| <= ||x|| L1 + EC + (DPX + 16) 2^-24 (||x|| L2 + L3)
-// with L1 = max_k ||T16_k - T_k||, L2 = max_k ||T16_k||, L3 = max_k (|c1| + |c2| + |c3|),
-// EC = max_k |c1 + c2 + c3 - c_k| (all unscaled): Cauchy-Schwarz for the table's rounding, and
-// the bound of a sum of DPX + 16 exact products accumulated in fp32 in any order (taken with
-// twice the unit roundoff, so that it holds whatever rounding the accumulation uses).
+// with L1 = max_k ||T16_k - T_k||, L2 = max_k ||T16_k||, L3 = max_k |fl32(c_k)|,
+// EC = max_k |fl32(c_k) - c_k| (all unscaled): Cauchy-Schwarz for the table's rounding, and the
+// bound of a sum of DPX exact products and the constant accumulated in fp32 in any order (taken
+// with DPX + 16 terms and twice the unit roundoff, so that it holds whatever rounding the
+// accumulation uses).
 #include "sil_internal.h"
 
 namespace sil {
@@ -33,7 +35,8 @@ __device__ __forceinline__ double read_slot(const int32_t* hdr, int slot) {
 }
 
 // Four clusters per wave, sixteen per workgroup.  Table row k (scaled by 2^-f, rounded to nearest
-// fp16): [T_k (D entries), 0 ... (to DPX), c1, c2, c3, 0 ... (to DPX + 24)], c1 + c2 + c3 ~ c_k.
+// fp16): [T_k (D entries), 0 ... (to DPX + 8)]; the constant is the fp32 c_k of the two-product
+// tables (ctab), which the screen kernel scales and starts each accumulation from.
 // The maxima over the workgroup's clusters raise the header slots (one atomic each); workgroup 0
 // also stores the norm of the centring vector.  Empty and padding clusters get a zero row (the
 // screen kernel excludes their columns).
@@ -58,7 +61,6 @@ __global__ __launch_bounds__(256) void k_screen_table(
     const double dn = static_cast<double>(n);
     double err2 = 0.0, nrm2 = 0.0;
     for (int l = lane; l < RSS; l += 64) {
-      if (l >= DPX && l < DPX + 3) continue;  // the constant's pieces, written below
       double g = 0.0;
       if (n > 0 && l < D) {  // the same binary64 operations as the two-product table
         const double mu = V[static_cast<int64_t>(k) * D + l] / dn;
@@ -75,27 +77,14 @@ __global__ __launch_bounds__(256) void k_screen_table(
     }
     err2 = wave_sum64(err2);
     nrm2 = wave_sum64(nrm2);
-    if (lane == 0) {
-      _Float16 p1 = 0, p2 = 0, p3 = 0;
-      if (n > 0) {
-        const double c = c64[k] * sc;
-        p1 = static_cast<_Float16>(static_cast<float>(c));
-        const double r1 = c - static_cast<double>(p1);
-        p2 = static_cast<_Float16>(static_cast<float>(r1));
-        const double r2 = r1 - static_cast<double>(p2);
-        p3 = static_cast<_Float16>(static_cast<float>(r2));
-        const double sum =
-            static_cast<double>(p1) + static_cast<double>(p2) + static_cast<double>(p3);
-        // binary64 rounding of these few operations is far below the margins the kernel adds
-        l1 = fmax(l1, sqrt(err2));
-        l2 = fmax(l2, sqrt(nrm2));
-        l3 = fmax(l3, (fabs(static_cast<double>(p1)) + fabs(static_cast<double>(p2)) +
-                       fabs(static_cast<double>(p3))) * usc);
-        ec = fmax(ec, fabs(sum - c) * usc);
-      }
-      row[DPX] = p1;
-      row[DPX + 1] = p2;
-      row[DPX + 2] = p3;
+    if (lane == 0 && n > 0) {
+      // the constant as the kernel takes it: the fp32 table value (its scaling by 2^-f is exact)
+      const double c32 = static_cast<double>(static_cast<float>(c64[k]));
+      // binary64 rounding of these few operations is far below the margins the kernel adds
+      l1 = fmax(l1, sqrt(err2));
+      l2 = fmax(l2, sqrt(nrm2));
+      l3 = fmax(l3, fabs(c32));
+      ec = fmax(ec, fabs(c32 - c64[k]));
     }
   }
   if (lane == 0) {

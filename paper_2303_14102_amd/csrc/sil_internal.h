@@ -54,9 +54,9 @@ inline void with_depth(DepthList<Ds...>, int DPX, F&& f) {
 // One-product screen (squared Euclidean, bf16 storage, two-product request): an fp16 MFMA sweep
 // finds each row's nearest other cluster, which the epilogue then scores exactly; rows whose two
 // best screened values are too close for the screen's error bound go to the two-product kernel.
-// Its table row: the fp16 table entries (DPX), one k-step holding the per-cluster constant as
-// three fp16 pieces (16), and one 16-byte chunk of padding (the odd chunk count of table_stride).
-constexpr int screen_stride(int DPX) { return DPX + 24; }
+// Its table row: the fp16 table entries (DPX) and one 16-byte chunk of padding (the odd chunk
+// count of table_stride); the per-cluster constant enters as the accumulators' initial value.
+constexpr int screen_stride(int DPX) { return DPX + 8; }
 constexpr int kScreenMaxDPX = 128;
 // Header slots of the screen: 64-bit words from int32 word 16, each the bit pattern of a
 // non-negative double raised with integer atomicMax (for such patterns the largest pattern is
@@ -66,8 +66,8 @@ enum ScreenSlot {
   SC_CMAX,      // max |c_k|
   SC_L1,        // max_k || fp16 table row - exact table row ||
   SC_L2,        // max_k || fp16 table row ||
-  SC_L3,        // max_k (|c1| + |c2| + |c3|), the constant's pieces
-  SC_EC,        // max_k |c1 + c2 + c3 - c_k|
+  SC_L3,        // max_k |fl32(c_k)|, the constant the accumulation starts from
+  SC_EC,        // max_k |fl32(c_k) - c_k|
   SC_MNORM,     // || centring vector (fp32, as the kernels use it) ||
   SC_COUNT
 };
