@@ -749,14 +749,14 @@ def main():
             "issued_frac counts every split product")
     if screened:
         fb = sil.fallback_rows(ws)
-        # the screen: one fp16 product over D coordinates plus the constant's k-step (16 deep) for
-        # every row; the two-product kernel over the listed rows
+        # the screen: one fp16 product over D coordinates for every row (the constant is the
+        # accumulators' initial value); the two-product kernel over the listed rows
         depth = -(-spec.d // 16) * 16
-        issued = 2.0 * spec.n * spec.k * (depth + 16) + 2.0 * 2.0 * fb * spec.k * depth
+        issued = 2.0 * spec.n * spec.k * depth + 2.0 * 2.0 * fb * spec.k * depth
         kname = "k_main_screen"
         note = ("achieved = 2*N*D*K useful flops / mean duration of the fused phase (the fp16 screen "
                 "kernel, then the two-product kernel over the rows it leaves); issued_frac counts the "
-                "screen's constant k-step and the fallback's two products")
+                "screen's padded depth and the fallback's two products")
         out["screen"] = {"fallback_rows": fb, "fallback_frac": fb / spec.n,
                          "kernels": ["k_main_screen", "k_main_fallback", "k_fb_sum"]}
     out["roofline"] = {"bound": "mfma", "achieved": useful / t_main / 1e12, "peak": peak / 1e12,
