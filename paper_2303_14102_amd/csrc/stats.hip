@@ -12,9 +12,10 @@
 // The paper accumulates Y and Psi together in one pass with per-worker partial sums that one
 // node then adds up (footnotes to Eq.6 and Eq.9).  On the GPU the "workers" are waves, and the
 // per-cluster sums are made contention-free by a counting sort of the row ids by label:
-//   k_hist      label histogram (LDS-privatised, validates labels)
+//   k_hist_lds  label histogram (LDS-privatised, validates labels; k_hist above 16384 clusters)
 //   k_scan      exclusive prefix of N_k -> start of every cluster in sorted order
-//   k_scatter   row ids scattered to their cluster's range (LDS-reserved blocks)
+//   k_scatter_staged  row ids scattered to their cluster's range, each chunk counting-sorted in
+//               LDS first (k_scatter, one reservation per row, above 4096 clusters)
 //   k_segreduce each wave owns kSegLen consecutive sorted positions and accumulates the rows it
 //               gathers in FP64 registers; a run of one cluster that lies wholly inside the
 //               segment is stored directly, a run cut by a segment border goes to one of two
